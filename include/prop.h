@@ -1,0 +1,157 @@
+/*
+ * prop.h -- C ABI of the MI355X (gfx950) domain-propagation library.
+ *
+ * The library propagates variable bounds through linear constraints
+ *
+ *     lhs_i <= sum_j A_ij x_j <= rhs_i      (i = 0..m-1)
+ *     lb_j  <= x_j <= ub_j                  (j = 0..n-1, some x_j integer)
+ *
+ * in synchronous rounds, as in Sofranac, Gleixner and Pokutta,
+ * "Accelerating Domain Propagation: an Efficient GPU-Parallel Algorithm
+ * over Sparse Matrices" (arXiv 2009.07785):
+ *
+ *   - every row's minimum and maximum activity (Sec. 1.1, Definition 1),
+ *     split into a finite part and a count of infinite contributions
+ *     (Sec. 3.4), from the bounds as they stood at the start of the round;
+ *   - one lower and one upper bound candidate per nonzero (Sec. 1.1, Step 3,
+ *     eqs. bound_candidates_pos / bound_candidates_neg), rounded inward for
+ *     integer variables;
+ *   - candidates that improve on the start-of-round bound are applied with
+ *     atomic max (lower) / min (upper) (Sec. 3.5, Algorithm 3);
+ *   - rounds repeat until no bound changes, a domain becomes empty or the
+ *     round limit is reached (Algorithm 2).
+ *
+ * Numerical contract (the same as the test oracle's, stated in full in the
+ * repository's design notes):
+ *   - activities are the exact sum of the products, rounded once to the
+ *     nearest double; every other operation is one IEEE double operation in
+ *     the order of the paper's formulas: (beta - activity) / a + bound;
+ *   - integer candidates: lower = ceil(c - eps_int), upper =
+ *     floor(c + eps_int);
+ *   - a candidate is applied when it beats the start-of-round bound b:
+ *     b infinite: any finite candidate; integer: strictly; continuous: by
+ *     more than cont_rel_tol * max(1, |b|); candidates beyond 2^200 in
+ *     magnitude are dropped;
+ *   - a domain is empty when l > u (integer) or
+ *     l - u > feas_tol * max(1, |l|, |u|) (continuous).
+ *
+ * Input domain (checked; violations return PROP_EINVAL): coefficients are
+ * finite and either 0 (skipped) or of magnitude in [2^-64, 2^64]; column
+ * indices are in [0, n) and distinct within a row; row_ptr starts at 0 and
+ * never decreases; lhs is finite or -inf, rhs finite or +inf; lb finite or
+ * -inf, ub finite or +inf; finite values have magnitude <= 2^200; no NaN;
+ * vartype is 0 (continuous) or 1 (integer; a binary is an integer in [0,1]).
+ *
+ * Threading: a prop_problem may be used by one thread at a time.  Calls on
+ * different problems may run concurrently.
+ */
+#ifndef PROP_H
+#define PROP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Outcome of a run (prop_result.status). */
+#define PROP_CONVERGED 0  /* a round changed nothing */
+#define PROP_INFEASIBLE 1 /* some domain became empty (bounds then unspecified) */
+#define PROP_MAX_ROUNDS 2 /* the round limit was reached with changes pending */
+
+/* Return codes: 0 on success, negative on error; the library never aborts. */
+#define PROP_OK 0
+#define PROP_EINVAL (-1)  /* invalid argument or input outside the domain above */
+#define PROP_ENOMEM (-2)  /* device or host allocation failed */
+#define PROP_EDEVICE (-3) /* HIP runtime error, no usable GPU, or device timeout */
+
+/* vartype values */
+#define PROP_CONTINUOUS 0
+#define PROP_INTEGER 1
+
+/* Round-loop drivers (prop_set_loop).  All give identical results. */
+#define PROP_LOOP_PERSISTENT 0 /* one cooperative launch, grid barriers between phases */
+#define PROP_LOOP_STREAM 1     /* per-round kernels queued without host sync; device flag */
+#define PROP_LOOP_HOST 2       /* per-round kernels, host reads the flag every round */
+
+typedef struct prop_problem prop_problem; /* opaque */
+
+/* Constraint matrix in CSR form, host memory.  row_ptr has m+1 entries. */
+typedef struct {
+  int32_t m;
+  int32_t n;
+  int64_t nnz;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const double* vals;
+} prop_csr;
+
+/* Tolerances; a NULL pointer means 1e-6 for each. */
+typedef struct {
+  double eps_int;      /* integer rounding slack, >= 0 and < 0.5 */
+  double cont_rel_tol; /* relative gain a continuous bound needs, >= 0 */
+  double feas_tol;     /* relative crossing a continuous domain may show, >= 0 */
+} prop_params;
+
+typedef struct {
+  int32_t status; /* PROP_CONVERGED / PROP_INFEASIBLE / PROP_MAX_ROUNDS */
+  int32_t rounds; /* rounds executed, counting the last change-free one */
+} prop_result;
+
+/* Size and layout figures of a created problem. */
+typedef struct {
+  int32_t m, n;
+  int64_t nnz;             /* nonzero coefficients (explicit zeros dropped) */
+  int64_t nnz_stored;      /* stored entries including layout padding */
+  int32_t n_chunks;        /* wave-sized tiles of rows with <= 1024 entries */
+  int32_t n_long_rows;     /* rows with more than 1024 entries */
+  int32_t n_segments;      /* 1024-entry segments of those rows */
+  int32_t grid_blocks;     /* blocks of the persistent launch */
+  int64_t device_bytes;    /* device memory held by the problem */
+  int64_t alg_bytes_round; /* algorithmic bytes per round: 12 nnz + 20 m + 33 n + 4 */
+} prop_info;
+
+/* Builds a problem on the current HIP device.  The inputs are copied; the
+ * caller keeps ownership of every array.  Rows are reordered and variables
+ * relabelled internally; results come back in the caller's order.
+ * Rows with lhs > rhs, and empty rows whose sides exclude 0, make every
+ * later run report PROP_INFEASIBLE after 0 rounds.  `params` may be NULL.
+ * Returns PROP_OK and stores the handle in *out, or an error code. */
+int prop_create(const prop_csr* A, const double* lhs, const double* rhs, const uint8_t* vartype,
+                const prop_params* params, prop_problem** out);
+
+/* Propagates host arrays lb[n], ub[n] in place (caller-owned, overwritten
+ * with the result; unspecified when the status is PROP_INFEASIBLE).
+ * Copies in, runs, copies out and synchronises.  max_rounds >= 0. */
+int prop_run(prop_problem* p, double* lb, double* ub, int32_t max_rounds, prop_result* out);
+
+/* Same on device arrays d_lb[n], d_ub[n] (HIP device memory, caller-owned,
+ * updated in place), queued on `stream` (a hipStream_t; NULL = the null
+ * stream).  Allocates nothing; synchronises the stream once at the end to
+ * fill *out (host memory).  Bound validation happens on the device; an
+ * invalid bound makes the call return PROP_EINVAL. */
+int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rounds,
+                    void* stream, prop_result* out);
+
+/* Selects the round-loop driver (PROP_LOOP_*) for later runs. */
+int prop_set_loop(prop_problem* p, int32_t mode);
+
+/* Fills *out with the problem's sizes. */
+int prop_get_info(const prop_problem* p, prop_info* out);
+
+/* Device time of the last run's round loop in milliseconds (HIP events on
+ * the launch stream around the loop kernels, pack/unpack excluded), and the
+ * same with the bound pack and unpack kernels included. */
+int prop_last_timing(const prop_problem* p, double* loop_ms, double* total_ms);
+
+/* Releases the problem (NULL is allowed). */
+void prop_destroy(prop_problem* p);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* prop_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PROP_H */

@@ -1,0 +1,229 @@
+"""ctypes binding of libprop.so (the C ABI in include/prop.h).
+
+Argument marshalling only: every step of propagation runs in the HIP
+kernels behind the C ABI.  PyTorch is used, when the caller wants it, only
+to hand over device memory and a stream.  There is no fallback: if the
+library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libprop.so")
+
+CONVERGED, INFEASIBLE, MAX_ROUNDS = 0, 1, 2
+STATUS_NAMES = {CONVERGED: "CONVERGED", INFEASIBLE: "INFEASIBLE", MAX_ROUNDS: "MAX_ROUNDS"}
+OK, EINVAL, ENOMEM, EDEVICE = 0, -1, -2, -3
+LOOP_PERSISTENT, LOOP_STREAM, LOOP_HOST = 0, 1, 2
+LOOP_NAMES = {"persistent": LOOP_PERSISTENT, "stream": LOOP_STREAM, "host": LOOP_HOST}
+
+# every function the header declares
+EXPORTED = ("prop_create", "prop_run", "prop_run_device", "prop_set_loop", "prop_get_info",
+            "prop_last_timing", "prop_destroy", "prop_last_error")
+
+
+class PropError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"prop error {code}: {msg}")
+        self.code = code
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("vals", ctypes.c_void_p)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("eps_int", ctypes.c_double), ("cont_rel_tol", ctypes.c_double),
+                ("feas_tol", ctypes.c_double)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("rounds", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("nnz_stored", ctypes.c_int64), ("n_chunks", ctypes.c_int32),
+                ("n_long_rows", ctypes.c_int32), ("n_segments", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+                ("alg_bytes_round", ctypes.c_int64)]
+
+
+def _load():
+    # PyTorch ships its own HIP runtime (same soname as the system one).  Load
+    # it first so that libprop binds to that copy: two HIP runtimes in one
+    # process cannot both open the GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32 = ctypes.c_void_p, ctypes.c_int32
+    lib.prop_create.argtypes = [ctypes.POINTER(_Csr), P, P, P, ctypes.POINTER(_Params),
+                                ctypes.POINTER(P)]
+    lib.prop_create.restype = ctypes.c_int
+    lib.prop_run.argtypes = [P, P, P, i32, ctypes.POINTER(_Result)]
+    lib.prop_run.restype = ctypes.c_int
+    lib.prop_run_device.argtypes = [P, P, P, i32, P, ctypes.POINTER(_Result)]
+    lib.prop_run_device.restype = ctypes.c_int
+    lib.prop_set_loop.argtypes = [P, i32]
+    lib.prop_set_loop.restype = ctypes.c_int
+    lib.prop_get_info.argtypes = [P, ctypes.POINTER(_Info)]
+    lib.prop_get_info.restype = ctypes.c_int
+    lib.prop_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.prop_last_timing.restype = ctypes.c_int
+    lib.prop_destroy.argtypes = [P]
+    lib.prop_destroy.restype = None
+    lib.prop_last_error.argtypes = []
+    lib.prop_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.prop_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise PropError(rc, last_error())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class RunResult:
+    status: int
+    rounds: int
+
+    @property
+    def status_name(self) -> str:
+        return STATUS_NAMES[self.status]
+
+
+class Problem:
+    """A constraint system resident on the current HIP device."""
+
+    def __init__(self, m, n, row_ptr, col_idx, vals, lhs, rhs, vartype, eps_int=1e-6,
+                 cont_rel_tol=1e-6, feas_tol=1e-6):
+        self._h = None
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        va = np.ascontiguousarray(vals, dtype=np.float64)
+        lh = np.ascontiguousarray(lhs, dtype=np.float64)
+        rh = np.ascontiguousarray(rhs, dtype=np.float64)
+        vt = np.ascontiguousarray(vartype, dtype=np.uint8)
+        if rp.shape != (m + 1,) or lh.shape != (m,) or rh.shape != (m,) or vt.shape != (n,):
+            raise ValueError("array shapes do not match m / n")
+        if ci.shape != va.shape or ci.shape[0] != int(rp[-1]):
+            raise ValueError("col_idx / vals do not match row_ptr")
+        csr = _Csr(int(m), int(n), int(rp[-1]), _ptr(rp).value, _ptr(ci).value, _ptr(va).value)
+        prm = _Params(float(eps_int), float(cont_rel_tol), float(feas_tol))
+        h = ctypes.c_void_p()
+        _check(lib.prop_create(ctypes.byref(csr), _ptr(lh), _ptr(rh), _ptr(vt), ctypes.byref(prm),
+                               ctypes.byref(h)))
+        self._h = h
+        self.m, self.n = int(m), int(n)
+
+    @classmethod
+    def from_instance(cls, inst, **params):
+        return cls(inst.m, inst.n, inst.row_ptr, inst.col_idx, inst.vals, inst.lhs, inst.rhs,
+                   inst.vartype, **params)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib.prop_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- runs ---------------------------------------------------------------
+    def run(self, lb, ub, max_rounds: int = 100):
+        """Host arrays in, (RunResult, lb, ub) out; the inputs are not modified."""
+        lb = np.array(lb, dtype=np.float64, copy=True)
+        ub = np.array(ub, dtype=np.float64, copy=True)
+        if lb.shape != (self.n,) or ub.shape != (self.n,):
+            raise ValueError("bounds must have shape (n,)")
+        res = _Result()
+        _check(lib.prop_run(self._h, _ptr(lb), _ptr(ub), int(max_rounds), ctypes.byref(res)))
+        return RunResult(res.status, res.rounds), lb, ub
+
+    def run_device(self, d_lb, d_ub, max_rounds: int = 100, stream=None) -> RunResult:
+        """Device tensors (float64, contiguous, length n) updated in place.
+        `stream` is a torch.cuda.Stream or a raw hipStream_t integer; default:
+        torch's current stream."""
+        for t in (d_lb, d_ub):
+            if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8
+                    and t.is_contiguous() and t.numel() == self.n):
+                raise ValueError("bounds must be contiguous float64 device tensors of length n")
+        if stream is None:
+            import torch
+
+            stream = torch.cuda.current_stream(d_lb.device)
+        raw = getattr(stream, "cuda_stream", stream)
+        res = _Result()
+        _check(lib.prop_run_device(self._h, ctypes.c_void_p(d_lb.data_ptr()),
+                                   ctypes.c_void_p(d_ub.data_ptr()), int(max_rounds),
+                                   ctypes.c_void_p(int(raw) if raw else 0), ctypes.byref(res)))
+        return RunResult(res.status, res.rounds)
+
+    def set_loop(self, mode):
+        if isinstance(mode, str):
+            mode = LOOP_NAMES[mode]
+        _check(lib.prop_set_loop(self._h, int(mode)))
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(lib.prop_get_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def last_timing(self):
+        """(loop_ms, total_ms) of the last run, from HIP events on its stream."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib.prop_last_timing(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+
+def create_raw(csr_args, lhs, rhs, vartype, params=None):
+    """Calls prop_create with explicit arrays; returns (rc, handle).  For tests
+    of the validation path, which runs before any device call."""
+    m, n, rp, ci, va = csr_args
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    ci = np.ascontiguousarray(ci, dtype=np.int32)
+    va = np.ascontiguousarray(va, dtype=np.float64)
+    lh = np.ascontiguousarray(lhs, dtype=np.float64)
+    rh = np.ascontiguousarray(rhs, dtype=np.float64)
+    vt = np.ascontiguousarray(vartype, dtype=np.uint8)
+    csr = _Csr(int(m), int(n), int(rp[-1]) if rp.size else 0, _ptr(rp).value, _ptr(ci).value,
+               _ptr(va).value)
+    prm = _Params(*(params or (1e-6, 1e-6, 1e-6)))
+    h = ctypes.c_void_p()
+    rc = lib.prop_create(ctypes.byref(csr), _ptr(lh), _ptr(rh), _ptr(vt), ctypes.byref(prm),
+                         ctypes.byref(h))
+    return rc, h

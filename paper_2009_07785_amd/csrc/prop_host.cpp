@@ -1,0 +1,544 @@
+// prop_host.cpp -- host runtime of the propagation library: input checks,
+// the device layout (row chunks, long-row segments, variable relabelling),
+// device memory, and the round-loop drivers behind the C ABI in prop.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/prop.h"
+#include "prop_launch.h"
+#include "prop_layout.h"
+
+using namespace prop;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(e_ == hipErrorOutOfMemory ? PROP_ENOMEM : PROP_EDEVICE, "%s: %s", #expr, \
+                  hipGetErrorString(e_));                                                \
+  } while (0)
+
+const double kHugeValue = std::ldexp(1.0, 200);
+const double kCoefMin = std::ldexp(1.0, -64);
+const double kCoefMax = std::ldexp(1.0, 64);
+
+bool side_ok(double x, bool is_lhs) {
+  if (std::isnan(x)) return false;
+  if (std::isinf(x)) return is_lhs ? x < 0 : x > 0;
+  return std::fabs(x) <= kHugeValue;
+}
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct prop_problem {
+  int device = 0;
+  int32_t m = 0, n = 0;
+  int64_t nnz = 0, nnz_stored = 0;
+  int32_t n_long_rows = 0;
+  int grid = 0;
+  int loop_mode = PROP_LOOP_PERSISTENT;
+  bool instance_infeasible = false;
+  prop_params params{1e-6, 1e-6, 1e-6};
+  Problem P{};
+  // device allocations
+  std::vector<void*> allocs;
+  int64_t device_bytes = 0;
+  double* d_stage_lb = nullptr;  // staging for prop_run (host arrays)
+  double* d_stage_ub = nullptr;
+  Ctrl* h_ctrl = nullptr;        // pinned host copy of the control block
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  float last_loop_ms = 0.f, last_total_ms = 0.f;
+};
+
+namespace {
+
+template <typename T>
+int dev_alloc(prop_problem* p, T** out, size_t count) {
+  size_t bytes = sizeof(T) * (count > 0 ? count : 1);
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, bytes);
+  if (e != hipSuccess)
+    return fail(PROP_ENOMEM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+  p->allocs.push_back(ptr);
+  p->device_bytes += (int64_t)bytes;
+  *out = static_cast<T*>(ptr);
+  return PROP_OK;
+}
+
+template <typename T>
+int dev_upload(prop_problem* p, T** out, const std::vector<T>& host) {
+  int rc = dev_alloc(p, out, host.size());
+  if (rc) return rc;
+  if (!host.empty()) HIP_TRY(hipMemcpy(*out, host.data(), sizeof(T) * host.size(), hipMemcpyHostToDevice));
+  return PROP_OK;
+}
+
+void release(prop_problem* p) {
+  if (!p) return;
+  for (void* a : p->allocs) hipFree(a);
+  p->allocs.clear();
+  if (p->h_ctrl) hipHostFree(p->h_ctrl);
+  for (auto& e : p->ev)
+    if (e) hipEventDestroy(e);
+  delete p;
+}
+
+int validate(const prop_csr* A, const double* lhs, const double* rhs, const uint8_t* vartype,
+             const prop_params* prm) {
+  if (!A) return fail(PROP_EINVAL, "matrix is NULL");
+  if (A->m < 0 || A->n < 0) return fail(PROP_EINVAL, "negative dimension");
+  if (A->m > 0 && (!A->row_ptr || !lhs || !rhs))
+    return fail(PROP_EINVAL, "row arrays are NULL");
+  if (A->n > 0 && !vartype) return fail(PROP_EINVAL, "vartype is NULL");
+  if (A->m == 0 && A->row_ptr == nullptr) {
+    if (A->nnz != 0) return fail(PROP_EINVAL, "nnz without rows");
+  } else {
+    if (A->row_ptr[0] != 0) return fail(PROP_EINVAL, "row_ptr[0] != 0");
+    for (int32_t i = 0; i < A->m; ++i)
+      if (A->row_ptr[i + 1] < A->row_ptr[i]) return fail(PROP_EINVAL, "row_ptr decreases at row %d", i);
+    if (A->row_ptr[A->m] != A->nnz) return fail(PROP_EINVAL, "row_ptr[m] != nnz");
+  }
+  if (A->nnz > 0 && (!A->col_idx || !A->vals)) return fail(PROP_EINVAL, "entry arrays are NULL");
+  std::vector<int32_t> last(A->n > 0 ? A->n : 1, -1);
+  for (int32_t i = 0; i < A->m; ++i) {
+    for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k) {
+      const int32_t j = A->col_idx[k];
+      if (j < 0 || j >= A->n) return fail(PROP_EINVAL, "column %d out of range in row %d", j, i);
+      if (last[j] == i) return fail(PROP_EINVAL, "column %d repeated in row %d", j, i);
+      last[j] = i;
+      const double a = A->vals[k];
+      if (!std::isfinite(a)) return fail(PROP_EINVAL, "non-finite coefficient in row %d", i);
+      if (a != 0.0 && (std::fabs(a) < kCoefMin || std::fabs(a) > kCoefMax))
+        return fail(PROP_EINVAL, "coefficient magnitude outside [2^-64, 2^64] in row %d", i);
+    }
+    if (!side_ok(lhs[i], true)) return fail(PROP_EINVAL, "invalid lhs in row %d", i);
+    if (!side_ok(rhs[i], false)) return fail(PROP_EINVAL, "invalid rhs in row %d", i);
+  }
+  for (int32_t j = 0; j < A->n; ++j)
+    if (vartype[j] > 1) return fail(PROP_EINVAL, "vartype[%d] is neither 0 nor 1", j);
+  if (prm) {
+    if (!(prm->eps_int >= 0.0 && prm->eps_int < 0.5))
+      return fail(PROP_EINVAL, "eps_int must lie in [0, 0.5)");
+    if (!(prm->cont_rel_tol >= 0.0 && std::isfinite(prm->cont_rel_tol)))
+      return fail(PROP_EINVAL, "cont_rel_tol must be finite and >= 0");
+    if (!(prm->feas_tol >= 0.0 && std::isfinite(prm->feas_tol)))
+      return fail(PROP_EINVAL, "feas_tol must be finite and >= 0");
+  }
+  return PROP_OK;
+}
+
+int ceil_log2(int64_t x) {
+  int k = 0;
+  while ((int64_t(1) << k) < x) ++k;
+  return k;
+}
+
+// Builds the device layout described in prop_layout.h and uploads it.
+int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const double* rhs,
+                 const uint8_t* vartype) {
+  const int32_t m = A->m, n = A->n;
+  // nonzero entries per row and per column
+  std::vector<int64_t> len(m, 0);
+  std::vector<int64_t> deg(n, 0);
+  int64_t nnz = 0;
+  for (int32_t i = 0; i < m; ++i)
+    for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k)
+      if (A->vals[k] != 0.0) {
+        ++len[i];
+        ++deg[A->col_idx[k]];
+        ++nnz;
+      }
+  p->nnz = nnz;
+  bool infeasible = false;
+  for (int32_t i = 0; i < m && !infeasible; ++i) {
+    if (lhs[i] > rhs[i]) infeasible = true;
+    if (len[i] == 0 && (lhs[i] > 0.0 || rhs[i] < 0.0)) infeasible = true;
+  }
+  p->instance_infeasible = infeasible;
+
+  // variables by decreasing degree
+  std::vector<int32_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
+  std::vector<int32_t> perm(n);
+  for (int32_t q = 0; q < n; ++q) perm[order[q]] = q;
+  std::vector<uint8_t> vtype(n);
+  for (int32_t j = 0; j < n; ++j) vtype[perm[j]] = vartype[j];
+
+  // rows by lanes-per-row class; long rows apart
+  std::vector<std::vector<int32_t>> cls(7);
+  std::vector<int32_t> longs;
+  for (int32_t i = 0; i < m; ++i) {
+    if (len[i] == 0) continue;
+    if (len[i] > kSegLen) {
+      longs.push_back(i);
+      continue;
+    }
+    const int64_t steps16 = (len[i] + kMaxSteps - 1) / kMaxSteps;
+    cls[ceil_log2(steps16)].push_back(i);
+  }
+  struct Chunk {
+    int klog, W, nrows;
+    size_t first;  // index into the class's sorted row list
+  };
+  std::vector<Chunk> chunks;
+  for (int k = 0; k <= 6; ++k) {
+    auto& rows = cls[k];
+    std::stable_sort(rows.begin(), rows.end(), [&](int32_t a, int32_t b) { return len[a] > len[b]; });
+    const int per = kWave >> k;
+    for (size_t q = 0; q < rows.size(); q += per) {
+      const int nr = (int)std::min<size_t>(per, rows.size() - q);
+      const int W = (int)((len[rows[q]] + (1 << k) - 1) >> k);
+      chunks.push_back({k, W, nr, q});
+    }
+  }
+  // heaviest tiles first
+  std::stable_sort(chunks.begin(), chunks.end(), [](const Chunk& a, const Chunk& b) {
+    return a.W != b.W ? a.W > b.W : a.klog > b.klog;
+  });
+
+  int64_t stored = 0;
+  for (auto& c : chunks) stored += (int64_t)kWave * c.W;
+  const int64_t chunk_entries = stored;
+  for (int32_t i : longs) stored += (len[i] + kWave - 1) / kWave * kWave;
+  if (chunk_entries / kWave > INT32_MAX) return fail(PROP_EINVAL, "matrix too large for the layout");
+  p->nnz_stored = stored;
+
+  std::vector<double> h_vals(stored, 0.0);
+  std::vector<int32_t> h_cols(stored, 0);
+  std::vector<ChunkDesc> h_chunks;
+  h_chunks.reserve(chunks.size());
+  std::vector<double> h_lhs, h_rhs;
+  h_lhs.reserve(m);
+  h_rhs.reserve(m);
+  int64_t off = 0;
+  int32_t next_row = 0;
+  for (auto& c : chunks) {
+    const auto& rows = cls[c.klog];
+    const int K = 1 << c.klog;
+    ChunkDesc d;
+    d.off64 = (int32_t)(off / kWave);
+    d.row0 = next_row;
+    d.meta = c.klog | (c.W << 8) | (c.nrows << 16);
+    d.pad = 0;
+    h_chunks.push_back(d);
+    for (int q = 0; q < c.nrows; ++q) {
+      const int32_t i = rows[c.first + q];
+      h_lhs.push_back(lhs[i] + 0.0);
+      h_rhs.push_back(rhs[i] + 0.0);
+      int64_t pos = 0;
+      for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k) {
+        if (A->vals[k] == 0.0) continue;
+        const int64_t lane = (int64_t)q * K + pos % K;
+        const int64_t step = pos / K;
+        const int64_t idx = off + step * kWave + lane;
+        h_vals[idx] = A->vals[k];
+        h_cols[idx] = perm[A->col_idx[k]];
+        ++pos;
+      }
+    }
+    next_row += c.nrows;
+    off += (int64_t)kWave * c.W;
+  }
+  std::vector<SegDesc> h_segs;
+  for (int32_t i : longs) {
+    const int32_t row = next_row++;
+    h_lhs.push_back(lhs[i] + 0.0);
+    h_rhs.push_back(rhs[i] + 0.0);
+    const int32_t first = (int32_t)h_segs.size();
+    const int32_t nseg = (int32_t)((len[i] + kSegLen - 1) / kSegLen);
+    for (int32_t s = 0; s < nseg; ++s) {
+      SegDesc d;
+      d.off = off + (int64_t)s * kSegLen;
+      d.row = row;
+      d.len = (int32_t)std::min<int64_t>(kSegLen, len[i] - (int64_t)s * kSegLen);
+      d.first = first;
+      d.nseg = nseg;
+      d.pad0 = d.pad1 = 0;
+      h_segs.push_back(d);
+    }
+    int64_t pos = 0;
+    for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k) {
+      if (A->vals[k] == 0.0) continue;
+      h_vals[off + pos] = A->vals[k];
+      h_cols[off + pos] = perm[A->col_idx[k]];
+      ++pos;
+    }
+    off += (len[i] + kWave - 1) / kWave * kWave;
+  }
+  p->n_long_rows = (int32_t)longs.size();
+
+  // every index a kernel forms must stay inside the arrays built above
+  const int64_t n_rows_internal = next_row;
+  for (const ChunkDesc& d : h_chunks) {
+    const int W = (d.meta >> 8) & 0xff, nr = (d.meta >> 16) & 0xff, kl = d.meta & 7;
+    if (W < 1 || W > kMaxSteps || nr < 1 || nr > (kWave >> kl) ||
+        (int64_t)d.off64 * kWave + (int64_t)W * kWave > chunk_entries || d.row0 < 0 ||
+        d.row0 + nr > n_rows_internal)
+      return fail(PROP_EINVAL, "internal layout check failed (chunk)");
+  }
+  for (const SegDesc& d : h_segs) {
+    if (d.len < 1 || d.len > kSegLen || d.off < chunk_entries || d.off + d.len > stored ||
+        d.first < 0 || d.first + d.nseg > (int32_t)h_segs.size() || d.row < 0 ||
+        d.row >= n_rows_internal)
+      return fail(PROP_EINVAL, "internal layout check failed (segment)");
+  }
+  for (int64_t q = 0; q < stored; ++q)
+    if (h_cols[q] < 0 || (n > 0 && h_cols[q] >= n) || (n == 0 && stored > 0))
+      return fail(PROP_EINVAL, "internal layout check failed (column)");
+  if ((int64_t)h_lhs.size() != n_rows_internal)
+    return fail(PROP_EINVAL, "internal layout check failed (rows)");
+
+  Problem& P = p->P;
+  int rc;
+  double* d_vals;
+  int32_t* d_cols;
+  ChunkDesc* d_chunks;
+  SegDesc* d_segs;
+  double *d_lhs, *d_rhs;
+  uint8_t* d_vtype;
+  int32_t* d_perm;
+  if ((rc = dev_upload(p, &d_vals, h_vals))) return rc;
+  if ((rc = dev_upload(p, &d_cols, h_cols))) return rc;
+  if ((rc = dev_upload(p, &d_chunks, h_chunks))) return rc;
+  if ((rc = dev_upload(p, &d_segs, h_segs))) return rc;
+  if ((rc = dev_upload(p, &d_lhs, h_lhs))) return rc;
+  if ((rc = dev_upload(p, &d_rhs, h_rhs))) return rc;
+  if ((rc = dev_upload(p, &d_vtype, vtype))) return rc;
+  if ((rc = dev_upload(p, &d_perm, perm))) return rc;
+  SegPartial* d_part;
+  if ((rc = dev_alloc(p, &d_part, h_segs.size()))) return rc;
+  double2 *b0, *b1;
+  if ((rc = dev_alloc(p, &b0, (size_t)n))) return rc;
+  if ((rc = dev_alloc(p, &b1, (size_t)n))) return rc;
+  int32_t *l0, *l1;
+  if ((rc = dev_alloc(p, &l0, 2 * (size_t)n))) return rc;
+  if ((rc = dev_alloc(p, &l1, 2 * (size_t)n))) return rc;
+  Ctrl* d_ctrl;
+  if ((rc = dev_alloc(p, &d_ctrl, 1))) return rc;
+  HIP_TRY(hipMemset(d_ctrl, 0, sizeof(Ctrl)));
+  if ((rc = dev_alloc(p, &p->d_stage_lb, (size_t)n))) return rc;
+  if ((rc = dev_alloc(p, &p->d_stage_ub, (size_t)n))) return rc;
+
+  P.vals = d_vals;
+  P.cols = d_cols;
+  P.chunks = d_chunks;
+  P.segs = d_segs;
+  P.partials = d_part;
+  P.lhs = d_lhs;
+  P.rhs = d_rhs;
+  P.vtype = d_vtype;
+  P.perm = d_perm;
+  P.n_chunks = (int32_t)h_chunks.size();
+  P.n_segs = (int32_t)h_segs.size();
+  P.n = n;
+  P.instance_infeasible = p->instance_infeasible ? 1 : 0;
+  P.bnd[0] = b0;
+  P.bnd[1] = b1;
+  P.list[0] = l0;
+  P.list[1] = l1;
+  P.ctrl = d_ctrl;
+  P.eps_int = p->params.eps_int;
+  P.cont_rel_tol = p->params.cont_rel_tol;
+  P.feas_tol = p->params.feas_tol;
+  return PROP_OK;
+}
+
+int run_loop(prop_problem* p, int32_t max_rounds, hipStream_t s) {
+  const Problem& P = p->P;
+  hipError_t e;
+  switch (p->loop_mode) {
+    case PROP_LOOP_PERSISTENT:
+      e = launch_persistent(P, max_rounds, p->grid, s);
+      if (e != hipSuccess)
+        return fail(PROP_EDEVICE, "cooperative launch failed: %s", hipGetErrorString(e));
+      return PROP_OK;
+    case PROP_LOOP_STREAM:
+      HIP_TRY(launch_start(P, max_rounds, s));
+      for (int r = 1; r <= max_rounds; ++r) HIP_TRY(launch_round(P, r, max_rounds, s));
+      return PROP_OK;
+    default:
+      HIP_TRY(launch_start(P, max_rounds, s));
+      for (int r = 1; r <= max_rounds; ++r) {
+        HIP_TRY(launch_round(P, r, max_rounds, s));
+        HIP_TRY(hipMemcpyAsync(&p->h_ctrl->done, &P.ctrl->done, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (p->h_ctrl->done == 1) break;
+      }
+      return PROP_OK;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int prop_create(const prop_csr* A, const double* lhs, const double* rhs, const uint8_t* vartype,
+                const prop_params* params, prop_problem** out) {
+  if (!out) return fail(PROP_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(A, lhs, rhs, vartype, params);
+  if (rc) return rc;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0)
+    return fail(PROP_EDEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+  prop_problem* p = new (std::nothrow) prop_problem();
+  if (!p) return fail(PROP_ENOMEM, "host allocation failed");
+  if (params) p->params = *params;
+  p->m = A->m;
+  p->n = A->n;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    release(p);
+    return fail(PROP_EDEVICE, "hipGetDevice failed");
+  }
+  rc = build_layout(p, A, lhs, rhs, vartype);
+  if (rc) {
+    release(p);
+    return rc;
+  }
+  int coop = 0, cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, p->device) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
+      persistent_occupancy(&per_cu) != hipSuccess || cus <= 0 || per_cu <= 0) {
+    release(p);
+    return fail(PROP_EDEVICE, "device attribute / occupancy query failed");
+  }
+  p->grid = cus * per_cu;
+  if (!coop) p->loop_mode = PROP_LOOP_STREAM;
+  if (hipHostMalloc((void**)&p->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+    release(p);
+    return fail(PROP_ENOMEM, "pinned host allocation failed");
+  }
+  for (auto& ev : p->ev)
+    if (hipEventCreate(&ev) != hipSuccess) {
+      release(p);
+      return fail(PROP_EDEVICE, "hipEventCreate failed");
+    }
+  *out = p;
+  g_error.clear();
+  return PROP_OK;
+}
+
+int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rounds, void* stream,
+                    prop_result* out) {
+  if (!p || !out) return fail(PROP_EINVAL, "NULL argument");
+  if (max_rounds < 0) return fail(PROP_EINVAL, "max_rounds < 0");
+  if (p->n > 0 && (!d_lb || !d_ub)) return fail(PROP_EINVAL, "bound arrays are NULL");
+  HIP_TRY(hipSetDevice(p->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Problem& P = p->P;
+  HIP_TRY(hipEventRecord(p->ev[0], s));
+  HIP_TRY(launch_init(P, s));
+  HIP_TRY(launch_pack(P, d_lb, d_ub, s));
+  HIP_TRY(hipEventRecord(p->ev[1], s));
+  int rc = run_loop(p, max_rounds, s);
+  if (rc) {
+    hipStreamSynchronize(s);
+    return rc;
+  }
+  HIP_TRY(hipEventRecord(p->ev[2], s));
+  HIP_TRY(launch_unpack(P, d_lb, d_ub, s));
+  HIP_TRY(hipMemcpyAsync(p->h_ctrl, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(p->ev[3], s));
+  HIP_TRY(hipStreamSynchronize(s));
+  hipEventElapsedTime(&p->last_loop_ms, p->ev[1], p->ev[2]);
+  hipEventElapsedTime(&p->last_total_ms, p->ev[0], p->ev[3]);
+  const Ctrl& C = *p->h_ctrl;
+  if (C.invalid) return fail(PROP_EINVAL, "a bound is NaN, +inf as lower, -inf as upper, or beyond 2^200");
+  if (C.abort) return fail(PROP_EDEVICE, "grid barrier wait timed out");
+  if (C.done != 1) return fail(PROP_EDEVICE, "round loop did not finish (done=%u)", C.done);
+  out->status = C.status;
+  out->rounds = C.rounds;
+  g_error.clear();
+  return PROP_OK;
+}
+
+int prop_run(prop_problem* p, double* lb, double* ub, int32_t max_rounds, prop_result* out) {
+  if (!p || !out) return fail(PROP_EINVAL, "NULL argument");
+  if (p->n > 0 && (!lb || !ub)) return fail(PROP_EINVAL, "bound arrays are NULL");
+  HIP_TRY(hipSetDevice(p->device));
+  const size_t bytes = sizeof(double) * (size_t)p->n;
+  if (bytes) {
+    HIP_TRY(hipMemcpy(p->d_stage_lb, lb, bytes, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->d_stage_ub, ub, bytes, hipMemcpyHostToDevice));
+  }
+  int rc = prop_run_device(p, p->d_stage_lb, p->d_stage_ub, max_rounds, nullptr, out);
+  if (rc) return rc;
+  if (bytes) {
+    HIP_TRY(hipMemcpy(lb, p->d_stage_lb, bytes, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ub, p->d_stage_ub, bytes, hipMemcpyDeviceToHost));
+  }
+  return PROP_OK;
+}
+
+int prop_set_loop(prop_problem* p, int32_t mode) {
+  if (!p) return fail(PROP_EINVAL, "NULL problem");
+  if (mode != PROP_LOOP_PERSISTENT && mode != PROP_LOOP_STREAM && mode != PROP_LOOP_HOST)
+    return fail(PROP_EINVAL, "unknown loop mode %d", mode);
+  p->loop_mode = mode;
+  return PROP_OK;
+}
+
+int prop_get_info(const prop_problem* p, prop_info* out) {
+  if (!p || !out) return fail(PROP_EINVAL, "NULL argument");
+  out->m = p->m;
+  out->n = p->n;
+  out->nnz = p->nnz;
+  out->nnz_stored = p->nnz_stored;
+  out->n_chunks = p->P.n_chunks;
+  out->n_long_rows = p->n_long_rows;
+  out->n_segments = p->P.n_segs;
+  out->grid_blocks = p->grid;
+  out->device_bytes = p->device_bytes;
+  out->alg_bytes_round = 12 * p->nnz + 20 * (int64_t)p->m + 33 * (int64_t)p->n + 4;
+  return PROP_OK;
+}
+
+int prop_last_timing(const prop_problem* p, double* loop_ms, double* total_ms) {
+  if (!p) return fail(PROP_EINVAL, "NULL problem");
+  if (loop_ms) *loop_ms = p->last_loop_ms;
+  if (total_ms) *total_ms = p->last_total_ms;
+  return PROP_OK;
+}
+
+void prop_destroy(prop_problem* p) {
+  if (!p) return;
+  hipSetDevice(p->device);
+  hipDeviceSynchronize();
+  release(p);
+}
+
+const char* prop_last_error(void) { return g_error.c_str(); }
+
+}  // extern "C"

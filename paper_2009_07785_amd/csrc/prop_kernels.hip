@@ -1,0 +1,721 @@
+// prop_kernels.hip -- gfx950 kernels of one synchronous propagation round
+// (Sofranac, Gleixner, Pokutta, arXiv 2009.07785, Algorithms 2 and 3) and
+// the drivers that repeat rounds on the device.
+//
+// One round, for every row:
+//   1. min / max activity from the start-of-round bounds: finite parts as
+//      exact-product double-double sums (rounded once at the end), plus the
+//      counts of infinite contributions (Definition 1; Sec. 3.4);
+//   2. per entry the candidates of Step 3 (eqs. bound_candidates_pos / _neg),
+//      rounded inward for integer variables, each one IEEE operation in the
+//      order (beta - activity) / a + bound;
+//   3. a candidate that beats the start-of-round bound is applied with an
+//      FP64 atomic max (lower) / min (upper) on the "next" bound array
+//      (Sec. 3.5, Algorithm 3); the first thread that moves a bound records
+//      the variable in the round's changed list.
+// The next round reads the array written in this one and writes the other;
+// the variables changed one round earlier are brought up to date in it with
+// the same atomics (max and min commute, so this can overlap the round's
+// own candidates), and their domains are checked for emptiness.
+//
+// Work units: a "chunk" is one wave's tile of short/medium rows, data laid
+// out so each of up to 16 steps is one contiguous 64-entry load; a row of
+// K lanes sums its entries lane-by-lane, then across its K lanes.  Long rows
+// (more than 1024 entries) are split into 1024-entry segments: phase 1
+// writes a partial sum per segment, phase 2 combines all partials of the
+// row in a fixed order and handles the segment's candidates.
+//
+// Before any candidate arithmetic an entry is skipped when its row's slack
+// provably cannot tighten it: slack > |a| * (u - l) with a 2^-40 margin
+// (and slack > 0 for a fixed variable).  The margin covers the rounding of
+// the test itself and of the candidate formula, so a skipped entry is one
+// whose exact candidate would not have been applied.
+#include <hip/hip_runtime.h>
+
+#include "prop_launch.h"
+#include "prop_layout.h"
+
+#pragma clang fp contract(off)
+
+namespace prop {
+
+#define PROP_HUGE 0x1p200
+#define PROP_SKIP_MARGIN (1.0 + 0x1p-40)
+#define PROP_SKIP_FLOOR 0x1p-900
+
+// ---------------------------------------------------------------------------
+// exact-product double-double accumulation
+// ---------------------------------------------------------------------------
+struct DD {
+  double hi, lo;
+};
+
+// s += a * b: the product is split exactly into p + ep (FMA), p is added to
+// s.hi with an error-free two-sum, and both error terms go to s.lo.
+__device__ __forceinline__ void dd_add_prod(DD& s, double a, double b) {
+  double p = a * b;
+  double ep = __builtin_fma(a, b, -p);
+  double t = s.hi + p;
+  double z = t - s.hi;
+  double e = (s.hi - (t - z)) + (p - z);
+  s.hi = t;
+  s.lo = s.lo + (e + ep);
+}
+
+// s += (yhi, ylo); symmetric in its two operands, so both lanes of a
+// butterfly exchange end with identical bits.
+__device__ __forceinline__ void dd_add(DD& s, double yhi, double ylo) {
+  double t = s.hi + yhi;
+  double z = t - s.hi;
+  double e = (s.hi - (t - z)) + (yhi - z);
+  s.hi = t;
+  s.lo = (s.lo + ylo) + e;
+}
+
+__device__ __forceinline__ double dd_value(const DD& s) { return (s.hi + s.lo) + 0.0; }
+
+template <int KLOG>
+__device__ __forceinline__ void group_reduce(DD& smin, DD& smax, int& cmin, int& cmax) {
+#pragma unroll
+  for (int off = 1; off < (1 << KLOG); off <<= 1) {
+    double a = __shfl_xor(smin.hi, off, kWave);
+    double b = __shfl_xor(smin.lo, off, kWave);
+    double c = __shfl_xor(smax.hi, off, kWave);
+    double d = __shfl_xor(smax.lo, off, kWave);
+    int e = __shfl_xor(cmin, off, kWave);
+    int f = __shfl_xor(cmax, off, kWave);
+    dd_add(smin, a, b);
+    dd_add(smax, c, d);
+    cmin += e;
+    cmax += f;
+  }
+}
+
+__device__ __forceinline__ bool is_inf(double x) { return __builtin_isinf(x); }
+
+// Contribution of one entry to both activities.
+__device__ __forceinline__ void accumulate(double a, double l, double u, DD& smin, DD& smax,
+                                           int& cmin, int& cmax) {
+  const double bmin = a > 0.0 ? l : u;
+  const double bmax = a > 0.0 ? u : l;
+  const bool imin = is_inf(bmin);
+  const bool imax = is_inf(bmax);
+  cmin += (a != 0.0 && imin) ? 1 : 0;
+  cmax += (a != 0.0 && imax) ? 1 : 0;
+  dd_add_prod(smin, a, imin ? 0.0 : bmin);
+  dd_add_prod(smax, a, imax ? 0.0 : bmax);
+}
+
+// Largest slack for which the entry could still be tightened (see header).
+__device__ __forceinline__ double skip_threshold(double a, double l, double u) {
+  const double w = u - l;
+  if (w == 0.0) return 0.0;
+  if (!(w > 0.0)) return __builtin_inf();
+  const double thr = (__builtin_fabs(a) * w) * PROP_SKIP_MARGIN;
+  return thr >= PROP_SKIP_FLOOR ? thr : __builtin_inf();
+}
+
+__device__ __forceinline__ bool domain_empty(bool is_int, double l, double u, double feas_tol) {
+  if (is_int) return l > u;
+  double s = __builtin_fabs(l) > __builtin_fabs(u) ? __builtin_fabs(l) : __builtin_fabs(u);
+  if (s < 1.0) s = 1.0;
+  return (l - u) > feas_tol * s;
+}
+
+__device__ __forceinline__ double atomic_max_f64(double* p, double v) {
+  return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double atomic_min_f64(double* p, double v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void record_change(int32_t j, int32_t* list, uint32_t* count) {
+  uint32_t q = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  list[q] = j;
+}
+
+// Row-level quantities every entry of a row needs.
+struct RowState {
+  double minfin, maxfin;
+  int cmin, cmax;
+  bool min_side, max_side;  // the rhs / lhs side can yield candidates
+  double smn;               // rhs - min activity
+  double smx;               // lhs - max activity
+};
+
+__device__ __forceinline__ RowState make_row_state(const DD& smin, const DD& smax, int cmin,
+                                                   int cmax, double lhs, double rhs) {
+  RowState R;
+  R.minfin = dd_value(smin);
+  R.maxfin = dd_value(smax);
+  R.cmin = cmin;
+  R.cmax = cmax;
+  R.min_side = (rhs < __builtin_inf()) && cmin <= 1;
+  R.max_side = (lhs > -__builtin_inf()) && cmax <= 1;
+  R.smn = rhs - R.minfin;
+  R.smx = lhs - R.maxfin;
+  return R;
+}
+
+// Whether entry (a; l, u) needs the candidate arithmetic at all.
+__device__ __forceinline__ bool entry_wanted(const RowState& R, double a, double l, double u) {
+  if (a == 0.0) return false;
+  const double thr = skip_threshold(a, l, u);
+  bool d = false;
+  if (R.min_side) d |= (R.cmin == 0) ? !(R.smn > thr) : is_inf(a > 0.0 ? l : u);
+  if (R.max_side) d |= (R.cmax == 0) ? !((-R.smx) > thr) : is_inf(a > 0.0 ? u : l);
+  return d;
+}
+
+// Candidates of one entry (a, j) with start-of-round bounds (l, u).
+__device__ __forceinline__ void entry_candidates(const Problem& P, const RowState& R, double a,
+                                                 double l, double u, int32_t j,
+                                                 double2* __restrict__ nxt, int32_t* list,
+                                                 uint32_t* count) {
+  if (a == 0.0) return;
+  const double bmin = a > 0.0 ? l : u;
+  const double bmax = a > 0.0 ? u : l;
+  bool dmin = false, dmax = false;
+  if (R.min_side) {
+    if (R.cmin == 0) dmin = !(R.smn > skip_threshold(a, l, u));
+    else dmin = is_inf(bmin);
+  }
+  if (R.max_side) {
+    if (R.cmax == 0) dmax = !((-R.smx) > skip_threshold(a, l, u));
+    else dmax = is_inf(bmax);
+  }
+  if (!(dmin || dmax)) return;
+
+  double lc = 0.0, uc = 0.0;
+  bool hl = false, hu = false;
+  if (dmin) {  // rhs side: (rhs - min act) / a (+ b_min when no infinity)
+    double t = R.smn / a;
+    if (R.cmin == 0) t = t + bmin;
+    if (a > 0.0) { uc = t; hu = true; } else { lc = t; hl = true; }
+  }
+  if (dmax) {  // lhs side: (lhs - max act) / a (+ b_max when no infinity)
+    double t = R.smx / a;
+    if (R.cmax == 0) t = t + bmax;
+    if (a > 0.0) { lc = t; hl = true; } else { uc = t; hu = true; }
+  }
+  const bool is_int = P.vtype[j] != 0;
+  if (hl) {
+    double c = is_int ? __builtin_ceil(lc - P.eps_int) : lc;
+    c = c + 0.0;
+    if (__builtin_fabs(c) <= PROP_HUGE) {
+      bool sig;
+      if (l == -__builtin_inf()) sig = true;
+      else if (is_int) sig = c > l;
+      else {
+        double s = __builtin_fabs(l) > 1.0 ? __builtin_fabs(l) : 1.0;
+        sig = c > l + P.cont_rel_tol * s;
+      }
+      if (sig) {
+        double old = atomic_max_f64(&nxt[j].x, c);
+        if (old <= l) record_change(j, list, count);
+      }
+    }
+  }
+  if (hu) {
+    double c = is_int ? __builtin_floor(uc + P.eps_int) : uc;
+    c = c + 0.0;
+    if (__builtin_fabs(c) <= PROP_HUGE) {
+      bool sig;
+      if (u == __builtin_inf()) sig = true;
+      else if (is_int) sig = c < u;
+      else {
+        double s = __builtin_fabs(u) > 1.0 ? __builtin_fabs(u) : 1.0;
+        sig = c < u - P.cont_rel_tol * s;
+      }
+      if (sig) {
+        double old = atomic_min_f64(&nxt[j].y, c);
+        if (old >= u) record_change(j, list, count);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one chunk: activities and candidates for 64/K rows, K lanes per row
+// ---------------------------------------------------------------------------
+template <int KLOG>
+__device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd, const double2* __restrict__ cur,
+                            double2* __restrict__ nxt, int32_t* list, uint32_t* count) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int W = (cd.meta >> 8) & 0xff;
+  const int nrows = (cd.meta >> 16) & 0xff;
+  const int r = lane >> KLOG;
+  const size_t base = (size_t)cd.off64 * kWave + lane;
+  double a[kMaxSteps], l[kMaxSteps], u[kMaxSteps];
+  int32_t jj[kMaxSteps];
+#pragma unroll
+  for (int w = 0; w < kMaxSteps; ++w) {
+    a[w] = 0.0;
+    jj[w] = 0;
+    if (w < W) {
+      a[w] = __builtin_nontemporal_load(P.vals + base + (size_t)w * kWave);
+      jj[w] = __builtin_nontemporal_load(P.cols + base + (size_t)w * kWave);
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < kMaxSteps; ++w) {
+    l[w] = 0.0;
+    u[w] = 0.0;
+    if (w < W && a[w] != 0.0) {
+      const double2 b = cur[jj[w]];
+      l[w] = b.x;
+      u[w] = b.y;
+    }
+  }
+  DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
+  int cmin = 0, cmax = 0;
+#pragma unroll
+  for (int w = 0; w < kMaxSteps; ++w)
+    if (w < W) accumulate(a[w], l[w], u[w], smin, smax, cmin, cmax);
+  group_reduce<KLOG>(smin, smax, cmin, cmax);
+  if (r >= nrows) return;
+  const int row = cd.row0 + r;
+  const RowState R = make_row_state(smin, smax, cmin, cmax, P.lhs[row], P.rhs[row]);
+  if (!(R.min_side || R.max_side)) return;
+  // cheap filter over the registers, then the rare full candidate work on
+  // the flagged entries, reloaded (cache-hot) by step index
+  uint32_t need = 0;
+#pragma unroll
+  for (int w = 0; w < kMaxSteps; ++w)
+    if (w < W && entry_wanted(R, a[w], l[w], u[w])) need |= 1u << w;
+  while (need) {
+    const int w = __builtin_ctz(need);
+    need &= need - 1;
+    const size_t idx = base + (size_t)w * kWave;
+    const double av = P.vals[idx];
+    const int32_t j = P.cols[idx];
+    const double2 b = cur[j];
+    entry_candidates(P, R, av, b.x, b.y, j, nxt, list, count);
+  }
+}
+
+__device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const double2* cur, double2* nxt,
+                               int32_t* list, uint32_t* count) {
+  const ChunkDesc cd = P.chunks[c];
+  switch (cd.meta & 7) {
+    case 0: chunk_round<0>(P, cd, cur, nxt, list, count); break;
+    case 1: chunk_round<1>(P, cd, cur, nxt, list, count); break;
+    case 2: chunk_round<2>(P, cd, cur, nxt, list, count); break;
+    case 3: chunk_round<3>(P, cd, cur, nxt, list, count); break;
+    case 4: chunk_round<4>(P, cd, cur, nxt, list, count); break;
+    case 5: chunk_round<5>(P, cd, cur, nxt, list, count); break;
+    default: chunk_round<6>(P, cd, cur, nxt, list, count); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// long rows
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void seg_phase1(const Problem& P, int s, const double2* __restrict__ cur) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const SegDesc sd = P.segs[s];
+  DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
+  int cmin = 0, cmax = 0;
+  double wmax = 0.0;
+  double a[kMaxSteps];
+  int32_t jj[kMaxSteps];
+#pragma unroll
+  for (int w = 0; w < kMaxSteps; ++w) {
+    const int p = w * kWave + lane;
+    a[w] = 0.0;
+    jj[w] = 0;
+    if (p < sd.len) {
+      a[w] = __builtin_nontemporal_load(P.vals + sd.off + p);
+      jj[w] = __builtin_nontemporal_load(P.cols + sd.off + p);
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < kMaxSteps; ++w) {
+    if (a[w] != 0.0) {
+      const double2 b = cur[jj[w]];
+      accumulate(a[w], b.x, b.y, smin, smax, cmin, cmax);
+      const double t = skip_threshold(a[w], b.x, b.y);
+      wmax = t > wmax ? t : wmax;
+    }
+  }
+  group_reduce<6>(smin, smax, cmin, cmax);
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double o = __shfl_xor(wmax, off, kWave);
+    wmax = o > wmax ? o : wmax;
+  }
+  if (lane == 0) {
+    SegPartial q;
+    q.min_hi = smin.hi;
+    q.min_lo = smin.lo;
+    q.max_hi = smax.hi;
+    q.max_lo = smax.lo;
+    q.wmax = wmax;
+    q.min_inf = cmin;
+    q.max_inf = cmax;
+    q.min_inf_own = cmin;
+    q.max_inf_own = cmax;
+    q.pad0 = q.pad1 = 0;
+    P.partials[s] = q;
+  }
+}
+
+__device__ __forceinline__ void seg_phase2(const Problem& P, int s, const double2* __restrict__ cur,
+                           double2* __restrict__ nxt, int32_t* list, uint32_t* count) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const SegDesc sd = P.segs[s];
+  DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
+  int cmin = 0, cmax = 0;
+  for (int q = lane; q < sd.nseg; q += kWave) {
+    const SegPartial pp = P.partials[sd.first + q];
+    dd_add(smin, pp.min_hi, pp.min_lo);
+    dd_add(smax, pp.max_hi, pp.max_lo);
+    cmin += pp.min_inf;
+    cmax += pp.max_inf;
+  }
+  group_reduce<6>(smin, smax, cmin, cmax);
+  const RowState R = make_row_state(smin, smax, cmin, cmax, P.lhs[sd.row], P.rhs[sd.row]);
+  const SegPartial own = P.partials[s];
+  bool need = false;
+  if (R.min_side) need |= (R.cmin == 0) ? !(R.smn > own.wmax) : (own.min_inf_own > 0);
+  if (R.max_side) need |= (R.cmax == 0) ? !((-R.smx) > own.wmax) : (own.max_inf_own > 0);
+  if (!need) return;
+  for (int p = lane; p < sd.len; p += kWave) {
+    const double a = P.vals[sd.off + p];
+    if (a == 0.0) continue;
+    const int32_t j = P.cols[sd.off + p];
+    const double2 b = cur[j];
+    if (entry_wanted(R, a, b.x, b.y)) entry_candidates(P, R, a, b.x, b.y, j, nxt, list, count);
+  }
+}
+
+// Bring the variables changed one round earlier up to date in `nxt` and
+// check their (now final) domains in `cur`.
+__device__ __forceinline__ void fixup_and_check(const Problem& P, const int32_t* plist, uint32_t pcount,
+                                const double2* __restrict__ cur, double2* __restrict__ nxt,
+                                uint32_t tid, uint32_t nthreads) {
+  for (uint32_t q = tid; q < pcount; q += nthreads) {
+    const int32_t j = plist[q];
+    const double2 b = cur[j];
+    atomic_max_f64(&nxt[j].x, b.x);
+    atomic_min_f64(&nxt[j].y, b.y);
+    if (domain_empty(P.vtype[j] != 0, b.x, b.y, P.feas_tol))
+      __hip_atomic_store(&P.ctrl->infeasible, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Check the domains of the variables in a list (after the last round).
+__device__ __forceinline__ void check_list(const Problem& P, const int32_t* lst, uint32_t count,
+                           const double2* __restrict__ b, uint32_t tid, uint32_t nthreads) {
+  for (uint32_t q = tid; q < count; q += nthreads) {
+    const int32_t j = lst[q];
+    const double2 v = b[j];
+    if (domain_empty(P.vtype[j] != 0, v.x, v.y, P.feas_tol))
+      __hip_atomic_store(&P.ctrl->infeasible, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ uint32_t ld_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Status after round r (single thread).  Returns nothing; sets ctrl->done.
+//   done = 1: finished; done = 2: round limit reached with changes, the
+//   domains changed in the last round still have to be checked.
+__device__ __forceinline__ void end_of_round(const Problem& P, int r, int max_rounds) {
+  Ctrl* C = P.ctrl;
+  const uint32_t inf = ld_u32(&C->infeasible);
+  const uint32_t cnt = ld_u32(&C->list_count[r & 1]);
+  if (inf) {
+    C->status = kInfeasible;
+    C->rounds = r - 1;
+    C->result_buf = (uint32_t)((r - 1) & 1);
+    C->done = 1;
+  } else if (cnt == 0) {
+    C->status = kConverged;
+    C->rounds = r;
+    C->result_buf = (uint32_t)(r & 1);
+    C->done = 1;
+  } else if (r >= max_rounds) {
+    C->status = kMaxRounds;
+    C->rounds = r;
+    C->result_buf = (uint32_t)(r & 1);
+    C->done = 2;
+  }
+  C->list_count[(r + 1) & 1] = 0;
+  C->round = r + 1;
+}
+
+__device__ __forceinline__ void after_final_check(const Problem& P) {
+  Ctrl* C = P.ctrl;
+  if (ld_u32(&C->infeasible)) C->status = kInfeasible;
+  C->done = 1;
+}
+
+// Round-0 decision, shared by all drivers (single thread).
+__device__ __forceinline__ void start_status(const Problem& P, int max_rounds) {
+  Ctrl* C = P.ctrl;
+  C->round = 1;
+  if (ld_u32(&C->invalid) || ld_u32(&C->infeasible) || P.instance_infeasible) {
+    C->status = kInfeasible;
+    C->rounds = 0;
+    C->result_buf = 0;
+    C->done = 1;
+  } else if (max_rounds == 0) {
+    C->status = kMaxRounds;
+    C->rounds = 0;
+    C->result_buf = 0;
+    C->done = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// grid barrier for the persistent driver (sense-reversing, bounded wait)
+// ---------------------------------------------------------------------------
+#define PROP_SPIN_LIMIT (1u << 26)
+
+// What the last block to arrive at a barrier does before releasing the rest.
+enum BarrierAction { kActNone = 0, kActStart = 1, kActEndRound = 2, kActFinal = 3 };
+
+// All threads of all blocks call this.  The action runs on the last
+// arriving block's thread 0 before the others are released.  Returns false
+// when the wait gave up (every block then leaves its loop).
+__device__ __forceinline__ bool grid_barrier(const Problem& P, int action, int r, int max_rounds) {
+  Ctrl* C = P.ctrl;
+  __threadfence();
+  __syncthreads();
+  __shared__ uint32_t ok_shared;
+  if (threadIdx.x == 0) {
+    uint32_t ok = 1;
+    const uint32_t g = __hip_atomic_load(&C->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t prev =
+        __hip_atomic_fetch_add(&C->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == gridDim.x - 1) {
+      if (action == kActStart) start_status(P, max_rounds);
+      else if (action == kActEndRound) end_of_round(P, r, max_rounds);
+      else if (action == kActFinal) after_final_check(P);
+      __hip_atomic_store(&C->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&C->bar_gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(&C->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > PROP_SPIN_LIMIT ||
+            __hip_atomic_load(&C->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          __hip_atomic_store(&C->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    ok_shared = ok;
+  }
+  __syncthreads();
+  __threadfence();
+  return ok_shared != 0;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+__global__ void k_init(Problem P) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctrl* C = P.ctrl;
+    C->list_count[0] = 0;
+    C->list_count[1] = 0;
+    C->infeasible = 0;
+    C->invalid = 0;
+    C->status = kMaxRounds;
+    C->rounds = 0;
+    C->done = 0;
+    C->result_buf = 0;
+    C->round = 1;
+    C->bar_count = 0;
+    C->bar_gen = 0;
+    C->abort = 0;
+  }
+}
+
+// Validate, integer-round and relabel the caller's bounds into both arrays.
+__global__ __launch_bounds__(kBlock) void k_pack(Problem P, const double* __restrict__ ulb,
+                                                 const double* __restrict__ uub) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)P.n; v += stride) {
+    double l = ulb[v], u = uub[v];
+    const bool bad = __builtin_isnan(l) || __builtin_isnan(u) || l == __builtin_inf() ||
+                     u == -__builtin_inf() ||
+                     (!is_inf(l) && __builtin_fabs(l) > PROP_HUGE) ||
+                     (!is_inf(u) && __builtin_fabs(u) > PROP_HUGE);
+    if (bad) __hip_atomic_store(&P.ctrl->invalid, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t j = P.perm[v];
+    const bool is_int = P.vtype[j] != 0;
+    if (is_int) {
+      l = __builtin_ceil(l - P.eps_int);
+      u = __builtin_floor(u + P.eps_int);
+    }
+    l = l + 0.0;
+    u = u + 0.0;
+    const double2 b = make_double2(l, u);
+    P.bnd[0][j] = b;
+    P.bnd[1][j] = b;
+    if (domain_empty(is_int, l, u, P.feas_tol))
+      __hip_atomic_store(&P.ctrl->infeasible, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_unpack(Problem P, double* __restrict__ ulb,
+                                                   double* __restrict__ uub) {
+  const double2* src = P.bnd[P.ctrl->result_buf & 1];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)P.n; v += stride) {
+    const double2 b = src[P.perm[v]];
+    ulb[v] = b.x;
+    uub[v] = b.y;
+  }
+}
+
+// ---- persistent driver: every round inside one cooperative launch -------
+__global__ __launch_bounds__(kBlock) void k_persistent(Problem P, int max_rounds) {
+  Ctrl* C = P.ctrl;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gwave = blockIdx.x * kWavesPerBlock + wave;
+  const int nwaves = gridDim.x * kWavesPerBlock;
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nthreads = gridDim.x * blockDim.x;
+
+  if (!grid_barrier(P, kActStart, 0, max_rounds)) return;
+  if (__hip_atomic_load(&C->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+
+  for (int r = 1; r <= max_rounds; ++r) {
+    const int cb = (r - 1) & 1, nb = r & 1;
+    const double2* cur = P.bnd[cb];
+    double2* nxt = P.bnd[nb];
+    int32_t* list = P.list[nb];
+    uint32_t* count = &C->list_count[nb];
+    const uint32_t pcount = r == 1 ? 0u : ld_u32(&C->list_count[cb]);
+    fixup_and_check(P, P.list[cb], pcount, cur, nxt, tid, nthreads);
+    for (int c = gwave; c < P.n_chunks; c += nwaves) chunk_dispatch(P, c, cur, nxt, list, count);
+    if (P.n_segs) {
+      for (int s = gwave; s < P.n_segs; s += nwaves) seg_phase1(P, s, cur);
+      if (!grid_barrier(P, kActNone, r, max_rounds)) return;
+      for (int s = gwave; s < P.n_segs; s += nwaves) seg_phase2(P, s, cur, nxt, list, count);
+    }
+    if (!grid_barrier(P, kActEndRound, r, max_rounds)) return;
+    const uint32_t done = __hip_atomic_load(&C->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (done == 1) return;
+    if (done == 2) {
+      check_list(P, P.list[nb], ld_u32(&C->list_count[nb]), nxt, tid, nthreads);
+      grid_barrier(P, kActFinal, r, max_rounds);
+      return;
+    }
+  }
+}
+
+// ---- stream / host drivers: one launch per phase, early exit when done ----
+__global__ void k_start(Problem P, int max_rounds) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) start_status(P, max_rounds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_round(Problem P, int r) {
+  Ctrl* C = P.ctrl;
+  if (__hip_atomic_load(&C->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int item = blockIdx.x * kWavesPerBlock + wave;
+  const int cb = (r - 1) & 1, nb = r & 1;
+  const double2* cur = P.bnd[cb];
+  double2* nxt = P.bnd[nb];
+  const uint32_t pcount = r == 1 ? 0u : ld_u32(&C->list_count[cb]);
+  fixup_and_check(P, P.list[cb], pcount, cur, nxt, blockIdx.x * blockDim.x + threadIdx.x,
+                  gridDim.x * blockDim.x);
+  if (item < P.n_segs) seg_phase1(P, item, cur);
+  else if (item - P.n_segs < P.n_chunks)
+    chunk_dispatch(P, item - P.n_segs, cur, nxt, P.list[nb], &C->list_count[nb]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_round_long(Problem P, int r) {
+  Ctrl* C = P.ctrl;
+  if (__hip_atomic_load(&C->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int s = blockIdx.x * kWavesPerBlock + wave;
+  const int cb = (r - 1) & 1, nb = r & 1;
+  if (s < P.n_segs)
+    seg_phase2(P, s, P.bnd[cb], P.bnd[nb], P.list[nb], &C->list_count[nb]);
+}
+
+__global__ void k_end_round(Problem P, int r, int max_rounds) {
+  Ctrl* C = P.ctrl;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && C->done == 0) end_of_round(P, r, max_rounds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_final_check(Problem P) {
+  Ctrl* C = P.ctrl;
+  if (__hip_atomic_load(&C->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 2) return;
+  const int b = C->result_buf & 1;
+  check_list(P, P.list[b], ld_u32(&C->list_count[b]), P.bnd[b],
+             blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+__global__ void k_final_status(Problem P) {
+  Ctrl* C = P.ctrl;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && C->done == 2) after_final_check(P);
+}
+
+// ---------------------------------------------------------------------------
+// launchers (host side)
+// ---------------------------------------------------------------------------
+static int blocks_for(int64_t items, int per_block, int cap) {
+  int64_t b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+hipError_t launch_init(const Problem& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const Problem& P, const double* lb, const double* ub, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(blocks_for(P.n, kBlock, 4096)), dim3(kBlock), 0, s, P, lb, ub);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const Problem& P, double* lb, double* ub, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack, dim3(blocks_for(P.n, kBlock, 4096)), dim3(kBlock), 0, s, P, lb,
+                     ub);
+  return hipGetLastError();
+}
+
+hipError_t persistent_occupancy(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent, kBlock, 0);
+}
+
+hipError_t launch_persistent(const Problem& P, int max_rounds, int grid, hipStream_t s) {
+  Problem p = P;
+  void* args[] = {(void*)&p, (void*)&max_rounds};
+  return hipLaunchCooperativeKernel((const void*)k_persistent, dim3(grid), dim3(kBlock), args, 0,
+                                    s);
+}
+
+hipError_t launch_start(const Problem& P, int max_rounds, hipStream_t s) {
+  hipLaunchKernelGGL(k_start, dim3(1), dim3(64), 0, s, P, max_rounds);
+  return hipGetLastError();
+}
+
+hipError_t launch_round(const Problem& P, int r, int max_rounds, hipStream_t s) {
+  const int items = P.n_chunks + P.n_segs;
+  hipLaunchKernelGGL(k_round, dim3(blocks_for(items, kWavesPerBlock, 1 << 30)), dim3(kBlock), 0,
+                     s, P, r);
+  if (P.n_segs)
+    hipLaunchKernelGGL(k_round_long, dim3(blocks_for(P.n_segs, kWavesPerBlock, 1 << 30)),
+                       dim3(kBlock), 0, s, P, r);
+  hipLaunchKernelGGL(k_end_round, dim3(1), dim3(64), 0, s, P, r, max_rounds);
+  if (r == max_rounds) {
+    hipLaunchKernelGGL(k_final_check, dim3(blocks_for(2 * (int64_t)P.n, kBlock, 4096)),
+                       dim3(kBlock), 0, s, P);
+    hipLaunchKernelGGL(k_final_status, dim3(1), dim3(64), 0, s, P);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace prop

@@ -1,0 +1,19 @@
+// prop_launch.h -- host-callable launchers of the propagation kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "prop_layout.h"
+
+namespace prop {
+
+hipError_t launch_init(const Problem& P, hipStream_t s);
+hipError_t launch_pack(const Problem& P, const double* lb, const double* ub, hipStream_t s);
+hipError_t launch_unpack(const Problem& P, double* lb, double* ub, hipStream_t s);
+hipError_t persistent_occupancy(int* blocks_per_cu);
+hipError_t launch_persistent(const Problem& P, int max_rounds, int grid, hipStream_t s);
+hipError_t launch_start(const Problem& P, int max_rounds, hipStream_t s);
+// Queues one round (and, at r == max_rounds, the final domain check).
+hipError_t launch_round(const Problem& P, int r, int max_rounds, hipStream_t s);
+
+}  // namespace prop

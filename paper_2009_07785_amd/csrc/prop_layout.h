@@ -1,0 +1,109 @@
+// prop_layout.h -- device data layout shared by the host runtime and the
+// gfx950 kernels of the propagation library.
+//
+// Matrix layout ("chunks").  Rows are grouped by length.  A row of L <= 1024
+// entries gets K = 1, 2, 4, ..., 64 lanes of a 64-lane wave, the smallest K
+// with ceil(L / K) <= 16; a chunk is one wave's tile of 64 / K rows of the
+// same K.  Inside a chunk, entry p of row r sits at lane r * K + p % K and
+// step p / K, stored at offset step * 64 + lane: every step is one
+// contiguous 64-entry load of values (512 B) and columns (256 B).  W, the
+// chunk's number of steps, is the largest ceil(L / K) of its rows; shorter
+// rows are padded with zero coefficients.  Rows are sorted by length inside
+// each K class so the padding stays small.
+//
+// Rows with more than 1024 entries are "long": their entries stay in CSR
+// order, split into segments of 1024 (one wave, 16 steps), and a round
+// handles them in two phases (partial sums per segment, then candidates per
+// segment once all partial sums of the row exist).
+//
+// Variables are relabelled by decreasing column degree so the bounds of
+// the most used variables share cache lines.  Bounds live as (lb, ub)
+// pairs, one 16-byte load per entry; two such arrays alternate between
+// "start of round" (read only) and "next" (atomic max / min target).
+#pragma once
+
+#include <stdint.h>
+
+namespace prop {
+
+constexpr int kWave = 64;        // lanes per wavefront on gfx950
+constexpr int kMaxSteps = 16;    // steps per wave tile
+constexpr int kSegLen = kWave * kMaxSteps;  // entries per long-row segment
+constexpr int kBlock = 256;      // threads per workgroup (4 waves)
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// run outcome codes (match PROP_CONVERGED / PROP_INFEASIBLE / PROP_MAX_ROUNDS)
+constexpr int kConverged = 0;
+constexpr int kInfeasible = 1;
+constexpr int kMaxRounds = 2;
+
+// One chunk of short/medium rows.
+struct ChunkDesc {
+  int32_t off64;   // data offset in units of 64 entries
+  int32_t row0;    // first (internal) row of the chunk
+  int32_t meta;    // bits 0-2: log2 K, bits 8-15: W, bits 16-23: rows in chunk
+  int32_t pad;
+};
+
+// One segment of a long row.
+struct SegDesc {
+  int64_t off;     // data offset (entries) of the segment
+  int32_t row;     // internal row index (lhs / rhs)
+  int32_t len;     // entries in the segment (<= kSegLen)
+  int32_t first;   // index of the row's first segment
+  int32_t nseg;    // segments of the row
+  int32_t pad0, pad1;
+};
+
+// Per-segment partial sums of a long row, written in phase 1 of a round.
+struct SegPartial {
+  double min_hi, min_lo;   // double-double finite part of the min activity
+  double max_hi, max_lo;   // same for the max activity
+  double wmax;             // largest |a| * (u - l) among the segment's entries
+  int32_t min_inf, max_inf;
+  int32_t min_inf_own;     // entries of this segment with an infinite min term
+  int32_t max_inf_own;
+  int32_t pad0, pad1;
+};
+
+// Device control block of one problem.
+struct Ctrl {
+  uint32_t list_count[2];  // lengths of the two changed-variable lists
+  uint32_t infeasible;     // set when a checked domain is empty
+  uint32_t invalid;        // set when a bound fails validation
+  int32_t status;
+  int32_t rounds;
+  uint32_t done;           // loop finished
+  uint32_t result_buf;     // which bound array holds the result
+  int32_t round;           // next round to run (stream / host drivers)
+  uint32_t bar_count;      // grid barrier arrival counter
+  uint32_t bar_gen;        // grid barrier generation
+  uint32_t abort;          // barrier wait gave up (device timeout)
+  uint32_t pad[4];
+};
+
+// Everything a kernel needs, passed by value.
+struct Problem {
+  // matrix
+  const double* vals;
+  const int32_t* cols;
+  const ChunkDesc* chunks;
+  const SegDesc* segs;
+  SegPartial* partials;
+  const double* lhs;        // internal row order
+  const double* rhs;
+  const uint8_t* vtype;     // internal variable order
+  const int32_t* perm;      // perm[user var] = internal var
+  int32_t n_chunks;
+  int32_t n_segs;
+  int32_t n;
+  int32_t instance_infeasible;
+  // state
+  double2* bnd[2];
+  int32_t* list[2];         // capacity 2 n each
+  Ctrl* ctrl;
+  // parameters
+  double eps_int, cont_rel_tol, feas_tol;
+};
+
+}  // namespace prop

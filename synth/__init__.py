@@ -8,6 +8,7 @@ from here.
 from .instances import (  # noqa: F401
     BASE_SEED,
     Instance,
+    cached,
     config0,
     config1,
     config2,
@@ -16,6 +17,8 @@ from .instances import (  # noqa: F401
     config4_pool,
     config4_requests,
     from_rows,
+    layout_mix,
+    request_bounds,
     node_bounds,
     random_small,
 )

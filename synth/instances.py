@@ -372,3 +372,77 @@ def random_small(seed: int, m: int, n: int, max_len: int = 6, int_frac: float = 
     lhs[one & dl] = -INF
     rhs[one & ~dl] = INF
     return Instance(f"small[{seed}]", m, n, row_ptr, col, vals, lhs, rhs, vartype, lb, ub, x0)
+
+
+def layout_mix(seed: int = 0, copies: int = 3) -> Instance:
+    """Rows of every length class a wave tile distinguishes (1 .. 1024 entries,
+    ragged within each class) plus rows longer than 1024 entries, some of them
+    built so that they do tighten bounds: a cardinality row forcing 3,000
+    binaries to 0, and a row whose only infinite contribution belongs to one
+    free variable."""
+    rng = _rng(BASE_SEED + 700_000 + seed)
+    n = 20_000
+    vartype, lb, ub, x0 = _variables(rng, n, 0.4, 0.3, 0.1)
+    lens = [1, 2, 3, 5, 8, 15, 16, 17, 24, 31, 32, 33, 47, 63, 64, 65, 100, 127, 128, 129,
+            200, 255, 256, 257, 400, 511, 512, 513, 700, 1000, 1023, 1024, 1025, 1500, 2047,
+            2048, 2049, 3000, 5000]
+    lengths = np.array(lens * copies + list(rng.integers(1, 40, size=400)), dtype=np.int64)
+    lengths = rng.permutation(lengths)
+    row_ptr, col = _distinct_columns(rng, lengths, n - 5001)
+    vals = _coeffs_mixed(rng, col.size)
+    lhs, rhs = _sides(rng, _row_dot(row_ptr, col, vals, x0))
+    # special long rows over variables no other row touches
+    base = n - 5001
+    card = np.arange(base, base + 3000)
+    vartype[card] = 1
+    lb[card], ub[card] = 0.0, 1.0
+    x0[card] = 0.0
+    grp = np.arange(base + 3000, base + 5000)
+    vartype[grp] = 1
+    lb[grp], ub[grp] = 0.0, 1.0
+    free = n - 1
+    vartype[free] = 0
+    lb[free], ub[free] = -INF, INF
+    x0[free] = 10.0
+    extra_rows = [(card, np.ones(card.size), -INF, 0.0),
+                  (np.concatenate([grp, [free]]), np.ones(grp.size + 1), 5.0, INF)]
+    rp = list(row_ptr)
+    cols = [col]
+    vs = [vals]
+    lh, rh = list(lhs), list(rhs)
+    for c, v, lo_, hi_ in extra_rows:
+        cols.append(c.astype(np.int32))
+        vs.append(v)
+        rp.append(rp[-1] + c.size)
+        lh.append(lo_)
+        rh.append(hi_)
+    return Instance(f"layout_mix[{seed}]", len(rp) - 1, n, np.array(rp, dtype=np.int64),
+                    np.concatenate(cols).astype(np.int32), np.concatenate(vs),
+                    np.array(lh), np.array(rh), vartype, lb, ub, x0)
+
+
+# --------------------------------------------------------------------------
+# optional on-disk cache (directory from PROP_SYNTH_CACHE), so one process can
+# reuse what an earlier one generated
+# --------------------------------------------------------------------------
+_FIELDS = ("row_ptr", "col_idx", "vals", "lhs", "rhs", "vartype", "lb", "ub", "x0")
+
+
+def cached(key: str, fn, *args, **kw) -> Instance:
+    import os
+
+    d = os.environ.get("PROP_SYNTH_CACHE")
+    if not d:
+        return fn(*args, **kw)
+    path = os.path.join(d, key + ".npz")
+    if os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        arrs = {f: z[f] for f in _FIELDS}
+        return Instance(str(z["name"]), int(z["m"]), int(z["n"]), x0=arrs.pop("x0"), **arrs)
+    inst = fn(*args, **kw)
+    os.makedirs(d, exist_ok=True)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, name=np.array(inst.name), m=np.array(inst.m), n=np.array(inst.n),
+             **{f: getattr(inst, f) for f in _FIELDS})
+    os.replace(tmp, path)
+    return inst

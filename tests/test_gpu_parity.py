@@ -1,0 +1,249 @@
+"""GPU parity: the HIP library (through its C ABI) against the oracle.
+
+Bar: status and rounds identical; bounds bitwise identical (activities are
+exactly rounded on both sides and every other step is the same IEEE
+operation, so no tolerance is needed; the comparison helper still reports
+the largest deviation for diagnosis).  Every run goes through all three
+round-loop drivers.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle_pins as pins
+import synth
+
+pytestmark = pytest.mark.gpu
+
+LOOPS = ("persistent", "stream", "host")
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lib(torch_cuda):
+    from paper_2009_07785_amd import binding
+
+    return binding
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def assert_same(tag, got, ref):
+    """Bitwise equality of status, rounds and (unless infeasible) bounds."""
+    res, lb, ub = got
+    assert (res.status, res.rounds) == (ref.status, ref.rounds), (
+        f"{tag}: status/rounds {res.status}/{res.rounds} vs oracle {ref.status}/{ref.rounds}")
+    if ref.status == oracle.INFEASIBLE:
+        return
+    for name, g, r in (("lb", lb, ref.lb), ("ub", ub, ref.ub)):
+        same = (g == r) | (np.isnan(g) & np.isnan(r))
+        if not same.all():
+            bad = np.nonzero(~same)[0]
+            fin = np.isfinite(g[bad]) & np.isfinite(r[bad])
+            dev = np.max(np.abs(g[bad][fin] - r[bad][fin])) if fin.any() else math.inf
+            raise AssertionError(f"{tag}: {name} differs at {bad.size} vars (first {bad[:5]}, "
+                                 f"max |diff| {dev})")
+
+
+def gpu_run(lib, inst, lb, ub, max_rounds, loop="persistent", params=None):
+    kw = {}
+    if params is not None:
+        kw = dict(eps_int=params.eps_int, cont_rel_tol=params.cont_rel_tol,
+                  feas_tol=params.feas_tol)
+    with lib.Problem.from_instance(inst, **kw) as p:
+        p.set_loop(loop)
+        return p.run(lb, ub, max_rounds)
+
+
+def check_against_oracle(lib, inst, max_rounds=100, params=None, loops=LOOPS, lb=None, ub=None):
+    lb = inst.lb if lb is None else lb
+    ub = inst.ub if ub is None else ub
+    ref = oracle.run(inst, lb, ub, max_rounds, params)
+    for loop in loops:
+        say(f"  {inst.name} loop={loop} max_rounds={max_rounds}")
+        assert_same(f"{inst.name}/{loop}", gpu_run(lib, inst, lb, ub, max_rounds, loop, params), ref)
+    return ref
+
+
+def test_closed_forms(lib):
+    for c in pins.load_closed_forms():
+        inst = pins.case_instance(c)
+        check_against_oracle(lib, inst, c["max_rounds"], pins.case_params(c))
+
+
+def test_config0(lib):
+    ref = check_against_oracle(lib, synth.config0())
+    assert ref.status == oracle.CONVERGED and ref.rounds > 5
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_layout_mix(lib, seed):
+    """Every lanes-per-row class, ragged tails and long rows that tighten."""
+    ref = check_against_oracle(lib, synth.layout_mix(seed))
+    assert ref.status == oracle.CONVERGED
+
+
+def test_random_small(lib):
+    for s in range(40):
+        inst = synth.random_small(s, m=int(3 + s % 9), n=int(3 + s % 7), box=6,
+                                  int_frac=[1.0, 0.5, 0.0][s % 3], inf_frac=0.2 * (s % 2))
+        check_against_oracle(lib, inst, loops=("persistent",) if s % 4 else LOOPS)
+
+
+def test_cascade_round_counts(lib):
+    for m, want in ((99, (oracle.CONVERGED, 100)), (100, (oracle.MAX_ROUNDS, 100))):
+        inst = pins.cascade_instance(m)
+        ref = check_against_oracle(lib, inst)
+        assert (ref.status, ref.rounds) == want
+
+
+def test_resume_and_idempotence(lib):
+    inst = synth.config0(1)
+    res, lb, ub = gpu_run(lib, inst, inst.lb, inst.ub, 100)
+    assert res.status == oracle.CONVERGED
+    k = res.rounds // 2
+    r1, lb1, ub1 = gpu_run(lib, inst, inst.lb, inst.ub, k)
+    r2, lb2, ub2 = gpu_run(lib, inst, lb1, ub1, 100)
+    assert r1.status == oracle.MAX_ROUNDS and r1.rounds + r2.rounds == res.rounds
+    assert np.array_equal(lb2, lb) and np.array_equal(ub2, ub)
+    r3, lb3, ub3 = gpu_run(lib, inst, lb, ub, 100)
+    assert (r3.status, r3.rounds) == (oracle.CONVERGED, 1)
+    assert np.array_equal(lb3, lb) and np.array_equal(ub3, ub)
+
+
+def test_config1_suite(lib):
+    for k in (1, 50):
+        inst = synth.config1(k)
+        ref = check_against_oracle(lib, inst, loops=("persistent", "stream"))
+        if k % 50 == 0:
+            assert ref.status == oracle.INFEASIBLE
+        else:
+            assert ref.status == oracle.CONVERGED
+
+
+def test_determinism_device_path(lib, torch_cuda):
+    torch = torch_cuda
+    inst = synth.config1(1)
+    outs = []
+    with lib.Problem.from_instance(inst) as p:
+        for _ in range(3):
+            d_lb = torch.tensor(inst.lb, dtype=torch.float64, device="cuda")
+            d_ub = torch.tensor(inst.ub, dtype=torch.float64, device="cuda")
+            res = p.run_device(d_lb, d_ub, 100)
+            outs.append((res.status, res.rounds, d_lb.cpu().numpy(), d_ub.cpu().numpy()))
+    for o in outs[1:]:
+        assert o[:2] == outs[0][:2]
+        assert np.array_equal(o[2], outs[0][2]) and np.array_equal(o[3], outs[0][3])
+
+
+def test_edge_cases(lib):
+    # no rows: one change-free round
+    inst = synth.from_rows([], [], [], [0.0, -1.0], [1.0, 2.0], [1, 0], n=2)
+    check_against_oracle(lib, inst)
+    # only empty rows, compatible with 0, and one incompatible
+    inst = synth.from_rows([[], []], [-1.0, -np.inf], [0.0, 3.0], [0.0], [5.0], [1], n=1)
+    check_against_oracle(lib, inst)
+    inst = synth.from_rows([[], []], [0.5, -np.inf], [1.0, 3.0], [0.0], [5.0], [1], n=1)
+    check_against_oracle(lib, inst)
+    # zero round limit, fractional integer bounds
+    inst = synth.from_rows([[(0, 2.0)]], [-np.inf], [5.0], [0.3], [9.7], [1], n=1)
+    check_against_oracle(lib, inst, max_rounds=0)
+    check_against_oracle(lib, inst, max_rounds=1)
+    # explicit zeros and a variable in no row
+    inst = synth.from_rows([[(0, 0.0), (1, 3.0)], [(1, 1.0), (2, -2.0)]], [-np.inf, 0.0],
+                           [4.0, np.inf], [-np.inf, 0.0, -5.0, 7.0], [np.inf, 10.0, 5.0, 9.0],
+                           [0, 1, 0, 1], n=4)
+    check_against_oracle(lib, inst)
+
+
+def test_invalid_bounds_rejected(lib):
+    inst = synth.config0()
+    with lib.Problem.from_instance(inst) as p:
+        for bad in (np.nan, np.inf):
+            lb = inst.lb.copy()
+            lb[5] = bad
+            with pytest.raises(lib.PropError) as e:
+                p.run(lb, inst.ub, 10)
+            assert e.value.code == lib.EINVAL
+        ub = inst.ub.copy()
+        ub[3] = -np.inf
+        with pytest.raises(lib.PropError):
+            p.run(inst.lb, ub, 10)
+        # the problem stays usable after a rejected call
+        res, _, _ = p.run(inst.lb, inst.ub, 100)
+        assert res.status == oracle.CONVERGED
+
+
+# ---------------------------------------------------------------------------
+# full-size config 2 (5M x 2M, ~52M nonzeros): round transitions checked one
+# by one against the oracle (a round is a function of the bounds it starts
+# from), plus properties of the final state
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def big(lib):
+    say("generating config2 (5,000,000 x 2,000,000)")
+    inst = synth.cached("config2", synth.config2)
+    say(f"config2: nnz={inst.nnz}; creating the device problem")
+    p = lib.Problem.from_instance(inst)
+    yield inst, p
+    p.close()
+
+
+def _normalized_root(inst):
+    lb = np.where(inst.vartype == 1, np.ceil(inst.lb - 1e-6), inst.lb) + 0.0
+    ub = np.where(inst.vartype == 1, np.floor(inst.ub + 1e-6), inst.ub) + 0.0
+    return lb, ub
+
+
+def test_config2_round1_lockstep(lib, big):
+    inst, p = big
+    res, lb1, ub1 = p.run(inst.lb, inst.ub, 1)
+    assert (res.status, res.rounds) == (oracle.MAX_ROUNDS, 1)
+    say("oracle round 1 on config2")
+    L0, U0 = _normalized_root(inst)
+    Ln, Un, ch, inf, _ = oracle.round_(inst, L0, U0)
+    assert ch and not inf
+    assert np.array_equal(lb1, Ln) and np.array_equal(ub1, Un)
+
+
+def test_config2_full_run_lockstep(lib, big):
+    inst, p = big
+    res, lb, ub = p.run(inst.lb, inst.ub, 100)
+    say(f"config2 GPU: status {res.status} rounds {res.rounds}")
+    assert res.status == oracle.CONVERGED
+    assert res.rounds >= 2
+    # the last round must reproduce the final state and report no change
+    r_prev, lbp, ubp = p.run(inst.lb, inst.ub, res.rounds - 1)
+    assert r_prev.status == oracle.MAX_ROUNDS
+    Ln, Un, ch, inf, _ = oracle.round_(inst, lbp, ubp)
+    assert not ch and not inf
+    assert np.array_equal(lbp, lb) and np.array_equal(ubp, ub)
+    assert np.array_equal(Ln, lb) and np.array_equal(Un, ub)
+    # x0 stays inside
+    tol = 1e-6 * np.maximum(1.0, np.abs(inst.x0))
+    assert np.all(lb - tol <= inst.x0) and np.all(inst.x0 <= ub + tol)
+
+
+def test_config2_round2_lockstep(lib, big):
+    inst, p = big
+    _, lb1, ub1 = p.run(inst.lb, inst.ub, 1)
+    res, lb2, ub2 = p.run(inst.lb, inst.ub, 2)
+    say("oracle round 2 on config2")
+    Ln, Un, ch, inf, _ = oracle.round_(inst, lb1, ub1)
+    assert np.array_equal(lb2, Ln) and np.array_equal(ub2, Un)
+    assert (res.status == oracle.MAX_ROUNDS) == ch
