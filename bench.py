@@ -1,0 +1,264 @@
+"""Benchmark: synchronous domain propagation on the large single-instance
+workload (5,000,000 rows x 2,000,000 variables, ~52M nonzeros, power-law
+row lengths and column degrees).
+
+A step is one full propagation run -- every round until no bound changes --
+from the root bounds, with the matrix and the bounds already in HBM.  The
+printed JSON line carries:
+  value      nonzeros processed per second, summed over rounds
+             (nnz * rounds * steps / timed seconds);
+  roofline   algorithmic bytes of the round-loop launch (rounds x
+             (12 nnz + 20 m + 33 n + 4)) over its average duration, measured
+             with HIP events on the launch stream, against 8 TB/s HBM;
+  cpu_baseline  the CPU oracle (single thread) on a bounded sample: one
+             synchronous round over the full instance.
+Progress goes to stderr; stdout gets the one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "nnz processed/s per round & HBM GB/s; batched B&B nodes/s vs one-at-a-time"
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(inst, skip: bool):
+    """One synchronous oracle round over the whole instance, single thread."""
+    if skip:
+        return None
+    import numpy as np
+
+    import oracle
+
+    lb = np.where(inst.vartype == 1, np.ceil(inst.lb - 1e-6), inst.lb) + 0.0
+    ub = np.where(inst.vartype == 1, np.floor(inst.ub + 1e-6), inst.ub) + 0.0
+    try:
+        os.sched_setaffinity(0, {sorted(os.sched_getaffinity(0))[0]})
+    except (AttributeError, OSError):
+        pass
+    log("oracle: one round over the full instance (single thread)")
+    t0 = time.perf_counter()
+    oracle.round_(inst, lb, ub)
+    dt = time.perf_counter() - t0
+    return {
+        "value": inst.nnz / dt,
+        "unit": "nnz/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"1 synchronous round of the full {inst.m}x{inst.n} instance "
+                  f"({inst.nnz} nnz) from the root bounds: {dt:.2f} s",
+        "host_cpu": host_cpu_model(),
+        "host_nproc": os.cpu_count(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--max-rounds", type=int, default=100)
+    ap.add_argument("--loop", default="stream", choices=["persistent", "stream", "host"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-loop-compare", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_config2.json"),
+                    help="HBM traffic per launch measured with rocprofv3 counters (JSON)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes 5 times (the reference "
+                         "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        n = args.copy_calibration // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}))
+        return
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2009_07785_amd import Problem
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    log("generating the 5,000,000 x 2,000,000 power-law instance")
+    t0 = time.perf_counter()
+    inst = synth.cached("config2", synth.config2)
+    log(f"generated: nnz={inst.nnz} in {time.perf_counter() - t0:.1f} s; building device problem")
+    t0 = time.perf_counter()
+    prob = Problem.from_instance(inst)
+    info = prob.info()
+    log(f"device problem ready in {time.perf_counter() - t0:.1f} s: {info}")
+    prob.set_loop(args.loop)
+    prob.set_kernel_timing(args.loop != "persistent")
+
+    root_lb = torch.tensor(inst.lb, dtype=torch.float64, device=dev)
+    root_ub = torch.tensor(inst.ub, dtype=torch.float64, device=dev)
+    d_lb = torch.empty_like(root_lb)
+    d_ub = torch.empty_like(root_ub)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        d_lb.copy_(root_lb)
+        d_ub.copy_(root_ub)
+        return prob.run_device(d_lb, d_ub, args.max_rounds, stream)
+
+    for i in range(args.warmup):
+        r = step()
+        log(f"warmup {i + 1}/{args.warmup}: {r.status_name} after {r.rounds} rounds, "
+            f"loop {prob.last_timing()[0]:.3f} ms")
+
+    loop_ms, total_ms, kern_ms, kern_n, rounds = [], [], [], [], set()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = step()
+        lm, tm = prob.last_timing()
+        km, kn = prob.last_kernel_timing()
+        loop_ms.append(lm)
+        total_ms.append(tm)
+        kern_ms.append(km)
+        kern_n.append(kn)
+        rounds.add((r.status, r.rounds))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {elapsed:.3f} s; status/rounds {sorted(rounds)}")
+    assert len(rounds) == 1, "runs disagree"
+    status, nrounds = rounds.pop()
+
+    nnz = info["nnz"]
+    alg_round = info["alg_bytes_round"]
+    value = nnz * nrounds * args.steps / elapsed
+    loop_avg_ms = float(np.mean(loop_ms))
+    loop_GBps = alg_round * nrounds / (loop_avg_ms * 1e-3) / 1e9
+    # dominant kernel: the per-round matrix kernel; per launch it reads the
+    # matrix (12 B per nonzero), the row sides and row pointers (20 B per
+    # row) and every variable's bounds and type once (17 B per variable);
+    # the commit kernel accounts for the remaining 16 B per variable
+    m_, n_ = info["m"], info["n"]
+    kern_bytes = 12 * nnz + 20 * m_ + 17 * n_
+    if sum(kern_n):
+        kern_avg_ms = float(np.sum(kern_ms) / np.sum(kern_n))
+        achieved = kern_bytes / (kern_avg_ms * 1e-3) / 1e9
+        kern_name = "k_round (per-round matrix kernel: activities, candidates, atomics)"
+    else:
+        kern_avg_ms = loop_avg_ms
+        achieved = loop_GBps
+        kern_name = "k_persistent (all rounds of one run in one cooperative launch)"
+
+    traffic = None
+    if os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_sha") == kernel_source_sha():
+            traffic = tr.get("bytes_per_launch")
+
+    loops = {}
+    if not args.no_loop_compare:
+        for mode in ("persistent", "stream", "host"):
+            prob.set_loop(mode)
+            ts = []
+            for _ in range(3):
+                rr = step()
+                ts.append(prob.last_timing()[0])
+            loops[mode] = {"loop_ms": float(np.median(ts)), "rounds": rr.rounds}
+        prob.set_loop(args.loop)
+        log(f"round-loop drivers: {loops}")
+
+    base = cpu_baseline(inst, args.no_cpu_baseline)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "config2: single instance, 5,000,000 x 2,000,000, power-law rows "
+                        "(pdf exponent 2.2, cap 200,000) and column degrees",
+            "m": inst.m, "n": inst.n, "nnz": nnz, "max_rounds": args.max_rounds,
+            "loop": args.loop, "parallelism": "single GPU",
+        },
+        "status": ["CONVERGED", "INFEASIBLE", "MAX_ROUNDS"][status],
+        "rounds": nrounds,
+        "loop_ms": loop_avg_ms,
+        "pack_run_unpack_ms": float(np.mean(total_ms)),
+        "alg_bytes_per_round": alg_round,
+        "loop_alg_GBps": loop_GBps,
+        "loop_frac": loop_GBps / HBM_PEAK_GBS,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kern_name,
+            "kernel_avg_ms": kern_avg_ms,
+            "alg_bytes_per_launch": kern_bytes if sum(kern_n) else alg_round * nrounds,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+        "round_loops": loops,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out), flush=True)
+    prob.close()
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in ("prop_kernels.hip", "prop_layout.h"):
+        with open(os.path.join(ROOT, "paper_2009_07785_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -71,7 +71,8 @@ extern "C" {
 
 /* Round-loop drivers (prop_set_loop).  All give identical results. */
 #define PROP_LOOP_PERSISTENT 0 /* one cooperative launch, grid barriers between phases */
-#define PROP_LOOP_STREAM 1     /* per-round kernels queued without host sync; device flag */
+#define PROP_LOOP_STREAM 1     /* default: per-round kernels queued in batches; the host
+                                  reads the device's done flag one batch behind */
 #define PROP_LOOP_HOST 2       /* per-round kernels, host reads the flag every round */
 
 typedef struct prop_problem prop_problem; /* opaque */
@@ -143,6 +144,14 @@ int prop_get_info(const prop_problem* p, prop_info* out);
  * the launch stream around the loop kernels, pack/unpack excluded), and the
  * same with the bound pack and unpack kernels included. */
 int prop_last_timing(const prop_problem* p, double* loop_ms, double* total_ms);
+
+/* With enable != 0, later runs of the stream and host drivers record HIP
+ * events around every launch of the per-round matrix kernel (the dominant
+ * kernel) on the launch stream; prop_last_kernel_timing then returns the
+ * summed duration in milliseconds and the number of launches of the last
+ * run.  Off by default; the events cost a few microseconds per round. */
+int prop_set_kernel_timing(prop_problem* p, int32_t enable);
+int prop_last_kernel_timing(const prop_problem* p, double* ms, int32_t* launches);
 
 /* Releases the problem (NULL is allowed). */
 void prop_destroy(prop_problem* p);

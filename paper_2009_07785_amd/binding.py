@@ -24,7 +24,8 @@ LOOP_NAMES = {"persistent": LOOP_PERSISTENT, "stream": LOOP_STREAM, "host": LOOP
 
 # every function the header declares
 EXPORTED = ("prop_create", "prop_run", "prop_run_device", "prop_set_loop", "prop_get_info",
-            "prop_last_timing", "prop_destroy", "prop_last_error")
+            "prop_last_timing", "prop_set_kernel_timing", "prop_last_kernel_timing",
+            "prop_destroy", "prop_last_error")
 
 
 class PropError(RuntimeError):
@@ -84,6 +85,11 @@ def _load():
     lib.prop_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
     lib.prop_last_timing.restype = ctypes.c_int
+    lib.prop_set_kernel_timing.argtypes = [P, i32]
+    lib.prop_set_kernel_timing.restype = ctypes.c_int
+    lib.prop_last_kernel_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_int32)]
+    lib.prop_last_kernel_timing.restype = ctypes.c_int
     lib.prop_destroy.argtypes = [P]
     lib.prop_destroy.restype = None
     lib.prop_last_error.argtypes = []
@@ -202,6 +208,15 @@ class Problem:
         inf = _Info()
         _check(lib.prop_get_info(self._h, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def set_kernel_timing(self, enable: bool):
+        _check(lib.prop_set_kernel_timing(self._h, 1 if enable else 0))
+
+    def last_kernel_timing(self):
+        """(summed ms, launches) of the per-round matrix kernel in the last run."""
+        ms, n = ctypes.c_double(), ctypes.c_int32()
+        _check(lib.prop_last_kernel_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def last_timing(self):
         """(loop_ms, total_ms) of the last run, from HIP events on its stream."""

@@ -13,7 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/prop.h"
+#include "prop.h"
 #include "prop_launch.h"
 #include "prop_layout.h"
 
@@ -65,7 +65,7 @@ struct prop_problem {
   int64_t nnz = 0, nnz_stored = 0;
   int32_t n_long_rows = 0;
   int grid = 0;
-  int loop_mode = PROP_LOOP_PERSISTENT;
+  int loop_mode = PROP_LOOP_STREAM;
   bool instance_infeasible = false;
   prop_params params{1e-6, 1e-6, 1e-6};
   Problem P{};
@@ -75,7 +75,14 @@ struct prop_problem {
   double* d_stage_lb = nullptr;  // staging for prop_run (host arrays)
   double* d_stage_ub = nullptr;
   Ctrl* h_ctrl = nullptr;        // pinned host copy of the control block
+  uint32_t* h_done = nullptr;    // pinned done flags of the stream driver's batches
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev_batch[2] = {nullptr, nullptr};
+  int batch_rounds = 4;          // rounds queued per batch by the stream driver
+  bool kernel_timing = false;    // events around every round-kernel launch
+  std::vector<hipEvent_t> kev;   // kev[2r], kev[2r+1] bracket round r's matrix kernel
+  int kev_used = 0;              // rounds bracketed in the last run
+  double last_kernel_ms = 0.0;
   float last_loop_ms = 0.f, last_total_ms = 0.f;
 };
 
@@ -107,7 +114,12 @@ void release(prop_problem* p) {
   for (void* a : p->allocs) hipFree(a);
   p->allocs.clear();
   if (p->h_ctrl) hipHostFree(p->h_ctrl);
+  if (p->h_done) hipHostFree(p->h_done);
   for (auto& e : p->ev)
+    if (e) hipEventDestroy(e);
+  for (auto& e : p->ev_batch)
+    if (e) hipEventDestroy(e);
+  for (auto& e : p->kev)
     if (e) hipEventDestroy(e);
   delete p;
 }
@@ -193,6 +205,9 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   for (int32_t q = 0; q < n; ++q) perm[order[q]] = q;
   std::vector<uint8_t> vtype(n);
   for (int32_t j = 0; j < n; ++j) vtype[perm[j]] = vartype[j];
+  auto col_word = [&](int32_t j) {
+    return (int32_t)((uint32_t)perm[j] | (vartype[j] ? 0x80000000u : 0u));
+  };
 
   // rows by lanes-per-row class; long rows apart
   std::vector<std::vector<int32_t>> cls(7);
@@ -262,7 +277,7 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
         const int64_t step = pos / K;
         const int64_t idx = off + step * kWave + lane;
         h_vals[idx] = A->vals[k];
-        h_cols[idx] = perm[A->col_idx[k]];
+        h_cols[idx] = col_word(A->col_idx[k]);
         ++pos;
       }
     }
@@ -290,7 +305,7 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
     for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k) {
       if (A->vals[k] == 0.0) continue;
       h_vals[off + pos] = A->vals[k];
-      h_cols[off + pos] = perm[A->col_idx[k]];
+      h_cols[off + pos] = col_word(A->col_idx[k]);
       ++pos;
     }
     off += (len[i] + kWave - 1) / kWave * kWave;
@@ -313,7 +328,7 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
       return fail(PROP_EINVAL, "internal layout check failed (segment)");
   }
   for (int64_t q = 0; q < stored; ++q)
-    if (h_cols[q] < 0 || (n > 0 && h_cols[q] >= n) || (n == 0 && stored > 0))
+    if ((n > 0 && (h_cols[q] & kColMask) >= n) || (n == 0 && stored > 0))
       return fail(PROP_EINVAL, "internal layout check failed (column)");
   if ((int64_t)h_lhs.size() != n_rows_internal)
     return fail(PROP_EINVAL, "internal layout check failed (rows)");
@@ -340,9 +355,6 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   double2 *b0, *b1;
   if ((rc = dev_alloc(p, &b0, (size_t)n))) return rc;
   if ((rc = dev_alloc(p, &b1, (size_t)n))) return rc;
-  int32_t *l0, *l1;
-  if ((rc = dev_alloc(p, &l0, 2 * (size_t)n))) return rc;
-  if ((rc = dev_alloc(p, &l1, 2 * (size_t)n))) return rc;
   Ctrl* d_ctrl;
   if ((rc = dev_alloc(p, &d_ctrl, 1))) return rc;
   HIP_TRY(hipMemset(d_ctrl, 0, sizeof(Ctrl)));
@@ -364,8 +376,6 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   P.instance_infeasible = p->instance_infeasible ? 1 : 0;
   P.bnd[0] = b0;
   P.bnd[1] = b1;
-  P.list[0] = l0;
-  P.list[1] = l1;
   P.ctrl = d_ctrl;
   P.eps_int = p->params.eps_int;
   P.cont_rel_tol = p->params.cont_rel_tol;
@@ -373,8 +383,27 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   return PROP_OK;
 }
 
+// Queues round r, bracketing its matrix kernel with events when asked to.
+int queue_round(prop_problem* p, int r, int32_t max_rounds, hipStream_t s) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (p->kernel_timing) {
+    const size_t need = 2 * (size_t)r;
+    while (p->kev.size() < need) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      p->kev.push_back(e);
+    }
+    e0 = p->kev[2 * (r - 1)];
+    e1 = p->kev[2 * (r - 1) + 1];
+    p->kev_used = r;
+  }
+  HIP_TRY(launch_round(p->P, r, max_rounds, s, e0, e1));
+  return PROP_OK;
+}
+
 int run_loop(prop_problem* p, int32_t max_rounds, hipStream_t s) {
   const Problem& P = p->P;
+  p->kev_used = 0;
   hipError_t e;
   switch (p->loop_mode) {
     case PROP_LOOP_PERSISTENT:
@@ -382,14 +411,39 @@ int run_loop(prop_problem* p, int32_t max_rounds, hipStream_t s) {
       if (e != hipSuccess)
         return fail(PROP_EDEVICE, "cooperative launch failed: %s", hipGetErrorString(e));
       return PROP_OK;
-    case PROP_LOOP_STREAM:
+    case PROP_LOOP_STREAM: {
+      // Rounds are queued in batches; after each batch the device's done
+      // flag is copied to pinned memory behind an event.  The host waits for
+      // batch i only after batch i+1 is queued, so the GPU never idles on
+      // the host, and at most two batches of early-exit launches follow
+      // convergence.
       HIP_TRY(launch_start(P, max_rounds, s));
-      for (int r = 1; r <= max_rounds; ++r) HIP_TRY(launch_round(P, r, max_rounds, s));
+      int slot = 0;
+      bool pending[2] = {false, false};
+      for (int r = 1; r <= max_rounds;) {
+        const int last = std::min(max_rounds, r + p->batch_rounds - 1);
+        for (; r <= last; ++r) {
+          const int rc = queue_round(p, r, max_rounds, s);
+          if (rc) return rc;
+        }
+        HIP_TRY(hipMemcpyAsync(&p->h_done[slot], &P.ctrl->done, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(p->ev_batch[slot], s));
+        pending[slot] = true;
+        slot ^= 1;
+        if (pending[slot]) {
+          HIP_TRY(hipEventSynchronize(p->ev_batch[slot]));
+          pending[slot] = false;
+          if (p->h_done[slot] == 1) break;
+        }
+      }
       return PROP_OK;
+    }
     default:
       HIP_TRY(launch_start(P, max_rounds, s));
       for (int r = 1; r <= max_rounds; ++r) {
-        HIP_TRY(launch_round(P, r, max_rounds, s));
+        const int rc = queue_round(p, r, max_rounds, s);
+        if (rc) return rc;
         HIP_TRY(hipMemcpyAsync(&p->h_ctrl->done, &P.ctrl->done, sizeof(uint32_t),
                                hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -436,12 +490,18 @@ int prop_create(const prop_csr* A, const double* lhs, const double* rhs, const u
   }
   p->grid = cus * per_cu;
   if (!coop) p->loop_mode = PROP_LOOP_STREAM;
-  if (hipHostMalloc((void**)&p->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&p->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&p->h_done, 2 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
     release(p);
     return fail(PROP_ENOMEM, "pinned host allocation failed");
   }
   for (auto& ev : p->ev)
     if (hipEventCreate(&ev) != hipSuccess) {
+      release(p);
+      return fail(PROP_EDEVICE, "hipEventCreate failed");
+    }
+  for (auto& ev : p->ev_batch)
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
       release(p);
       return fail(PROP_EDEVICE, "hipEventCreate failed");
     }
@@ -474,6 +534,14 @@ int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rou
   HIP_TRY(hipStreamSynchronize(s));
   hipEventElapsedTime(&p->last_loop_ms, p->ev[1], p->ev[2]);
   hipEventElapsedTime(&p->last_total_ms, p->ev[0], p->ev[3]);
+  p->last_kernel_ms = 0.0;
+  // launches queued after the last executed round exit at once; leave them out
+  if (p->kev_used > p->h_ctrl->rounds) p->kev_used = p->h_ctrl->rounds;
+  for (int r = 0; r < p->kev_used; ++r) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->kev[2 * r], p->kev[2 * r + 1]) == hipSuccess)
+      p->last_kernel_ms += ms;
+  }
   const Ctrl& C = *p->h_ctrl;
   if (C.invalid) return fail(PROP_EINVAL, "a bound is NaN, +inf as lower, -inf as upper, or beyond 2^200");
   if (C.abort) return fail(PROP_EDEVICE, "grid barrier wait timed out");
@@ -529,6 +597,19 @@ int prop_last_timing(const prop_problem* p, double* loop_ms, double* total_ms) {
   if (!p) return fail(PROP_EINVAL, "NULL problem");
   if (loop_ms) *loop_ms = p->last_loop_ms;
   if (total_ms) *total_ms = p->last_total_ms;
+  return PROP_OK;
+}
+
+int prop_set_kernel_timing(prop_problem* p, int32_t enable) {
+  if (!p) return fail(PROP_EINVAL, "NULL problem");
+  p->kernel_timing = enable != 0;
+  return PROP_OK;
+}
+
+int prop_last_kernel_timing(const prop_problem* p, double* ms, int32_t* launches) {
+  if (!p) return fail(PROP_EINVAL, "NULL problem");
+  if (ms) *ms = p->last_kernel_ms;
+  if (launches) *launches = p->kev_used;
   return PROP_OK;
 }
 

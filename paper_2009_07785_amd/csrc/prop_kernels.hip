@@ -2,28 +2,28 @@
 // (Sofranac, Gleixner, Pokutta, arXiv 2009.07785, Algorithms 2 and 3) and
 // the drivers that repeat rounds on the device.
 //
-// One round, for every row:
-//   1. min / max activity from the start-of-round bounds: finite parts as
-//      exact-product double-double sums (rounded once at the end), plus the
-//      counts of infinite contributions (Definition 1; Sec. 3.4);
+// Bounds live in two arrays of (lb, ub) pairs: A holds the bounds as they
+// stood at the start of the round and is only read during it; B starts
+// equal to A and receives the candidates.  One round:
+//   1. every row's min / max activity from A: finite parts as exact-product
+//      double-double sums (rounded once at the end), plus the counts of
+//      infinite contributions (Definition 1; Sec. 3.4);
 //   2. per entry the candidates of Step 3 (eqs. bound_candidates_pos / _neg),
 //      rounded inward for integer variables, each one IEEE operation in the
 //      order (beta - activity) / a + bound;
-//   3. a candidate that beats the start-of-round bound is applied with an
-//      FP64 atomic max (lower) / min (upper) on the "next" bound array
-//      (Sec. 3.5, Algorithm 3); the first thread that moves a bound records
-//      the variable in the round's changed list.
-// The next round reads the array written in this one and writes the other;
-// the variables changed one round earlier are brought up to date in it with
-// the same atomics (max and min commute, so this can overlap the round's
-// own candidates), and their domains are checked for emptiness.
+//   3. a candidate that beats the start-of-round bound (the pre-check of
+//      Sec. 3.5) goes to B with an FP64 atomic max (lower) / min (upper);
+//      the atomics return nothing, so no wave waits on them (Algorithm 3);
+//   4. commit: every variable whose pair in B differs from A is copied to A,
+//      counted, and its domain checked for emptiness; the last block to
+//      finish decides the round's status from one packed counter.
 //
-// Work units: a "chunk" is one wave's tile of short/medium rows, data laid
-// out so each of up to 16 steps is one contiguous 64-entry load; a row of
-// K lanes sums its entries lane-by-lane, then across its K lanes.  Long rows
-// (more than 1024 entries) are split into 1024-entry segments: phase 1
-// writes a partial sum per segment, phase 2 combines all partials of the
-// row in a fixed order and handles the segment's candidates.
+// Work units: a "chunk" is one wave's tile of short/medium rows, laid out so
+// each of up to 16 steps is one contiguous 64-entry load; a row of K lanes
+// sums its entries lane by lane, then across its K lanes.  Rows longer than
+// 1024 entries are split into 1024-entry segments: phase 1 writes a partial
+// sum per segment, phase 2 combines all partials of the row in a fixed order
+// and handles the segment's candidates.
 //
 // Before any candidate arithmetic an entry is skipped when its row's slack
 // provably cannot tighten it: slack > |a| * (u - l) with a 2^-40 margin
@@ -122,16 +122,12 @@ __device__ __forceinline__ bool domain_empty(bool is_int, double l, double u, do
   return (l - u) > feas_tol * s;
 }
 
-__device__ __forceinline__ double atomic_max_f64(double* p, double v) {
-  return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Fire-and-forget FP64 atomics (the result is unused, so no wave waits).
+__device__ __forceinline__ void atomic_max_f64(double* p, double v) {
+  (void)__hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ double atomic_min_f64(double* p, double v) {
-  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void record_change(int32_t j, int32_t* list, uint32_t* count) {
-  uint32_t q = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  list[q] = j;
+__device__ __forceinline__ void atomic_min_f64(double* p, double v) {
+  (void)__hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Row-level quantities every entry of a row needs.
@@ -167,12 +163,15 @@ __device__ __forceinline__ bool entry_wanted(const RowState& R, double a, double
   return d;
 }
 
-// Candidates of one entry (a, j) with start-of-round bounds (l, u).
+// Candidates of one entry (a, column word cw) with start-of-round bounds
+// (l, u); the column word holds the variable in bits 0-30 and its
+// integrality in bit 31.
 __device__ __forceinline__ void entry_candidates(const Problem& P, const RowState& R, double a,
-                                                 double l, double u, int32_t j,
-                                                 double2* __restrict__ nxt, int32_t* list,
-                                                 uint32_t* count) {
+                                                 double l, double u, int32_t cw,
+                                                 double2* __restrict__ nxt) {
   if (a == 0.0) return;
+  const int32_t j = cw & kColMask;
+  const bool is_int = cw < 0;
   const double bmin = a > 0.0 ? l : u;
   const double bmax = a > 0.0 ? u : l;
   bool dmin = false, dmax = false;
@@ -198,7 +197,6 @@ __device__ __forceinline__ void entry_candidates(const Problem& P, const RowStat
     if (R.cmax == 0) t = t + bmax;
     if (a > 0.0) { lc = t; hl = true; } else { uc = t; hu = true; }
   }
-  const bool is_int = P.vtype[j] != 0;
   if (hl) {
     double c = is_int ? __builtin_ceil(lc - P.eps_int) : lc;
     c = c + 0.0;
@@ -210,10 +208,7 @@ __device__ __forceinline__ void entry_candidates(const Problem& P, const RowStat
         double s = __builtin_fabs(l) > 1.0 ? __builtin_fabs(l) : 1.0;
         sig = c > l + P.cont_rel_tol * s;
       }
-      if (sig) {
-        double old = atomic_max_f64(&nxt[j].x, c);
-        if (old <= l) record_change(j, list, count);
-      }
+      if (sig) atomic_max_f64(&nxt[j].x, c);
     }
   }
   if (hu) {
@@ -227,10 +222,7 @@ __device__ __forceinline__ void entry_candidates(const Problem& P, const RowStat
         double s = __builtin_fabs(u) > 1.0 ? __builtin_fabs(u) : 1.0;
         sig = c < u - P.cont_rel_tol * s;
       }
-      if (sig) {
-        double old = atomic_min_f64(&nxt[j].y, c);
-        if (old >= u) record_change(j, list, count);
-      }
+      if (sig) atomic_min_f64(&nxt[j].y, c);
     }
   }
 }
@@ -239,8 +231,9 @@ __device__ __forceinline__ void entry_candidates(const Problem& P, const RowStat
 // one chunk: activities and candidates for 64/K rows, K lanes per row
 // ---------------------------------------------------------------------------
 template <int KLOG>
-__device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd, const double2* __restrict__ cur,
-                            double2* __restrict__ nxt, int32_t* list, uint32_t* count) {
+__device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd,
+                                            const double2* __restrict__ cur,
+                                            double2* __restrict__ nxt) {
   const int lane = threadIdx.x & (kWave - 1);
   const int W = (cd.meta >> 8) & 0xff;
   const int nrows = (cd.meta >> 16) & 0xff;
@@ -262,7 +255,7 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
     l[w] = 0.0;
     u[w] = 0.0;
     if (w < W && a[w] != 0.0) {
-      const double2 b = cur[jj[w]];
+      const double2 b = cur[jj[w] & kColMask];
       l[w] = b.x;
       u[w] = b.y;
     }
@@ -277,41 +270,33 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
   const int row = cd.row0 + r;
   const RowState R = make_row_state(smin, smax, cmin, cmax, P.lhs[row], P.rhs[row]);
   if (!(R.min_side || R.max_side)) return;
-  // cheap filter over the registers, then the rare full candidate work on
-  // the flagged entries, reloaded (cache-hot) by step index
-  uint32_t need = 0;
+  // cheap filter first; the full candidate arithmetic runs only for the
+  // entries that pass it (a step no lane needs is skipped by the wave)
 #pragma unroll
   for (int w = 0; w < kMaxSteps; ++w)
-    if (w < W && entry_wanted(R, a[w], l[w], u[w])) need |= 1u << w;
-  while (need) {
-    const int w = __builtin_ctz(need);
-    need &= need - 1;
-    const size_t idx = base + (size_t)w * kWave;
-    const double av = P.vals[idx];
-    const int32_t j = P.cols[idx];
-    const double2 b = cur[j];
-    entry_candidates(P, R, av, b.x, b.y, j, nxt, list, count);
-  }
+    if (w < W && entry_wanted(R, a[w], l[w], u[w]))
+      entry_candidates(P, R, a[w], l[w], u[w], jj[w], nxt);
 }
 
-__device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const double2* cur, double2* nxt,
-                               int32_t* list, uint32_t* count) {
+__device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const double2* cur,
+                                               double2* nxt) {
   const ChunkDesc cd = P.chunks[c];
   switch (cd.meta & 7) {
-    case 0: chunk_round<0>(P, cd, cur, nxt, list, count); break;
-    case 1: chunk_round<1>(P, cd, cur, nxt, list, count); break;
-    case 2: chunk_round<2>(P, cd, cur, nxt, list, count); break;
-    case 3: chunk_round<3>(P, cd, cur, nxt, list, count); break;
-    case 4: chunk_round<4>(P, cd, cur, nxt, list, count); break;
-    case 5: chunk_round<5>(P, cd, cur, nxt, list, count); break;
-    default: chunk_round<6>(P, cd, cur, nxt, list, count); break;
+    case 0: chunk_round<0>(P, cd, cur, nxt); break;
+    case 1: chunk_round<1>(P, cd, cur, nxt); break;
+    case 2: chunk_round<2>(P, cd, cur, nxt); break;
+    case 3: chunk_round<3>(P, cd, cur, nxt); break;
+    case 4: chunk_round<4>(P, cd, cur, nxt); break;
+    case 5: chunk_round<5>(P, cd, cur, nxt); break;
+    default: chunk_round<6>(P, cd, cur, nxt); break;
   }
 }
 
 // ---------------------------------------------------------------------------
 // long rows
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void seg_phase1(const Problem& P, int s, const double2* __restrict__ cur) {
+__device__ __forceinline__ void seg_phase1(const Problem& P, int s,
+                                           const double2* __restrict__ cur) {
   const int lane = threadIdx.x & (kWave - 1);
   const SegDesc sd = P.segs[s];
   DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
@@ -332,7 +317,7 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s, const double
 #pragma unroll
   for (int w = 0; w < kMaxSteps; ++w) {
     if (a[w] != 0.0) {
-      const double2 b = cur[jj[w]];
+      const double2 b = cur[jj[w] & kColMask];
       accumulate(a[w], b.x, b.y, smin, smax, cmin, cmax);
       const double t = skip_threshold(a[w], b.x, b.y);
       wmax = t > wmax ? t : wmax;
@@ -360,8 +345,9 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s, const double
   }
 }
 
-__device__ __forceinline__ void seg_phase2(const Problem& P, int s, const double2* __restrict__ cur,
-                           double2* __restrict__ nxt, int32_t* list, uint32_t* count) {
+__device__ __forceinline__ void seg_phase2(const Problem& P, int s,
+                                           const double2* __restrict__ cur,
+                                           double2* __restrict__ nxt) {
   const int lane = threadIdx.x & (kWave - 1);
   const SegDesc sd = P.segs[s];
   DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
@@ -383,91 +369,98 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s, const double
   for (int p = lane; p < sd.len; p += kWave) {
     const double a = P.vals[sd.off + p];
     if (a == 0.0) continue;
-    const int32_t j = P.cols[sd.off + p];
-    const double2 b = cur[j];
-    if (entry_wanted(R, a, b.x, b.y)) entry_candidates(P, R, a, b.x, b.y, j, nxt, list, count);
+    const int32_t cw = P.cols[sd.off + p];
+    const double2 b = cur[cw & kColMask];
+    if (entry_wanted(R, a, b.x, b.y)) entry_candidates(P, R, a, b.x, b.y, cw, nxt);
   }
 }
 
-// Bring the variables changed one round earlier up to date in `nxt` and
-// check their (now final) domains in `cur`.
-__device__ __forceinline__ void fixup_and_check(const Problem& P, const int32_t* plist, uint32_t pcount,
-                                const double2* __restrict__ cur, double2* __restrict__ nxt,
-                                uint32_t tid, uint32_t nthreads) {
-  for (uint32_t q = tid; q < pcount; q += nthreads) {
-    const int32_t j = plist[q];
-    const double2 b = cur[j];
-    atomic_max_f64(&nxt[j].x, b.x);
-    atomic_min_f64(&nxt[j].y, b.y);
-    if (domain_empty(P.vtype[j] != 0, b.x, b.y, P.feas_tol))
-      __hip_atomic_store(&P.ctrl->infeasible, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-// Check the domains of the variables in a list (after the last round).
-__device__ __forceinline__ void check_list(const Problem& P, const int32_t* lst, uint32_t count,
-                           const double2* __restrict__ b, uint32_t tid, uint32_t nthreads) {
-  for (uint32_t q = tid; q < count; q += nthreads) {
-    const int32_t j = lst[q];
-    const double2 v = b[j];
-    if (domain_empty(P.vtype[j] != 0, v.x, v.y, P.feas_tol))
-      __hip_atomic_store(&P.ctrl->infeasible, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-__device__ __forceinline__ uint32_t ld_u32(const uint32_t* p) {
+// ---------------------------------------------------------------------------
+// commit: copy changed pairs B -> A, count them, check their domains
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t u32_load(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Status after round r (single thread).  Returns nothing; sets ctrl->done.
-//   done = 1: finished; done = 2: round limit reached with changes, the
-//   domains changed in the last round still have to be checked.
-__device__ __forceinline__ void end_of_round(const Problem& P, int r, int max_rounds) {
+// Per-thread part over a grid-stride range.
+__device__ __forceinline__ void commit_range(const Problem& P, uint32_t tid, uint32_t nthreads,
+                                             uint32_t& changed, uint32_t& infeasible) {
+  double2* A = P.bnd[0];
+  const double2* B = P.bnd[1];
+  for (uint32_t v = tid; v < (uint32_t)P.n; v += nthreads) {
+    const double2 a = A[v];
+    const double2 b = B[v];
+    if (a.x != b.x || a.y != b.y) {
+      A[v] = b;
+      ++changed;
+      if (domain_empty(P.vtype[v] != 0, b.x, b.y, P.feas_tol)) infeasible = 1;
+    }
+  }
+}
+
+// Block-wide sums; every thread gets the totals.
+__device__ __forceinline__ void block_sum2(uint32_t& x, uint32_t& y) {
+  __shared__ uint32_t sx[kWavesPerBlock], sy[kWavesPerBlock];
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    x += __shfl_xor(x, off, kWave);
+    y += __shfl_xor(y, off, kWave);
+  }
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    sx[wave] = x;
+    sy[wave] = y;
+  }
+  __syncthreads();
+  x = 0;
+  y = 0;
+#pragma unroll
+  for (int q = 0; q < kWavesPerBlock; ++q) {
+    x += sx[q];
+    y += sy[q];
+  }
+}
+
+// Status after round r from the round's totals (single thread).
+__device__ __forceinline__ void end_of_round(const Problem& P, int r, int max_rounds,
+                                             uint32_t changed, uint32_t infeasible) {
   Ctrl* C = P.ctrl;
-  const uint32_t inf = ld_u32(&C->infeasible);
-  const uint32_t cnt = ld_u32(&C->list_count[r & 1]);
-  if (inf) {
+  C->round = r + 1;
+  if (infeasible) {
     C->status = kInfeasible;
-    C->rounds = r - 1;
-    C->result_buf = (uint32_t)((r - 1) & 1);
+    C->rounds = r;
     C->done = 1;
-  } else if (cnt == 0) {
+  } else if (changed == 0) {
     C->status = kConverged;
     C->rounds = r;
-    C->result_buf = (uint32_t)(r & 1);
     C->done = 1;
   } else if (r >= max_rounds) {
     C->status = kMaxRounds;
     C->rounds = r;
-    C->result_buf = (uint32_t)(r & 1);
-    C->done = 2;
+    C->done = 1;
   }
-  C->list_count[(r + 1) & 1] = 0;
-  C->round = r + 1;
-}
-
-__device__ __forceinline__ void after_final_check(const Problem& P) {
-  Ctrl* C = P.ctrl;
-  if (ld_u32(&C->infeasible)) C->status = kInfeasible;
-  C->done = 1;
 }
 
 // Round-0 decision, shared by all drivers (single thread).
 __device__ __forceinline__ void start_status(const Problem& P, int max_rounds) {
   Ctrl* C = P.ctrl;
   C->round = 1;
-  if (ld_u32(&C->invalid) || ld_u32(&C->infeasible) || P.instance_infeasible) {
+  if (u32_load(&C->invalid) || u32_load(&C->infeasible) || P.instance_infeasible) {
     C->status = kInfeasible;
     C->rounds = 0;
-    C->result_buf = 0;
     C->done = 1;
   } else if (max_rounds == 0) {
     C->status = kMaxRounds;
     C->rounds = 0;
-    C->result_buf = 0;
     C->done = 1;
   }
 }
+
+// packed commit counter: bits 0-31 changed pairs, 32-47 blocks that saw an
+// empty domain, 48-63 blocks finished
+constexpr uint64_t kCommitBlock = 1ull << 48;
+constexpr uint64_t kCommitInf = 1ull << 32;
 
 // ---------------------------------------------------------------------------
 // grid barrier for the persistent driver (sense-reversing, bounded wait)
@@ -475,25 +468,30 @@ __device__ __forceinline__ void start_status(const Problem& P, int max_rounds) {
 #define PROP_SPIN_LIMIT (1u << 26)
 
 // What the last block to arrive at a barrier does before releasing the rest.
-enum BarrierAction { kActNone = 0, kActStart = 1, kActEndRound = 2, kActFinal = 3 };
+enum BarrierAction { kActNone = 0, kActStart = 1, kActEndRound = 2 };
 
 // All threads of all blocks call this.  The action runs on the last
 // arriving block's thread 0 before the others are released.  Returns false
 // when the wait gave up (every block then leaves its loop).
 __device__ __forceinline__ bool grid_barrier(const Problem& P, int action, int r, int max_rounds) {
   Ctrl* C = P.ctrl;
-  __threadfence();
   __syncthreads();
   __shared__ uint32_t ok_shared;
   if (threadIdx.x == 0) {
+    __threadfence();
     uint32_t ok = 1;
     const uint32_t g = __hip_atomic_load(&C->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t prev =
         __hip_atomic_fetch_add(&C->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     if (prev == gridDim.x - 1) {
-      if (action == kActStart) start_status(P, max_rounds);
-      else if (action == kActEndRound) end_of_round(P, r, max_rounds);
-      else if (action == kActFinal) after_final_check(P);
+      if (action == kActStart) {
+        start_status(P, max_rounds);
+      } else if (action == kActEndRound) {
+        const uint64_t w =
+            __hip_atomic_load(&C->commit_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        end_of_round(P, r, max_rounds, (uint32_t)w, (uint32_t)((w >> 32) & 0xffff));
+        __hip_atomic_store(&C->commit_word, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       __hip_atomic_store(&C->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&C->bar_gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
@@ -508,10 +506,10 @@ __device__ __forceinline__ bool grid_barrier(const Problem& P, int action, int r
         }
       }
     }
+    __threadfence();
     ok_shared = ok;
   }
   __syncthreads();
-  __threadfence();
   return ok_shared != 0;
 }
 
@@ -521,14 +519,12 @@ __device__ __forceinline__ bool grid_barrier(const Problem& P, int action, int r
 __global__ void k_init(Problem P) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     Ctrl* C = P.ctrl;
-    C->list_count[0] = 0;
-    C->list_count[1] = 0;
+    C->commit_word = 0;
     C->infeasible = 0;
     C->invalid = 0;
     C->status = kMaxRounds;
     C->rounds = 0;
     C->done = 0;
-    C->result_buf = 0;
     C->round = 1;
     C->bar_count = 0;
     C->bar_gen = 0;
@@ -565,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(Problem P, const double* __rest
 
 __global__ __launch_bounds__(kBlock) void k_unpack(Problem P, double* __restrict__ ulb,
                                                    double* __restrict__ uub) {
-  const double2* src = P.bnd[P.ctrl->result_buf & 1];
+  const double2* src = P.bnd[0];
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)P.n; v += stride) {
     const double2 b = src[P.perm[v]];
@@ -582,32 +578,29 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Problem P, int max_rounds
   const int nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t nthreads = gridDim.x * blockDim.x;
+  const double2* A = P.bnd[0];
+  double2* B = P.bnd[1];
 
   if (!grid_barrier(P, kActStart, 0, max_rounds)) return;
-  if (__hip_atomic_load(&C->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  if (u32_load(&C->done)) return;
 
   for (int r = 1; r <= max_rounds; ++r) {
-    const int cb = (r - 1) & 1, nb = r & 1;
-    const double2* cur = P.bnd[cb];
-    double2* nxt = P.bnd[nb];
-    int32_t* list = P.list[nb];
-    uint32_t* count = &C->list_count[nb];
-    const uint32_t pcount = r == 1 ? 0u : ld_u32(&C->list_count[cb]);
-    fixup_and_check(P, P.list[cb], pcount, cur, nxt, tid, nthreads);
-    for (int c = gwave; c < P.n_chunks; c += nwaves) chunk_dispatch(P, c, cur, nxt, list, count);
+    for (int c = gwave; c < P.n_chunks; c += nwaves) chunk_dispatch(P, c, A, B);
     if (P.n_segs) {
-      for (int s = gwave; s < P.n_segs; s += nwaves) seg_phase1(P, s, cur);
+      for (int s = gwave; s < P.n_segs; s += nwaves) seg_phase1(P, s, A);
       if (!grid_barrier(P, kActNone, r, max_rounds)) return;
-      for (int s = gwave; s < P.n_segs; s += nwaves) seg_phase2(P, s, cur, nxt, list, count);
+      for (int s = gwave; s < P.n_segs; s += nwaves) seg_phase2(P, s, A, B);
     }
+    if (!grid_barrier(P, kActNone, r, max_rounds)) return;
+    uint32_t changed = 0, infeasible = 0;
+    commit_range(P, tid, nthreads, changed, infeasible);
+    block_sum2(changed, infeasible);
+    if (threadIdx.x == 0 && (changed || infeasible))
+      __hip_atomic_fetch_add(&C->commit_word,
+                             (uint64_t)changed | (infeasible ? kCommitInf : 0ull),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!grid_barrier(P, kActEndRound, r, max_rounds)) return;
-    const uint32_t done = __hip_atomic_load(&C->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (done == 1) return;
-    if (done == 2) {
-      check_list(P, P.list[nb], ld_u32(&C->list_count[nb]), nxt, tid, nthreads);
-      grid_barrier(P, kActFinal, r, max_rounds);
-      return;
-    }
+    if (u32_load(&C->done)) return;
   }
 }
 
@@ -616,48 +609,39 @@ __global__ void k_start(Problem P, int max_rounds) {
   if (blockIdx.x == 0 && threadIdx.x == 0) start_status(P, max_rounds);
 }
 
-__global__ __launch_bounds__(kBlock) void k_round(Problem P, int r) {
-  Ctrl* C = P.ctrl;
-  if (__hip_atomic_load(&C->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+__global__ __launch_bounds__(kBlock) void k_round(Problem P) {
+  if (u32_load(&P.ctrl->done)) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = blockIdx.x * kWavesPerBlock + wave;
-  const int cb = (r - 1) & 1, nb = r & 1;
-  const double2* cur = P.bnd[cb];
-  double2* nxt = P.bnd[nb];
-  const uint32_t pcount = r == 1 ? 0u : ld_u32(&C->list_count[cb]);
-  fixup_and_check(P, P.list[cb], pcount, cur, nxt, blockIdx.x * blockDim.x + threadIdx.x,
-                  gridDim.x * blockDim.x);
-  if (item < P.n_segs) seg_phase1(P, item, cur);
-  else if (item - P.n_segs < P.n_chunks)
-    chunk_dispatch(P, item - P.n_segs, cur, nxt, P.list[nb], &C->list_count[nb]);
+  if (item < P.n_segs) seg_phase1(P, item, P.bnd[0]);
+  else if (item - P.n_segs < P.n_chunks) chunk_dispatch(P, item - P.n_segs, P.bnd[0], P.bnd[1]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_round_long(Problem P, int r) {
-  Ctrl* C = P.ctrl;
-  if (__hip_atomic_load(&C->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+__global__ __launch_bounds__(kBlock) void k_round_long(Problem P) {
+  if (u32_load(&P.ctrl->done)) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int s = blockIdx.x * kWavesPerBlock + wave;
-  const int cb = (r - 1) & 1, nb = r & 1;
-  if (s < P.n_segs)
-    seg_phase2(P, s, P.bnd[cb], P.bnd[nb], P.list[nb], &C->list_count[nb]);
+  if (s < P.n_segs) seg_phase2(P, s, P.bnd[0], P.bnd[1]);
 }
 
-__global__ void k_end_round(Problem P, int r, int max_rounds) {
+// Commit of round r; the last block to finish decides the status.
+__global__ __launch_bounds__(kBlock) void k_commit(Problem P, int r, int max_rounds) {
   Ctrl* C = P.ctrl;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && C->done == 0) end_of_round(P, r, max_rounds);
-}
-
-__global__ __launch_bounds__(kBlock) void k_final_check(Problem P) {
-  Ctrl* C = P.ctrl;
-  if (__hip_atomic_load(&C->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 2) return;
-  const int b = C->result_buf & 1;
-  check_list(P, P.list[b], ld_u32(&C->list_count[b]), P.bnd[b],
-             blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-}
-
-__global__ void k_final_status(Problem P) {
-  Ctrl* C = P.ctrl;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && C->done == 2) after_final_check(P);
+  if (u32_load(&C->done)) return;
+  uint32_t changed = 0, infeasible = 0;
+  commit_range(P, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, changed,
+               infeasible);
+  block_sum2(changed, infeasible);
+  if (threadIdx.x == 0) {
+    const uint64_t add = kCommitBlock | (uint64_t)changed | (infeasible ? kCommitInf : 0ull);
+    const uint64_t old =
+        __hip_atomic_fetch_add(&C->commit_word, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((old >> 48) == gridDim.x - 1u) {
+      const uint64_t tot = old + add;
+      end_of_round(P, r, max_rounds, (uint32_t)tot, (uint32_t)((tot >> 32) & 0xffff));
+      __hip_atomic_store(&C->commit_word, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -702,19 +686,19 @@ hipError_t launch_start(const Problem& P, int max_rounds, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_round(const Problem& P, int r, int max_rounds, hipStream_t s) {
+hipError_t launch_round(const Problem& P, int r, int max_rounds, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1) {
   const int items = P.n_chunks + P.n_segs;
+  if (e0) hipEventRecord(e0, s);
   hipLaunchKernelGGL(k_round, dim3(blocks_for(items, kWavesPerBlock, 1 << 30)), dim3(kBlock), 0,
-                     s, P, r);
+                     s, P);
+  if (e1) hipEventRecord(e1, s);
   if (P.n_segs)
     hipLaunchKernelGGL(k_round_long, dim3(blocks_for(P.n_segs, kWavesPerBlock, 1 << 30)),
-                       dim3(kBlock), 0, s, P, r);
-  hipLaunchKernelGGL(k_end_round, dim3(1), dim3(64), 0, s, P, r, max_rounds);
-  if (r == max_rounds) {
-    hipLaunchKernelGGL(k_final_check, dim3(blocks_for(2 * (int64_t)P.n, kBlock, 4096)),
                        dim3(kBlock), 0, s, P);
-    hipLaunchKernelGGL(k_final_status, dim3(1), dim3(64), 0, s, P);
-  }
+  // at most 65535 blocks: the packed commit counter keeps 16 bits per field
+  hipLaunchKernelGGL(k_commit, dim3(blocks_for(P.n, kBlock, 1024)), dim3(kBlock), 0, s, P, r,
+                     max_rounds);
   return hipGetLastError();
 }
 

@@ -13,7 +13,9 @@ hipError_t launch_unpack(const Problem& P, double* lb, double* ub, hipStream_t s
 hipError_t persistent_occupancy(int* blocks_per_cu);
 hipError_t launch_persistent(const Problem& P, int max_rounds, int grid, hipStream_t s);
 hipError_t launch_start(const Problem& P, int max_rounds, hipStream_t s);
-// Queues one round (and, at r == max_rounds, the final domain check).
-hipError_t launch_round(const Problem& P, int r, int max_rounds, hipStream_t s);
+// Queues one round: the matrix kernel (bracketed by e0 / e1 when they are
+// not null), the long-row kernel, and the commit.
+hipError_t launch_round(const Problem& P, int r, int max_rounds, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1);
 
 }  // namespace prop

@@ -18,8 +18,9 @@
 //
 // Variables are relabelled by decreasing column degree so the bounds of
 // the most used variables share cache lines.  Bounds live as (lb, ub)
-// pairs, one 16-byte load per entry; two such arrays alternate between
-// "start of round" (read only) and "next" (atomic max / min target).
+// pairs, one 16-byte load per entry, in two arrays: the start-of-round
+// bounds (read only during a round) and the candidate target (atomic max /
+// min), reconciled by a commit pass at the end of every round.
 #pragma once
 
 #include <stdint.h>
@@ -31,6 +32,10 @@ constexpr int kMaxSteps = 16;    // steps per wave tile
 constexpr int kSegLen = kWave * kMaxSteps;  // entries per long-row segment
 constexpr int kBlock = 256;      // threads per workgroup (4 waves)
 constexpr int kWavesPerBlock = kBlock / kWave;
+
+// A stored column word holds the (relabelled) variable in bits 0-30 and
+// the variable's integrality in bit 31.
+constexpr int32_t kColMask = 0x7fffffff;
 
 // run outcome codes (match PROP_CONVERGED / PROP_INFEASIBLE / PROP_MAX_ROUNDS)
 constexpr int kConverged = 0;
@@ -68,18 +73,17 @@ struct SegPartial {
 
 // Device control block of one problem.
 struct Ctrl {
-  uint32_t list_count[2];  // lengths of the two changed-variable lists
-  uint32_t infeasible;     // set when a checked domain is empty
+  uint64_t commit_word;    // packed per-round commit totals (see the kernels)
+  uint32_t infeasible;     // set when an input domain is empty
   uint32_t invalid;        // set when a bound fails validation
   int32_t status;
   int32_t rounds;
   uint32_t done;           // loop finished
-  uint32_t result_buf;     // which bound array holds the result
-  int32_t round;           // next round to run (stream / host drivers)
+  int32_t round;           // next round to run
   uint32_t bar_count;      // grid barrier arrival counter
   uint32_t bar_gen;        // grid barrier generation
   uint32_t abort;          // barrier wait gave up (device timeout)
-  uint32_t pad[4];
+  uint32_t pad[5];
 };
 
 // Everything a kernel needs, passed by value.
@@ -98,9 +102,8 @@ struct Problem {
   int32_t n_segs;
   int32_t n;
   int32_t instance_infeasible;
-  // state
+  // state: bnd[0] = start-of-round bounds, bnd[1] = candidate target
   double2* bnd[2];
-  int32_t* list[2];         // capacity 2 n each
   Ctrl* ctrl;
   // parameters
   double eps_int, cont_rel_tol, feas_tol;
