@@ -25,11 +25,18 @@
 // sum per segment, phase 2 combines all partials of the row in a fixed order
 // and handles the segment's candidates.
 //
-// Before any candidate arithmetic an entry is skipped when its row's slack
-// provably cannot tighten it: slack > |a| * (u - l) with a 2^-40 margin
-// (and slack > 0 for a fixed variable).  The margin covers the rounding of
-// the test itself and of the candidate formula, so a skipped entry is one
-// whose exact candidate would not have been applied.
+// Before any candidate arithmetic an entry side is skipped when the row's
+// slack s on that side (rhs - min activity, or max activity - lhs) proves
+// that its candidate cannot count.  For a > 0 on the rhs side the candidate
+// is c = RN(RN(s / a) + l) and counts when c < V, V the point below which an
+// upper bound must move (u itself for integers, up to the eps_int rounding;
+// u - tau * max(1, |u|) for continuous variables, evaluated exactly as the
+// significance test does).  If s > RN(RN(|a| * W) * (1 + 2^-39)) with
+// W = RN(V - l) > 0, then s > |a| * (V - l) * (1 + 2^-40) in exact terms, so
+// RN(s / a) > V - l and c >= V: the candidate cannot count.  The other three
+// sign / side combinations are mirror images; integers use W = u - l, where
+// c >= u already rules out floor(c + eps_int) < u.  A skipped side is thus
+// exactly one whose candidate the oracle would also have discarded.
 #include <hip/hip_runtime.h>
 
 #include "prop_launch.h"
@@ -40,7 +47,7 @@
 namespace prop {
 
 #define PROP_HUGE 0x1p200
-#define PROP_SKIP_MARGIN (1.0 + 0x1p-40)
+#define PROP_SKIP_MARGIN (1.0 + 0x1p-39)
 #define PROP_SKIP_FLOOR 0x1p-900
 
 // ---------------------------------------------------------------------------
@@ -106,11 +113,40 @@ __device__ __forceinline__ void accumulate(double a, double l, double u, DD& smi
   dd_add_prod(smax, a, imax ? 0.0 : bmax);
 }
 
-// Largest slack for which the entry could still be tightened (see header).
-__device__ __forceinline__ double skip_threshold(double a, double l, double u) {
-  const double w = u - l;
-  if (w == 0.0) return 0.0;
-  if (!(w > 0.0)) return __builtin_inf();
+// Skip threshold of one side of an entry: the candidate that side yields
+// cannot count (be applied) when the row's slack on that side exceeds the
+// returned value.  `upper` says which bound the side would tighten.  The
+// width used is the distance from the other bound to the point where a
+// candidate starts to count: u - l for integers, and for continuous
+// variables the same expressions the significance test evaluates
+// (u - tau * max(1, |u|) for an upper bound, l + tau * max(1, |l|) for a
+// lower one).  With that width W > 0 the threshold is |a| * W with a
+// 1 + 2^-39 margin, which covers the rounding of these three operations and
+// of the candidate's own s / a and + bound (see the file header).  W <= 0
+// means the candidate cannot count while the slack is >= 0, encoded as the
+// threshold -2^-1074 (slack > -2^-1074 <=> slack >= 0).  An infinite bound
+// to tighten counts every finite candidate: threshold +inf.
+__device__ __forceinline__ double side_threshold(double a, double l, double u, bool is_int,
+                                                 bool upper, double tau) {
+  double w;
+  if (upper) {
+    if (u == __builtin_inf()) return __builtin_inf();
+    if (is_int) {
+      w = u - l;
+    } else {
+      const double s = __builtin_fabs(u) > 1.0 ? __builtin_fabs(u) : 1.0;
+      w = (u - tau * s) - l;
+    }
+  } else {
+    if (l == -__builtin_inf()) return __builtin_inf();
+    if (is_int) {
+      w = u - l;
+    } else {
+      const double s = __builtin_fabs(l) > 1.0 ? __builtin_fabs(l) : 1.0;
+      w = u - (l + tau * s);
+    }
+  }
+  if (!(w > 0.0)) return -0x1p-1074;
   const double thr = (__builtin_fabs(a) * w) * PROP_SKIP_MARGIN;
   return thr >= PROP_SKIP_FLOOR ? thr : __builtin_inf();
 }
@@ -153,14 +189,31 @@ __device__ __forceinline__ RowState make_row_state(const DD& smin, const DD& sma
   return R;
 }
 
-// Whether entry (a; l, u) needs the candidate arithmetic at all.
-__device__ __forceinline__ bool entry_wanted(const RowState& R, double a, double l, double u) {
-  if (a == 0.0) return false;
-  const double thr = skip_threshold(a, l, u);
-  bool d = false;
-  if (R.min_side) d |= (R.cmin == 0) ? !(R.smn > thr) : is_inf(a > 0.0 ? l : u);
-  if (R.max_side) d |= (R.cmax == 0) ? !((-R.smx) > thr) : is_inf(a > 0.0 ? u : l);
-  return d;
+// Which sides of entry (a, column word cw; start-of-round l, u) need the
+// candidate arithmetic.  The rhs side works through the min activity and
+// tightens u when a > 0, l when a < 0; the lhs side the other way round.
+// With one infinite contribution only its owner gets a candidate.
+__device__ __forceinline__ void entry_sides(const RowState& R, double a, double l, double u,
+                                            int32_t cw, double tau, bool& dmin, bool& dmax) {
+  dmin = dmax = false;
+  if (a == 0.0) return;
+  const bool is_int = cw < 0;
+  const bool pos = a > 0.0;
+  if (R.min_side) {
+    if (R.cmin == 0) dmin = !(R.smn > side_threshold(a, l, u, is_int, pos, tau));
+    else dmin = is_inf(pos ? l : u);
+  }
+  if (R.max_side) {
+    if (R.cmax == 0) dmax = !((-R.smx) > side_threshold(a, l, u, is_int, !pos, tau));
+    else dmax = is_inf(pos ? u : l);
+  }
+}
+
+__device__ __forceinline__ bool entry_wanted(const RowState& R, double a, double l, double u,
+                                             int32_t cw, double tau) {
+  bool dmin, dmax;
+  entry_sides(R, a, l, u, cw, tau, dmin, dmax);
+  return dmin || dmax;
 }
 
 // Candidates of one entry (a, column word cw) with start-of-round bounds
@@ -169,21 +222,13 @@ __device__ __forceinline__ bool entry_wanted(const RowState& R, double a, double
 __device__ __forceinline__ void entry_candidates(const Problem& P, const RowState& R, double a,
                                                  double l, double u, int32_t cw,
                                                  double2* __restrict__ nxt) {
-  if (a == 0.0) return;
+  bool dmin, dmax;
+  entry_sides(R, a, l, u, cw, P.cont_rel_tol, dmin, dmax);
+  if (!(dmin || dmax)) return;
   const int32_t j = cw & kColMask;
   const bool is_int = cw < 0;
   const double bmin = a > 0.0 ? l : u;
   const double bmax = a > 0.0 ? u : l;
-  bool dmin = false, dmax = false;
-  if (R.min_side) {
-    if (R.cmin == 0) dmin = !(R.smn > skip_threshold(a, l, u));
-    else dmin = is_inf(bmin);
-  }
-  if (R.max_side) {
-    if (R.cmax == 0) dmax = !((-R.smx) > skip_threshold(a, l, u));
-    else dmax = is_inf(bmax);
-  }
-  if (!(dmin || dmax)) return;
 
   double lc = 0.0, uc = 0.0;
   bool hl = false, hu = false;
@@ -274,7 +319,7 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
   // entries that pass it (a step no lane needs is skipped by the wave)
 #pragma unroll
   for (int w = 0; w < kMaxSteps; ++w)
-    if (w < W && entry_wanted(R, a[w], l[w], u[w]))
+    if (w < W && entry_wanted(R, a[w], l[w], u[w], jj[w], P.cont_rel_tol))
       entry_candidates(P, R, a[w], l[w], u[w], jj[w], nxt);
 }
 
@@ -301,7 +346,7 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
   const SegDesc sd = P.segs[s];
   DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
   int cmin = 0, cmax = 0;
-  double wmax = 0.0;
+  double tmin = -0x1p-1074, tmax = -0x1p-1074;  // per-side skip thresholds
   double a[kMaxSteps];
   int32_t jj[kMaxSteps];
 #pragma unroll
@@ -319,15 +364,20 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
     if (a[w] != 0.0) {
       const double2 b = cur[jj[w] & kColMask];
       accumulate(a[w], b.x, b.y, smin, smax, cmin, cmax);
-      const double t = skip_threshold(a[w], b.x, b.y);
-      wmax = t > wmax ? t : wmax;
+      const bool is_int = jj[w] < 0, pos = a[w] > 0.0;
+      const double t1 = side_threshold(a[w], b.x, b.y, is_int, pos, P.cont_rel_tol);
+      const double t2 = side_threshold(a[w], b.x, b.y, is_int, !pos, P.cont_rel_tol);
+      tmin = t1 > tmin ? t1 : tmin;
+      tmax = t2 > tmax ? t2 : tmax;
     }
   }
   group_reduce<6>(smin, smax, cmin, cmax);
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) {
-    const double o = __shfl_xor(wmax, off, kWave);
-    wmax = o > wmax ? o : wmax;
+    const double o1 = __shfl_xor(tmin, off, kWave);
+    const double o2 = __shfl_xor(tmax, off, kWave);
+    tmin = o1 > tmin ? o1 : tmin;
+    tmax = o2 > tmax ? o2 : tmax;
   }
   if (lane == 0) {
     SegPartial q;
@@ -335,11 +385,10 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
     q.min_lo = smin.lo;
     q.max_hi = smax.hi;
     q.max_lo = smax.lo;
-    q.wmax = wmax;
+    q.tmin = tmin;
+    q.tmax = tmax;
     q.min_inf = cmin;
     q.max_inf = cmax;
-    q.min_inf_own = cmin;
-    q.max_inf_own = cmax;
     q.pad0 = q.pad1 = 0;
     P.partials[s] = q;
   }
@@ -363,15 +412,16 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
   const RowState R = make_row_state(smin, smax, cmin, cmax, P.lhs[sd.row], P.rhs[sd.row]);
   const SegPartial own = P.partials[s];
   bool need = false;
-  if (R.min_side) need |= (R.cmin == 0) ? !(R.smn > own.wmax) : (own.min_inf_own > 0);
-  if (R.max_side) need |= (R.cmax == 0) ? !((-R.smx) > own.wmax) : (own.max_inf_own > 0);
+  if (R.min_side) need |= (R.cmin == 0) ? !(R.smn > own.tmin) : (own.min_inf > 0);
+  if (R.max_side) need |= (R.cmax == 0) ? !((-R.smx) > own.tmax) : (own.max_inf > 0);
   if (!need) return;
   for (int p = lane; p < sd.len; p += kWave) {
     const double a = P.vals[sd.off + p];
     if (a == 0.0) continue;
     const int32_t cw = P.cols[sd.off + p];
     const double2 b = cur[cw & kColMask];
-    if (entry_wanted(R, a, b.x, b.y)) entry_candidates(P, R, a, b.x, b.y, cw, nxt);
+    if (entry_wanted(R, a, b.x, b.y, cw, P.cont_rel_tol))
+      entry_candidates(P, R, a, b.x, b.y, cw, nxt);
   }
 }
 

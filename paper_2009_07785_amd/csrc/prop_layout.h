@@ -64,10 +64,8 @@ struct SegDesc {
 struct SegPartial {
   double min_hi, min_lo;   // double-double finite part of the min activity
   double max_hi, max_lo;   // same for the max activity
-  double wmax;             // largest |a| * (u - l) among the segment's entries
+  double tmin, tmax;       // largest per-side skip threshold of the segment's entries
   int32_t min_inf, max_inf;
-  int32_t min_inf_own;     // entries of this segment with an infinite min term
-  int32_t max_inf_own;
   int32_t pad0, pad1;
 };
 
