@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--loop", default="stream", choices=["persistent", "stream", "host"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-loop-compare", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched branch-and-bound node comparison")
+    ap.add_argument("--batch-nodes", type=int, default=256)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_config2.json"),
                     help="HBM traffic per launch measured with rocprofv3 counters (JSON)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -204,6 +207,8 @@ def main():
         prob.set_loop(args.loop)
         log(f"round-loop drivers: {loops}")
 
+    batch = None if args.no_batch else batched_nodes(args.batch_nodes, args.max_rounds)
+
     base = cpu_baseline(inst, args.no_cpu_baseline)
 
     out = {
@@ -244,10 +249,88 @@ def main():
             "traffic": traffic,
         },
         "round_loops": loops,
+        "batched": batch,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)
     prob.close()
+
+
+def batched_nodes(count: int, max_rounds: int):
+    """Branch-and-bound nodes on the 1,000,000 x 500,000 power-law matrix:
+    `count` bound vectors (1-5% of the integer variables fixed each),
+    propagated in one batched run and as `count` separate runs, with the
+    results required to be identical."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2009_07785_amd import Problem
+
+    dev = torch.device("cuda:0")
+    log("generating the 1,000,000 x 500,000 matrix and the node bounds")
+    inst = synth.cached("config3", synth.config3_matrix)
+    lbs, ubs = synth.config3_nodes(inst, count)
+    prob = Problem.from_instance(inst)
+    D_lb = torch.tensor(lbs, dtype=torch.float64, device=dev)
+    D_ub = torch.tensor(ubs, dtype=torch.float64, device=dev)
+    s_lb = torch.empty(inst.n, dtype=torch.float64, device=dev)
+    s_ub = torch.empty_like(s_lb)
+    out_lb = torch.empty_like(D_lb)
+    out_ub = torch.empty_like(D_ub)
+    stream = torch.cuda.current_stream(dev)
+
+    def one_at_a_time():
+        res = []
+        for k in range(count):
+            s_lb.copy_(D_lb[k])
+            s_ub.copy_(D_ub[k])
+            res.append(prob.run_device(s_lb, s_ub, max_rounds, stream))
+            out_lb[k].copy_(s_lb)
+            out_ub[k].copy_(s_ub)
+        return res
+
+    def batched():
+        b_lb = D_lb.clone()
+        b_ub = D_ub.clone()
+        return prob.run_batch_device(b_lb, b_ub, max_rounds, stream), b_lb, b_ub
+
+    one_at_a_time()
+    batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = one_at_a_time()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bat, b_lb, b_ub = batched()
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    same_status = all((a.status, a.rounds) == (b.status, b.rounds) for a, b in zip(seq, bat))
+    feas = torch.tensor([r.status != 1 for r in seq], device=dev)
+    same_bounds = bool(torch.all(torch.where(feas[:, None], (b_lb == out_lb) & (b_ub == out_ub),
+                                             True)).item())
+    statuses = {}
+    for r in seq:
+        statuses[r.status_name] = statuses.get(r.status_name, 0) + 1
+    rounds = [r.rounds for r in seq]
+    out = {
+        "workload": f"config3: {inst.m}x{inst.n} power-law matrix ({inst.nnz} nnz), {count} "
+                    "nodes fixing 1-5% of the integer variables",
+        "nodes": count,
+        "batched_nodes_per_s": count / t_bat,
+        "one_at_a_time_nodes_per_s": count / t_seq,
+        "speedup": t_seq / t_bat,
+        "batched_ms": t_bat * 1e3,
+        "one_at_a_time_ms": t_seq * 1e3,
+        "rounds_max": max(rounds),
+        "rounds_mean": float(np.mean(rounds)),
+        "statuses": statuses,
+        "identical_results": bool(same_status and same_bounds),
+    }
+    log(f"batched nodes: {out}")
+    prob.close()
+    return out
 
 
 def kernel_source_sha() -> str:

@@ -134,6 +134,20 @@ int prop_run(prop_problem* p, double* lb, double* ub, int32_t max_rounds, prop_r
 int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rounds,
                     void* stream, prop_result* out);
 
+/* Propagates `nodes` bound vectors of the same problem together (for
+ * example branch-and-bound nodes).  d_lb, d_ub: device arrays of nodes * n
+ * doubles, node k's bounds at [k * n, (k + 1) * n), caller-owned, updated in
+ * place.  out: host array of `nodes` results.  Each node's status, rounds
+ * and bounds are bitwise those a separate prop_run_device call on that node
+ * returns; nodes that finish early stop consuming work.  Rounds are queued
+ * on `stream` in batches as by PROP_LOOP_STREAM.  The first call with more
+ * nodes than any earlier call allocates the batch workspace
+ * (32 * n * ceil(nodes / 8) * 8 bytes of bounds, plus per-node counters and
+ * long-row partials), kept until prop_destroy; later calls allocate
+ * nothing.  An invalid bound in any node returns PROP_EINVAL. */
+int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* d_ub,
+                          int32_t max_rounds, void* stream, prop_result* out);
+
 /* Selects the round-loop driver (PROP_LOOP_*) for later runs. */
 int prop_set_loop(prop_problem* p, int32_t mode);
 

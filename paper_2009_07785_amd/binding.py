@@ -23,7 +23,8 @@ LOOP_PERSISTENT, LOOP_STREAM, LOOP_HOST = 0, 1, 2
 LOOP_NAMES = {"persistent": LOOP_PERSISTENT, "stream": LOOP_STREAM, "host": LOOP_HOST}
 
 # every function the header declares
-EXPORTED = ("prop_create", "prop_run", "prop_run_device", "prop_set_loop", "prop_get_info",
+EXPORTED = ("prop_create", "prop_run", "prop_run_device", "prop_run_batch_device",
+            "prop_set_loop", "prop_get_info",
             "prop_last_timing", "prop_set_kernel_timing", "prop_last_kernel_timing",
             "prop_destroy", "prop_last_error")
 
@@ -78,6 +79,8 @@ def _load():
     lib.prop_run.restype = ctypes.c_int
     lib.prop_run_device.argtypes = [P, P, P, i32, P, ctypes.POINTER(_Result)]
     lib.prop_run_device.restype = ctypes.c_int
+    lib.prop_run_batch_device.argtypes = [P, i32, P, P, i32, P, ctypes.POINTER(_Result)]
+    lib.prop_run_batch_device.restype = ctypes.c_int
     lib.prop_set_loop.argtypes = [P, i32]
     lib.prop_set_loop.restype = ctypes.c_int
     lib.prop_get_info.argtypes = [P, ctypes.POINTER(_Info)]
@@ -198,6 +201,27 @@ class Problem:
                                    ctypes.c_void_p(d_ub.data_ptr()), int(max_rounds),
                                    ctypes.c_void_p(int(raw) if raw else 0), ctypes.byref(res)))
         return RunResult(res.status, res.rounds)
+
+    def run_batch_device(self, d_lb, d_ub, max_rounds: int = 100, stream=None):
+        """Batched nodes: device tensors of shape (nodes, n), float64, updated
+        in place.  Returns one RunResult per node."""
+        for t in (d_lb, d_ub):
+            if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8
+                    and t.is_contiguous() and t.dim() == 2 and t.shape[1] == self.n):
+                raise ValueError("bounds must be contiguous float64 device tensors (nodes, n)")
+        nodes = int(d_lb.shape[0])
+        if d_ub.shape[0] != nodes:
+            raise ValueError("lb and ub hold different node counts")
+        if stream is None:
+            import torch
+
+            stream = torch.cuda.current_stream(d_lb.device)
+        raw = getattr(stream, "cuda_stream", stream)
+        res = (_Result * nodes)()
+        _check(lib.prop_run_batch_device(self._h, nodes, ctypes.c_void_p(d_lb.data_ptr()),
+                                         ctypes.c_void_p(d_ub.data_ptr()), int(max_rounds),
+                                         ctypes.c_void_p(int(raw) if raw else 0), res))
+        return [RunResult(r.status, r.rounds) for r in res]
 
     def set_loop(self, mode):
         if isinstance(mode, str):

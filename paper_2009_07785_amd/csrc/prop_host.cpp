@@ -84,6 +84,12 @@ struct prop_problem {
   int kev_used = 0;              // rounds bracketed in the last run
   double last_kernel_ms = 0.0;
   float last_loop_ms = 0.f, last_total_ms = 0.f;
+  // batch workspace (grown on demand, kept until destroy)
+  Batch bt{};
+  int32_t batch_capacity = 0;
+  std::vector<void*> batch_allocs;
+  int32_t* h_bstatus = nullptr;  // pinned copies of per-node status / rounds
+  int32_t* h_brounds = nullptr;
 };
 
 namespace {
@@ -121,6 +127,9 @@ void release(prop_problem* p) {
     if (e) hipEventDestroy(e);
   for (auto& e : p->kev)
     if (e) hipEventDestroy(e);
+  for (void* a : p->batch_allocs) hipFree(a);
+  if (p->h_bstatus) hipHostFree(p->h_bstatus);
+  if (p->h_brounds) hipHostFree(p->h_brounds);
   delete p;
 }
 
@@ -453,6 +462,48 @@ int run_loop(prop_problem* p, int32_t max_rounds, hipStream_t s) {
   }
 }
 
+// Makes the batch workspace hold at least `nodes` nodes.
+int ensure_batch(prop_problem* p, int32_t nodes) {
+  if (nodes <= p->batch_capacity) return PROP_OK;
+  for (void* a : p->batch_allocs) hipFree(a);
+  p->batch_allocs.clear();
+  if (p->h_bstatus) hipHostFree(p->h_bstatus);
+  if (p->h_brounds) hipHostFree(p->h_brounds);
+  p->h_bstatus = p->h_brounds = nullptr;
+  p->batch_capacity = 0;
+  const int32_t groups = (nodes + kNodeGroup - 1) / kNodeGroup;
+  const size_t pairs = (size_t)groups * kNodeGroup * (size_t)(p->n > 0 ? p->n : 1);
+  auto alloc = [&](void** ptr, size_t bytes) -> int {
+    hipError_t e = hipMalloc(ptr, bytes > 0 ? bytes : 1);
+    if (e != hipSuccess)
+      return fail(PROP_ENOMEM, "batch workspace hipMalloc(%zu bytes): %s", bytes,
+                  hipGetErrorString(e));
+    p->batch_allocs.push_back(*ptr);
+    return PROP_OK;
+  };
+  Batch b{};
+  int rc;
+  if ((rc = alloc((void**)&b.A, pairs * sizeof(double2)))) return rc;
+  if ((rc = alloc((void**)&b.B, pairs * sizeof(double2)))) return rc;
+  if ((rc = alloc((void**)&b.partials,
+                  (size_t)(p->P.n_segs > 0 ? p->P.n_segs : 1) * nodes * sizeof(SegPartial))))
+    return rc;
+  if ((rc = alloc((void**)&b.active, nodes * sizeof(uint32_t)))) return rc;
+  if ((rc = alloc((void**)&b.status, nodes * sizeof(int32_t)))) return rc;
+  if ((rc = alloc((void**)&b.rounds, nodes * sizeof(int32_t)))) return rc;
+  if ((rc = alloc((void**)&b.changed, nodes * sizeof(uint32_t)))) return rc;
+  if ((rc = alloc((void**)&b.infeasible, nodes * sizeof(uint32_t)))) return rc;
+  if ((rc = alloc((void**)&b.invalid, nodes * sizeof(uint32_t)))) return rc;
+  if (hipHostMalloc((void**)&p->h_bstatus, nodes * sizeof(int32_t), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&p->h_brounds, nodes * sizeof(int32_t), hipHostMallocDefault) !=
+          hipSuccess)
+    return fail(PROP_ENOMEM, "pinned host allocation failed");
+  p->bt = b;
+  p->batch_capacity = nodes;
+  return PROP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -567,6 +618,71 @@ int prop_run(prop_problem* p, double* lb, double* ub, int32_t max_rounds, prop_r
     HIP_TRY(hipMemcpy(lb, p->d_stage_lb, bytes, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(ub, p->d_stage_ub, bytes, hipMemcpyDeviceToHost));
   }
+  return PROP_OK;
+}
+
+int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* d_ub,
+                          int32_t max_rounds, void* stream, prop_result* out) {
+  if (!p || !out) return fail(PROP_EINVAL, "NULL argument");
+  if (nodes < 1) return fail(PROP_EINVAL, "nodes < 1");
+  if (max_rounds < 0) return fail(PROP_EINVAL, "max_rounds < 0");
+  if (p->n > 0 && (!d_lb || !d_ub)) return fail(PROP_EINVAL, "bound arrays are NULL");
+  HIP_TRY(hipSetDevice(p->device));
+  int rc = ensure_batch(p, nodes);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Problem& P = p->P;
+  Batch bt = p->bt;
+  bt.nodes = nodes;
+  bt.groups = (nodes + kNodeGroup - 1) / kNodeGroup;
+  HIP_TRY(hipEventRecord(p->ev[0], s));
+  HIP_TRY(launch_init(P, s));
+  HIP_TRY(hipMemsetAsync(bt.invalid, 0, nodes * sizeof(uint32_t), s));
+  HIP_TRY(hipMemsetAsync(bt.infeasible, 0, nodes * sizeof(uint32_t), s));
+  HIP_TRY(launch_pack_batch(P, bt, d_lb, d_ub, s));
+  HIP_TRY(launch_start_batch(P, bt, max_rounds, s));
+  HIP_TRY(hipEventRecord(p->ev[1], s));
+  // rounds in batches; the done flag is read one batch behind (see the
+  // stream driver of single runs)
+  int slot = 0;
+  bool pending[2] = {false, false};
+  for (int r = 1; r <= max_rounds;) {
+    const int last = std::min(max_rounds, r + p->batch_rounds - 1);
+    for (; r <= last; ++r) HIP_TRY(launch_round_batch(P, bt, r, max_rounds, s));
+    HIP_TRY(hipMemcpyAsync(&p->h_done[slot], &P.ctrl->done, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(p->ev_batch[slot], s));
+    pending[slot] = true;
+    slot ^= 1;
+    if (pending[slot]) {
+      HIP_TRY(hipEventSynchronize(p->ev_batch[slot]));
+      pending[slot] = false;
+      if (p->h_done[slot] == 1) break;
+    }
+  }
+  HIP_TRY(hipEventRecord(p->ev[2], s));
+  HIP_TRY(launch_unpack_batch(P, bt, d_lb, d_ub, s));
+  HIP_TRY(hipMemcpyAsync(p->h_bstatus, bt.status, nodes * sizeof(int32_t), hipMemcpyDeviceToHost,
+                         s));
+  HIP_TRY(hipMemcpyAsync(p->h_brounds, bt.rounds, nodes * sizeof(int32_t), hipMemcpyDeviceToHost,
+                         s));
+  std::vector<uint32_t> invalid(nodes);
+  HIP_TRY(hipMemcpyAsync(invalid.data(), bt.invalid, nodes * sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(p->ev[3], s));
+  HIP_TRY(hipStreamSynchronize(s));
+  hipEventElapsedTime(&p->last_loop_ms, p->ev[1], p->ev[2]);
+  hipEventElapsedTime(&p->last_total_ms, p->ev[0], p->ev[3]);
+  p->kev_used = 0;
+  p->last_kernel_ms = 0.0;
+  for (int32_t k = 0; k < nodes; ++k)
+    if (invalid[k])
+      return fail(PROP_EINVAL, "node %d: a bound is NaN, +inf as lower, -inf as upper, or beyond 2^200", k);
+  for (int32_t k = 0; k < nodes; ++k) {
+    out[k].status = p->h_bstatus[k];
+    out[k].rounds = p->h_brounds[k];
+  }
+  g_error.clear();
   return PROP_OK;
 }
 

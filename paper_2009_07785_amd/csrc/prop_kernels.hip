@@ -219,13 +219,14 @@ __device__ __forceinline__ bool entry_wanted(const RowState& R, double a, double
 // Candidates of one entry (a, column word cw) with start-of-round bounds
 // (l, u); the column word holds the variable in bits 0-30 and its
 // integrality in bit 31.
+// `nxt` points at this node's first pair; variable j's pair is nxt[j * stride].
 __device__ __forceinline__ void entry_candidates(const Problem& P, const RowState& R, double a,
                                                  double l, double u, int32_t cw,
-                                                 double2* __restrict__ nxt) {
+                                                 double2* __restrict__ nxt, uint32_t stride) {
   bool dmin, dmax;
   entry_sides(R, a, l, u, cw, P.cont_rel_tol, dmin, dmax);
   if (!(dmin || dmax)) return;
-  const int32_t j = cw & kColMask;
+  const size_t j = (size_t)(cw & kColMask) * stride;
   const bool is_int = cw < 0;
   const double bmin = a > 0.0 ? l : u;
   const double bmax = a > 0.0 ? u : l;
@@ -274,17 +275,23 @@ __device__ __forceinline__ void entry_candidates(const Problem& P, const RowStat
 
 // ---------------------------------------------------------------------------
 // one chunk: activities and candidates for 64/K rows, K lanes per row
+//
+// Bound arrays are addressed as base[var * stride + node]: stride 1 for a
+// single problem, 8 for a batch (8 nodes share each variable's cache line).
+// The chunk's matrix data is loaded once and reused for every active node
+// of the group (bit t of node_mask).
 // ---------------------------------------------------------------------------
 template <int KLOG>
 __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd,
                                             const double2* __restrict__ cur,
-                                            double2* __restrict__ nxt) {
+                                            double2* __restrict__ nxt, uint32_t stride,
+                                            uint32_t node_mask) {
   const int lane = threadIdx.x & (kWave - 1);
   const int W = (cd.meta >> 8) & 0xff;
   const int nrows = (cd.meta >> 16) & 0xff;
   const int r = lane >> KLOG;
   const size_t base = (size_t)cd.off64 * kWave + lane;
-  double a[kMaxSteps], l[kMaxSteps], u[kMaxSteps];
+  double a[kMaxSteps];
   int32_t jj[kMaxSteps];
 #pragma unroll
   for (int w = 0; w < kMaxSteps; ++w) {
@@ -295,58 +302,64 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
       jj[w] = __builtin_nontemporal_load(P.cols + base + (size_t)w * kWave);
     }
   }
+  const bool row_ok = r < nrows;
+  const int row = cd.row0 + (row_ok ? r : 0);
+  const double lhs = P.lhs[row], rhs = P.rhs[row];
+  for (uint32_t mask = node_mask; mask; mask &= mask - 1) {
+    const uint32_t t = __builtin_ctz(mask);
+    double l[kMaxSteps], u[kMaxSteps];
 #pragma unroll
-  for (int w = 0; w < kMaxSteps; ++w) {
-    l[w] = 0.0;
-    u[w] = 0.0;
-    if (w < W && a[w] != 0.0) {
-      const double2 b = cur[jj[w] & kColMask];
-      l[w] = b.x;
-      u[w] = b.y;
+    for (int w = 0; w < kMaxSteps; ++w) {
+      l[w] = 0.0;
+      u[w] = 0.0;
+      if (w < W && a[w] != 0.0) {
+        const double2 b = cur[(size_t)(jj[w] & kColMask) * stride + t];
+        l[w] = b.x;
+        u[w] = b.y;
+      }
     }
+    DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
+    int cmin = 0, cmax = 0;
+#pragma unroll
+    for (int w = 0; w < kMaxSteps; ++w)
+      if (w < W) accumulate(a[w], l[w], u[w], smin, smax, cmin, cmax);
+    group_reduce<KLOG>(smin, smax, cmin, cmax);
+    if (!row_ok) continue;
+    const RowState R = make_row_state(smin, smax, cmin, cmax, lhs, rhs);
+    if (!(R.min_side || R.max_side)) continue;
+    // cheap filter first; the full candidate arithmetic runs only for the
+    // entries that pass it (a step no lane needs is skipped by the wave)
+#pragma unroll
+    for (int w = 0; w < kMaxSteps; ++w)
+      if (w < W && entry_wanted(R, a[w], l[w], u[w], jj[w], P.cont_rel_tol))
+        entry_candidates(P, R, a[w], l[w], u[w], jj[w], nxt + t, stride);
   }
-  DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
-  int cmin = 0, cmax = 0;
-#pragma unroll
-  for (int w = 0; w < kMaxSteps; ++w)
-    if (w < W) accumulate(a[w], l[w], u[w], smin, smax, cmin, cmax);
-  group_reduce<KLOG>(smin, smax, cmin, cmax);
-  if (r >= nrows) return;
-  const int row = cd.row0 + r;
-  const RowState R = make_row_state(smin, smax, cmin, cmax, P.lhs[row], P.rhs[row]);
-  if (!(R.min_side || R.max_side)) return;
-  // cheap filter first; the full candidate arithmetic runs only for the
-  // entries that pass it (a step no lane needs is skipped by the wave)
-#pragma unroll
-  for (int w = 0; w < kMaxSteps; ++w)
-    if (w < W && entry_wanted(R, a[w], l[w], u[w], jj[w], P.cont_rel_tol))
-      entry_candidates(P, R, a[w], l[w], u[w], jj[w], nxt);
 }
 
 __device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const double2* cur,
-                                               double2* nxt) {
+                                               double2* nxt, uint32_t stride,
+                                               uint32_t node_mask) {
   const ChunkDesc cd = P.chunks[c];
   switch (cd.meta & 7) {
-    case 0: chunk_round<0>(P, cd, cur, nxt); break;
-    case 1: chunk_round<1>(P, cd, cur, nxt); break;
-    case 2: chunk_round<2>(P, cd, cur, nxt); break;
-    case 3: chunk_round<3>(P, cd, cur, nxt); break;
-    case 4: chunk_round<4>(P, cd, cur, nxt); break;
-    case 5: chunk_round<5>(P, cd, cur, nxt); break;
-    default: chunk_round<6>(P, cd, cur, nxt); break;
+    case 0: chunk_round<0>(P, cd, cur, nxt, stride, node_mask); break;
+    case 1: chunk_round<1>(P, cd, cur, nxt, stride, node_mask); break;
+    case 2: chunk_round<2>(P, cd, cur, nxt, stride, node_mask); break;
+    case 3: chunk_round<3>(P, cd, cur, nxt, stride, node_mask); break;
+    case 4: chunk_round<4>(P, cd, cur, nxt, stride, node_mask); break;
+    case 5: chunk_round<5>(P, cd, cur, nxt, stride, node_mask); break;
+    default: chunk_round<6>(P, cd, cur, nxt, stride, node_mask); break;
   }
 }
 
 // ---------------------------------------------------------------------------
-// long rows
+// long rows: partials live at partials[segment * pstride + node]
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
-                                           const double2* __restrict__ cur) {
+                                           const double2* __restrict__ cur, uint32_t stride,
+                                           uint32_t node_mask, SegPartial* parts,
+                                           uint32_t pstride, uint32_t node0) {
   const int lane = threadIdx.x & (kWave - 1);
   const SegDesc sd = P.segs[s];
-  DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
-  int cmin = 0, cmax = 0;
-  double tmin = -0x1p-1074, tmax = -0x1p-1074;  // per-side skip thresholds
   double a[kMaxSteps];
   int32_t jj[kMaxSteps];
 #pragma unroll
@@ -359,50 +372,58 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
       jj[w] = __builtin_nontemporal_load(P.cols + sd.off + p);
     }
   }
+  for (uint32_t mask = node_mask; mask; mask &= mask - 1) {
+    const uint32_t t = __builtin_ctz(mask);
+    DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
+    int cmin = 0, cmax = 0;
+    double tmin = -0x1p-1074, tmax = -0x1p-1074;  // per-side skip thresholds
 #pragma unroll
-  for (int w = 0; w < kMaxSteps; ++w) {
-    if (a[w] != 0.0) {
-      const double2 b = cur[jj[w] & kColMask];
-      accumulate(a[w], b.x, b.y, smin, smax, cmin, cmax);
-      const bool is_int = jj[w] < 0, pos = a[w] > 0.0;
-      const double t1 = side_threshold(a[w], b.x, b.y, is_int, pos, P.cont_rel_tol);
-      const double t2 = side_threshold(a[w], b.x, b.y, is_int, !pos, P.cont_rel_tol);
-      tmin = t1 > tmin ? t1 : tmin;
-      tmax = t2 > tmax ? t2 : tmax;
+    for (int w = 0; w < kMaxSteps; ++w) {
+      if (a[w] != 0.0) {
+        const double2 b = cur[(size_t)(jj[w] & kColMask) * stride + t];
+        accumulate(a[w], b.x, b.y, smin, smax, cmin, cmax);
+        const bool is_int = jj[w] < 0, pos = a[w] > 0.0;
+        const double t1 = side_threshold(a[w], b.x, b.y, is_int, pos, P.cont_rel_tol);
+        const double t2 = side_threshold(a[w], b.x, b.y, is_int, !pos, P.cont_rel_tol);
+        tmin = t1 > tmin ? t1 : tmin;
+        tmax = t2 > tmax ? t2 : tmax;
+      }
     }
-  }
-  group_reduce<6>(smin, smax, cmin, cmax);
+    group_reduce<6>(smin, smax, cmin, cmax);
 #pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const double o1 = __shfl_xor(tmin, off, kWave);
-    const double o2 = __shfl_xor(tmax, off, kWave);
-    tmin = o1 > tmin ? o1 : tmin;
-    tmax = o2 > tmax ? o2 : tmax;
-  }
-  if (lane == 0) {
-    SegPartial q;
-    q.min_hi = smin.hi;
-    q.min_lo = smin.lo;
-    q.max_hi = smax.hi;
-    q.max_lo = smax.lo;
-    q.tmin = tmin;
-    q.tmax = tmax;
-    q.min_inf = cmin;
-    q.max_inf = cmax;
-    q.pad0 = q.pad1 = 0;
-    P.partials[s] = q;
+    for (int off = 1; off < kWave; off <<= 1) {
+      const double o1 = __shfl_xor(tmin, off, kWave);
+      const double o2 = __shfl_xor(tmax, off, kWave);
+      tmin = o1 > tmin ? o1 : tmin;
+      tmax = o2 > tmax ? o2 : tmax;
+    }
+    if (lane == 0) {
+      SegPartial q;
+      q.min_hi = smin.hi;
+      q.min_lo = smin.lo;
+      q.max_hi = smax.hi;
+      q.max_lo = smax.lo;
+      q.tmin = tmin;
+      q.tmax = tmax;
+      q.min_inf = cmin;
+      q.max_inf = cmax;
+      q.pad0 = q.pad1 = 0;
+      parts[(size_t)s * pstride + node0 + t] = q;
+    }
   }
 }
 
 __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
                                            const double2* __restrict__ cur,
-                                           double2* __restrict__ nxt) {
+                                           double2* __restrict__ nxt, uint32_t stride, uint32_t t,
+                                           const SegPartial* parts, uint32_t pstride,
+                                           uint32_t node) {
   const int lane = threadIdx.x & (kWave - 1);
   const SegDesc sd = P.segs[s];
   DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
   int cmin = 0, cmax = 0;
   for (int q = lane; q < sd.nseg; q += kWave) {
-    const SegPartial pp = P.partials[sd.first + q];
+    const SegPartial pp = parts[(size_t)(sd.first + q) * pstride + node];
     dd_add(smin, pp.min_hi, pp.min_lo);
     dd_add(smax, pp.max_hi, pp.max_lo);
     cmin += pp.min_inf;
@@ -410,7 +431,7 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
   }
   group_reduce<6>(smin, smax, cmin, cmax);
   const RowState R = make_row_state(smin, smax, cmin, cmax, P.lhs[sd.row], P.rhs[sd.row]);
-  const SegPartial own = P.partials[s];
+  const SegPartial own = parts[(size_t)s * pstride + node];
   bool need = false;
   if (R.min_side) need |= (R.cmin == 0) ? !(R.smn > own.tmin) : (own.min_inf > 0);
   if (R.max_side) need |= (R.cmax == 0) ? !((-R.smx) > own.tmax) : (own.max_inf > 0);
@@ -419,9 +440,9 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
     const double a = P.vals[sd.off + p];
     if (a == 0.0) continue;
     const int32_t cw = P.cols[sd.off + p];
-    const double2 b = cur[cw & kColMask];
+    const double2 b = cur[(size_t)(cw & kColMask) * stride + t];
     if (entry_wanted(R, a, b.x, b.y, cw, P.cont_rel_tol))
-      entry_candidates(P, R, a, b.x, b.y, cw, nxt);
+      entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride);
   }
 }
 
@@ -635,11 +656,12 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Problem P, int max_rounds
   if (u32_load(&C->done)) return;
 
   for (int r = 1; r <= max_rounds; ++r) {
-    for (int c = gwave; c < P.n_chunks; c += nwaves) chunk_dispatch(P, c, A, B);
+    for (int c = gwave; c < P.n_chunks; c += nwaves) chunk_dispatch(P, c, A, B, 1, 1);
     if (P.n_segs) {
-      for (int s = gwave; s < P.n_segs; s += nwaves) seg_phase1(P, s, A);
+      for (int s = gwave; s < P.n_segs; s += nwaves) seg_phase1(P, s, A, 1, 1, P.partials, 1, 0);
       if (!grid_barrier(P, kActNone, r, max_rounds)) return;
-      for (int s = gwave; s < P.n_segs; s += nwaves) seg_phase2(P, s, A, B);
+      for (int s = gwave; s < P.n_segs; s += nwaves)
+        seg_phase2(P, s, A, B, 1, 0, P.partials, 1, 0);
     }
     if (!grid_barrier(P, kActNone, r, max_rounds)) return;
     uint32_t changed = 0, infeasible = 0;
@@ -663,15 +685,16 @@ __global__ __launch_bounds__(kBlock) void k_round(Problem P) {
   if (u32_load(&P.ctrl->done)) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = blockIdx.x * kWavesPerBlock + wave;
-  if (item < P.n_segs) seg_phase1(P, item, P.bnd[0]);
-  else if (item - P.n_segs < P.n_chunks) chunk_dispatch(P, item - P.n_segs, P.bnd[0], P.bnd[1]);
+  if (item < P.n_segs) seg_phase1(P, item, P.bnd[0], 1, 1, P.partials, 1, 0);
+  else if (item - P.n_segs < P.n_chunks)
+    chunk_dispatch(P, item - P.n_segs, P.bnd[0], P.bnd[1], 1, 1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_round_long(Problem P) {
   if (u32_load(&P.ctrl->done)) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int s = blockIdx.x * kWavesPerBlock + wave;
-  if (s < P.n_segs) seg_phase2(P, s, P.bnd[0], P.bnd[1]);
+  if (s < P.n_segs) seg_phase2(P, s, P.bnd[0], P.bnd[1], 1, 0, P.partials, 1, 0);
 }
 
 // Commit of round r; the last block to finish decides the status.
@@ -692,6 +715,192 @@ __global__ __launch_bounds__(kBlock) void k_commit(Problem P, int r, int max_rou
       __hip_atomic_store(&C->commit_word, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
+}
+
+
+// ---------------------------------------------------------------------------
+// batched nodes (one problem, many bound vectors): every node runs exactly
+// the arithmetic of a single run; nodes that finished are masked out
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t group_mask(const Batch& Bt, int g) {
+  uint32_t mask = 0;
+#pragma unroll
+  for (int t = 0; t < kNodeGroup; ++t) {
+    const int k = g * kNodeGroup + t;
+    if (k < Bt.nodes && Bt.active[k]) mask |= 1u << t;
+  }
+  return mask;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_batch(Problem P, Batch Bt,
+                                                       const double* __restrict__ ulb,
+                                                       const double* __restrict__ uub) {
+  const size_t total = (size_t)Bt.nodes * P.n;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int k = (int)(i / (size_t)P.n);
+    const int v = (int)(i - (size_t)k * P.n);
+    double l = ulb[i], u = uub[i];
+    const bool bad = __builtin_isnan(l) || __builtin_isnan(u) || l == __builtin_inf() ||
+                     u == -__builtin_inf() ||
+                     (!is_inf(l) && __builtin_fabs(l) > PROP_HUGE) ||
+                     (!is_inf(u) && __builtin_fabs(u) > PROP_HUGE);
+    if (bad) __hip_atomic_store(&Bt.invalid[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t j = P.perm[v];
+    const bool is_int = P.vtype[j] != 0;
+    if (is_int) {
+      l = __builtin_ceil(l - P.eps_int);
+      u = __builtin_floor(u + P.eps_int);
+    }
+    l = l + 0.0;
+    u = u + 0.0;
+    const size_t dst = ((size_t)(k / kNodeGroup) * P.n + j) * kNodeGroup + (k % kNodeGroup);
+    const double2 b = make_double2(l, u);
+    Bt.A[dst] = b;
+    Bt.B[dst] = b;
+    if (domain_empty(is_int, l, u, P.feas_tol))
+      __hip_atomic_store(&Bt.infeasible[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_unpack_batch(Problem P, Batch Bt,
+                                                         double* __restrict__ ulb,
+                                                         double* __restrict__ uub) {
+  const size_t total = (size_t)Bt.nodes * P.n;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int k = (int)(i / (size_t)P.n);
+    const int v = (int)(i - (size_t)k * P.n);
+    const size_t src =
+        ((size_t)(k / kNodeGroup) * P.n + P.perm[v]) * kNodeGroup + (k % kNodeGroup);
+    const double2 b = Bt.A[src];
+    ulb[i] = b.x;
+    uub[i] = b.y;
+  }
+}
+
+// Block-wide count of active nodes after a status update; sets ctrl->done.
+__device__ __forceinline__ void batch_set_done(const Problem& P, uint32_t my_active) {
+  uint32_t dummy = 0;
+  block_sum2(my_active, dummy);
+  if (threadIdx.x == 0) P.ctrl->done = my_active == 0 ? 1u : 0u;
+}
+
+// One block: round-0 decision per node.
+__global__ __launch_bounds__(kBlock) void k_start_batch(Problem P, Batch Bt, int max_rounds) {
+  uint32_t act = 0;
+  for (int k = threadIdx.x; k < Bt.nodes; k += blockDim.x) {
+    uint32_t a = 0;
+    if (Bt.invalid[k] || Bt.infeasible[k] || P.instance_infeasible) {
+      Bt.status[k] = kInfeasible;
+    } else if (max_rounds == 0) {
+      Bt.status[k] = kMaxRounds;
+    } else {
+      Bt.status[k] = kMaxRounds;
+      a = 1;
+    }
+    Bt.rounds[k] = 0;
+    Bt.active[k] = a;
+    Bt.changed[k] = 0;
+    Bt.infeasible[k] = 0;
+    act += a;
+  }
+  batch_set_done(P, act);
+}
+
+__global__ __launch_bounds__(kBlock) void k_round_batch(Problem P, Batch Bt) {
+  if (u32_load(&P.ctrl->done)) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  const int unit = (int)(wid / Bt.groups);
+  const int g = (int)(wid - (int64_t)unit * Bt.groups);
+  if (unit >= P.n_segs + P.n_chunks) return;
+  const uint32_t mask = group_mask(Bt, g);
+  if (!mask) return;
+  const size_t base = (size_t)g * P.n * kNodeGroup;
+  if (unit < P.n_segs)
+    seg_phase1(P, unit, Bt.A + base, kNodeGroup, mask, Bt.partials, Bt.nodes, g * kNodeGroup);
+  else
+    chunk_dispatch(P, unit - P.n_segs, Bt.A + base, Bt.B + base, kNodeGroup, mask);
+}
+
+__global__ __launch_bounds__(kBlock) void k_round_long_batch(Problem P, Batch Bt) {
+  if (u32_load(&P.ctrl->done)) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  const int s = (int)(wid / Bt.nodes);
+  const int k = (int)(wid - (int64_t)s * Bt.nodes);
+  if (s >= P.n_segs || !Bt.active[k]) return;
+  const size_t base = (size_t)(k / kNodeGroup) * P.n * kNodeGroup;
+  seg_phase2(P, s, Bt.A + base, Bt.B + base, kNodeGroup, k % kNodeGroup, Bt.partials, Bt.nodes,
+             k);
+}
+
+// Commit per (variable, node) of group blockIdx.y, with per-node counts.
+__global__ __launch_bounds__(kBlock) void k_commit_batch(Problem P, Batch Bt) {
+  if (u32_load(&P.ctrl->done)) return;
+  __shared__ uint32_t ch[kNodeGroup], inf[kNodeGroup];
+  if (threadIdx.x < kNodeGroup) {
+    ch[threadIdx.x] = 0;
+    inf[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  const int g = blockIdx.y;
+  const uint32_t mask = group_mask(Bt, g);
+  if (mask) {
+    double2* A = Bt.A + (size_t)g * P.n * kNodeGroup;
+    const double2* B = Bt.B + (size_t)g * P.n * kNodeGroup;
+    const size_t total = (size_t)P.n * kNodeGroup;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+      const uint32_t t = (uint32_t)(e % kNodeGroup);
+      if (!((mask >> t) & 1u)) continue;
+      const double2 a = A[e];
+      const double2 b = B[e];
+      if (a.x != b.x || a.y != b.y) {
+        A[e] = b;
+        atomicAdd(&ch[t], 1u);
+        if (domain_empty(P.vtype[e / kNodeGroup] != 0, b.x, b.y, P.feas_tol)) inf[t] = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kNodeGroup) {
+    const int k = g * kNodeGroup + threadIdx.x;
+    if (ch[threadIdx.x])
+      __hip_atomic_fetch_add(&Bt.changed[k], ch[threadIdx.x], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    if (inf[threadIdx.x])
+      __hip_atomic_store(&Bt.infeasible[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// One block: per-node status after round r.
+__global__ __launch_bounds__(kBlock) void k_end_batch(Problem P, Batch Bt, int r,
+                                                      int max_rounds) {
+  if (u32_load(&P.ctrl->done)) return;
+  uint32_t act = 0;
+  for (int k = threadIdx.x; k < Bt.nodes; k += blockDim.x) {
+    if (!Bt.active[k]) continue;
+    uint32_t a = 0;
+    if (Bt.infeasible[k]) {
+      Bt.status[k] = kInfeasible;
+      Bt.rounds[k] = r;
+    } else if (Bt.changed[k] == 0) {
+      Bt.status[k] = kConverged;
+      Bt.rounds[k] = r;
+    } else if (r >= max_rounds) {
+      Bt.status[k] = kMaxRounds;
+      Bt.rounds[k] = r;
+    } else {
+      a = 1;
+    }
+    Bt.active[k] = a;
+    Bt.changed[k] = 0;
+    Bt.infeasible[k] = 0;
+    act += a;
+  }
+  batch_set_done(P, act);
 }
 
 // ---------------------------------------------------------------------------
@@ -749,6 +958,41 @@ hipError_t launch_round(const Problem& P, int r, int max_rounds, hipStream_t s, 
   // at most 65535 blocks: the packed commit counter keeps 16 bits per field
   hipLaunchKernelGGL(k_commit, dim3(blocks_for(P.n, kBlock, 1024)), dim3(kBlock), 0, s, P, r,
                      max_rounds);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_batch(const Problem& P, const Batch& Bt, const double* lb, const double* ub,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_batch, dim3(blocks_for((int64_t)Bt.nodes * P.n, kBlock, 16384)),
+                     dim3(kBlock), 0, s, P, Bt, lb, ub);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_batch(const Problem& P, const Batch& Bt, double* lb, double* ub,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack_batch, dim3(blocks_for((int64_t)Bt.nodes * P.n, kBlock, 16384)),
+                     dim3(kBlock), 0, s, P, Bt, lb, ub);
+  return hipGetLastError();
+}
+
+hipError_t launch_start_batch(const Problem& P, const Batch& Bt, int max_rounds, hipStream_t s) {
+  hipLaunchKernelGGL(k_start_batch, dim3(1), dim3(kBlock), 0, s, P, Bt, max_rounds);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_batch(const Problem& P, const Batch& Bt, int r, int max_rounds,
+                              hipStream_t s) {
+  const int64_t waves = (int64_t)(P.n_chunks + P.n_segs) * Bt.groups;
+  hipLaunchKernelGGL(k_round_batch, dim3(blocks_for(waves, kWavesPerBlock, 1 << 30)),
+                     dim3(kBlock), 0, s, P, Bt);
+  if (P.n_segs)
+    hipLaunchKernelGGL(k_round_long_batch,
+                       dim3(blocks_for((int64_t)P.n_segs * Bt.nodes, kWavesPerBlock, 1 << 30)),
+                       dim3(kBlock), 0, s, P, Bt);
+  hipLaunchKernelGGL(k_commit_batch,
+                     dim3(blocks_for((int64_t)P.n * kNodeGroup, kBlock, 256), Bt.groups),
+                     dim3(kBlock), 0, s, P, Bt);
+  hipLaunchKernelGGL(k_end_batch, dim3(1), dim3(kBlock), 0, s, P, Bt, r, max_rounds);
   return hipGetLastError();
 }
 

@@ -18,4 +18,14 @@ hipError_t launch_start(const Problem& P, int max_rounds, hipStream_t s);
 hipError_t launch_round(const Problem& P, int r, int max_rounds, hipStream_t s, hipEvent_t e0,
                         hipEvent_t e1);
 
+// Batched nodes: pack / unpack the caller's node-major arrays, and the
+// per-round kernels (matrix, long rows, commit, per-node status).
+hipError_t launch_pack_batch(const Problem& P, const Batch& Bt, const double* lb, const double* ub,
+                             hipStream_t s);
+hipError_t launch_unpack_batch(const Problem& P, const Batch& Bt, double* lb, double* ub,
+                               hipStream_t s);
+hipError_t launch_start_batch(const Problem& P, const Batch& Bt, int max_rounds, hipStream_t s);
+hipError_t launch_round_batch(const Problem& P, const Batch& Bt, int r, int max_rounds,
+                              hipStream_t s);
+
 }  // namespace prop

@@ -107,4 +107,23 @@ struct Problem {
   double eps_int, cont_rel_tol, feas_tol;
 };
 
+// Batch of branch-and-bound nodes sharing one problem.  Bounds of node
+// k = 8 g + t for variable j sit at A[(g * n + j) * 8 + t]: the 8 nodes of a
+// group share each variable's 128-byte line.
+constexpr int kNodeGroup = 8;
+
+struct Batch {
+  double2* A;              // start-of-round bounds, [groups][n][8]
+  double2* B;              // candidate targets, same layout
+  SegPartial* partials;    // [segments][nodes]
+  uint32_t* active;        // [nodes] still propagating
+  int32_t* status;         // [nodes]
+  int32_t* rounds;         // [nodes]
+  uint32_t* changed;       // [nodes] pairs changed in the current round
+  uint32_t* infeasible;    // [nodes] empty domain seen
+  uint32_t* invalid;       // [nodes] bound failed validation
+  int32_t nodes;
+  int32_t groups;
+};
+
 }  // namespace prop

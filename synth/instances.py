@@ -19,7 +19,8 @@ Workloads (sizes and distributions):
            law and each row's distinct columns drawn in proportion to them;
            40% binary / 30% integer / 30% continuous.
   config3  1,000,000 x 500,000 matrix drawn as config2, plus 256 node bound
-           vectors, each fixing 1-5% of the integer variables.
+           vectors, each fixing 1-5% of the integer variables (to x0, or in a
+           quarter of the nodes to random values).
   config4  64 instances of log-uniform size in [1e4, 2e6] rows drawn as
            config1, plus a Poisson request stream fixing 0-5% of the vars.
 """
@@ -278,26 +279,28 @@ def config3_matrix(m: int = 1_000_000, n: int = 500_000) -> Instance:
     return _powerlaw_instance(rng, m, n, f"config3[{m}x{n}]")
 
 
-def node_bounds(inst: Instance, seed: int, frac_lo=0.01, frac_hi=0.05, only_int=True):
-    """Root bounds with a random fraction of the variables fixed: integer
-    variables to x0_j or to a uniform integer in their range (50/50),
-    continuous ones (when included) to x0_j."""
+def node_bounds(inst: Instance, seed: int, frac_lo=0.01, frac_hi=0.05, only_int=True,
+                random_share=0.25):
+    """Root bounds with a random fraction of the variables fixed.  A node
+    either fixes every chosen variable to its x0 value (x0 stays feasible) or,
+    with probability `random_share`, fixes the chosen integer variables to
+    uniform integers in their range (such nodes are usually infeasible);
+    continuous variables, when included, are fixed to x0_j."""
     rng = _rng(seed)
     lb = inst.lb.copy()
     ub = inst.ub.copy()
     frac = rng.uniform(frac_lo, frac_hi)
+    random_node = rng.random() < random_share
     pool = np.nonzero(inst.vartype == 1)[0] if only_int else np.arange(inst.n)
     k = int(round(frac * pool.size))
     if k == 0:
         return lb, ub
     pick = rng.choice(pool, size=k, replace=False)
     is_int = inst.vartype[pick] == 1
-    use_x0 = rng.random(k) < 0.5
     lo = np.where(np.isfinite(lb[pick]), lb[pick], -1e3)
     hi = np.where(np.isfinite(ub[pick]), ub[pick], 1e3)
-    rand_int = np.floor(lo + rng.random(k) * (hi - lo + 1.0))
-    rand_int = np.minimum(rand_int, hi)
-    val = np.where(is_int & ~use_x0, rand_int, inst.x0[pick])
+    rand_int = np.minimum(np.floor(lo + rng.random(k) * (hi - lo + 1.0)), hi)
+    val = np.where(is_int & random_node, rand_int, inst.x0[pick])
     lb[pick] = val
     ub[pick] = val
     return lb, ub
@@ -338,7 +341,9 @@ def config4_requests(pool, rate: float = 2000.0, duration: float = 60.0, seed_of
 
 
 def request_bounds(inst: Instance, node_seed: int):
-    return node_bounds(inst, node_seed, frac_lo=0.0, frac_hi=0.05, only_int=False)
+    """A serving request: 0-5% of all variables fixed to their x0 values."""
+    return node_bounds(inst, node_seed, frac_lo=0.0, frac_hi=0.05, only_int=False,
+                       random_share=0.0)
 
 
 def random_small(seed: int, m: int, n: int, max_len: int = 6, int_frac: float = 1.0,

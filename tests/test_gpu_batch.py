@@ -1,0 +1,111 @@
+"""Batched nodes on the GPU: every node of a batch must give bitwise the
+status, rounds and bounds of its own single run (and therefore of the
+oracle, checked directly on the smaller cases)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lib(torch_cuda):
+    from paper_2009_07785_amd import binding
+
+    return binding
+
+
+def node_set(inst, count, seed0, frac_hi=0.05, only_int=True):
+    lbs = np.empty((count, inst.n))
+    ubs = np.empty((count, inst.n))
+    for k in range(count):
+        lbs[k], ubs[k] = synth.node_bounds(inst, seed0 + k, frac_hi=frac_hi, only_int=only_int)
+    return lbs, ubs
+
+
+def run_batch(torch, p, lbs, ubs, max_rounds=100):
+    d_lb = torch.tensor(lbs, dtype=torch.float64, device="cuda")
+    d_ub = torch.tensor(ubs, dtype=torch.float64, device="cuda")
+    res = p.run_batch_device(d_lb, d_ub, max_rounds)
+    return res, d_lb.cpu().numpy(), d_ub.cpu().numpy()
+
+
+def check_batch_vs_single(torch, lib, inst, lbs, ubs, max_rounds=100, with_oracle=False):
+    with lib.Problem.from_instance(inst) as p:
+        res, blb, bub = run_batch(torch, p, lbs, ubs, max_rounds)
+        statuses = set()
+        for k in range(lbs.shape[0]):
+            r1, lb1, ub1 = p.run(lbs[k], ubs[k], max_rounds)
+            assert (res[k].status, res[k].rounds) == (r1.status, r1.rounds), (inst.name, k)
+            statuses.add(r1.status)
+            if r1.status != oracle.INFEASIBLE:
+                assert np.array_equal(blb[k], lb1) and np.array_equal(bub[k], ub1), (inst.name, k)
+            if with_oracle:
+                ref = oracle.run(inst, lbs[k], ubs[k], max_rounds)
+                assert (ref.status, ref.rounds) == (r1.status, r1.rounds), (inst.name, k)
+                if ref.status != oracle.INFEASIBLE:
+                    assert np.array_equal(ref.lb, lb1) and np.array_equal(ref.ub, ub1)
+    return statuses
+
+
+def test_batch_config0(torch_cuda, lib):
+    inst = synth.config0()
+    lbs, ubs = node_set(inst, 20, 11_000, frac_hi=0.2)
+    statuses = check_batch_vs_single(torch_cuda, lib, inst, lbs, ubs, with_oracle=True)
+    assert oracle.CONVERGED in statuses
+
+
+def test_batch_ragged_group_and_long_rows(torch_cuda, lib):
+    """13 nodes (not a multiple of the 8-node group), rows of every class."""
+    inst = synth.layout_mix(1)
+    lbs, ubs = node_set(inst, 13, 12_000, frac_hi=0.1, only_int=False)
+    check_batch_vs_single(torch_cuda, lib, inst, lbs, ubs, with_oracle=True)
+
+
+def test_batch_mixed_outcomes(torch_cuda, lib):
+    """Nodes that converge, hit the round limit and are infeasible at rounds
+    0 and 1, all in one batch."""
+    inst = synth.config0(1)
+    lbs, ubs = node_set(inst, 9, 13_000, frac_hi=0.3)
+    # node 0: the root; node 1: an empty input domain
+    lbs[0], ubs[0] = inst.lb, inst.ub
+    ivar = int(np.nonzero(inst.vartype == 1)[0][0])
+    lbs[1][ivar], ubs[1][ivar] = 5.0, 4.0
+    statuses = check_batch_vs_single(torch_cuda, lib, inst, lbs, ubs, max_rounds=3)
+    assert oracle.MAX_ROUNDS in statuses and oracle.INFEASIBLE in statuses
+
+
+def test_batch_medium(torch_cuda, lib):
+    inst = synth.config3_matrix(100_000, 50_000)
+    lbs, ubs = node_set(inst, 37, 14_000)
+    check_batch_vs_single(torch_cuda, lib, inst, lbs, ubs)
+
+
+def test_batch_reuse_and_invalid(torch_cuda, lib):
+    torch = torch_cuda
+    inst = synth.config0(2)
+    lbs, ubs = node_set(inst, 16, 15_000)
+    with lib.Problem.from_instance(inst) as p:
+        a, alb, aub = run_batch(torch, p, lbs, ubs)
+        b, blb, bub = run_batch(torch, p, lbs[:5], ubs[:5])  # smaller batch, same workspace
+        for k in range(5):
+            assert (a[k].status, a[k].rounds) == (b[k].status, b[k].rounds)
+            assert np.array_equal(alb[k], blb[k]) and np.array_equal(aub[k], bub[k])
+        bad = lbs.copy()
+        bad[3, 7] = np.nan
+        with pytest.raises(lib.PropError) as e:
+            run_batch(torch, p, bad, ubs)
+        assert e.value.code == lib.EINVAL
+        c, clb, cub = run_batch(torch, p, lbs, ubs)  # still usable
+        assert [(r.status, r.rounds) for r in c] == [(r.status, r.rounds) for r in a]
