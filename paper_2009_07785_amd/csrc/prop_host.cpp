@@ -364,6 +364,11 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   double2 *b0, *b1;
   if ((rc = dev_alloc(p, &b0, (size_t)n))) return rc;
   if ((rc = dev_alloc(p, &b1, (size_t)n))) return rc;
+  // hot variables: the leading relabelled ones with degree >= kHotDegree
+  int32_t n_hot = 0;
+  while (n_hot < n && n_hot < kMaxHot && deg[order[n_hot]] >= kHotDegree) ++n_hot;
+  double2* stripes;
+  if ((rc = dev_alloc(p, &stripes, (size_t)kStripes * (n_hot > 0 ? n_hot : 1)))) return rc;
   Ctrl* d_ctrl;
   if ((rc = dev_alloc(p, &d_ctrl, 1))) return rc;
   HIP_TRY(hipMemset(d_ctrl, 0, sizeof(Ctrl)));
@@ -385,6 +390,8 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   P.instance_infeasible = p->instance_infeasible ? 1 : 0;
   P.bnd[0] = b0;
   P.bnd[1] = b1;
+  P.stripes = stripes;
+  P.n_hot = n_hot;
   P.ctrl = d_ctrl;
   P.eps_int = p->params.eps_int;
   P.cont_rel_tol = p->params.cont_rel_tol;

@@ -220,13 +220,20 @@ __device__ __forceinline__ bool entry_wanted(const RowState& R, double a, double
 // (l, u); the column word holds the variable in bits 0-30 and its
 // integrality in bit 31.
 // `nxt` points at this node's first pair; variable j's pair is nxt[j * stride].
+// With `striped`, variables below P.n_hot write to this block's stripe copy.
 __device__ __forceinline__ void entry_candidates(const Problem& P, const RowState& R, double a,
                                                  double l, double u, int32_t cw,
-                                                 double2* __restrict__ nxt, uint32_t stride) {
+                                                 double2* __restrict__ nxt, uint32_t stride,
+                                                 bool striped) {
   bool dmin, dmax;
   entry_sides(R, a, l, u, cw, P.cont_rel_tol, dmin, dmax);
   if (!(dmin || dmax)) return;
-  const size_t j = (size_t)(cw & kColMask) * stride;
+  const int32_t var = cw & kColMask;
+  size_t j = (size_t)var * stride;
+  if (striped && var < P.n_hot) {
+    nxt = P.stripes + (size_t)(blockIdx.x % kStripes) * P.n_hot;
+    j = (size_t)var;
+  }
   const bool is_int = cw < 0;
   const double bmin = a > 0.0 ? l : u;
   const double bmax = a > 0.0 ? u : l;
@@ -332,7 +339,7 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
 #pragma unroll
     for (int w = 0; w < kMaxSteps; ++w)
       if (w < W && entry_wanted(R, a[w], l[w], u[w], jj[w], P.cont_rel_tol))
-        entry_candidates(P, R, a[w], l[w], u[w], jj[w], nxt + t, stride);
+        entry_candidates(P, R, a[w], l[w], u[w], jj[w], nxt + t, stride, stride == 1);
   }
 }
 
@@ -442,7 +449,7 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
     const int32_t cw = P.cols[sd.off + p];
     const double2 b = cur[(size_t)(cw & kColMask) * stride + t];
     if (entry_wanted(R, a, b.x, b.y, cw, P.cont_rel_tol))
-      entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride);
+      entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride, stride == 1);
   }
 }
 
@@ -457,12 +464,30 @@ __device__ __forceinline__ uint32_t u32_load(const uint32_t* p) {
 __device__ __forceinline__ void commit_range(const Problem& P, uint32_t tid, uint32_t nthreads,
                                              uint32_t& changed, uint32_t& infeasible) {
   double2* A = P.bnd[0];
-  const double2* B = P.bnd[1];
+  double2* B = P.bnd[1];
   for (uint32_t v = tid; v < (uint32_t)P.n; v += nthreads) {
     const double2 a = A[v];
-    const double2 b = B[v];
+    double2 b;
+    if (v < (uint32_t)P.n_hot) {
+      // a hot variable's candidates sit in its stripe copies (B is not a
+      // target for it): merge them into the committed pair, reset them
+      b = a;
+      double2* st = P.stripes + v;
+#pragma unroll 8
+      for (int c = 0; c < kStripes; ++c) {
+        const double2 q = st[(size_t)c * P.n_hot];
+        b.x = q.x > b.x ? q.x : b.x;
+        b.y = q.y < b.y ? q.y : b.y;
+      }
+#pragma unroll 8
+      for (int c = 0; c < kStripes; ++c)
+        st[(size_t)c * P.n_hot] = make_double2(-__builtin_inf(), __builtin_inf());
+    } else {
+      b = B[v];
+    }
     if (a.x != b.x || a.y != b.y) {
       A[v] = b;
+      B[v] = b;
       ++changed;
       if (domain_empty(P.vtype[v] != 0, b.x, b.y, P.feas_tol)) infeasible = 1;
     }
@@ -628,6 +653,13 @@ __global__ __launch_bounds__(kBlock) void k_pack(Problem P, const double* __rest
     if (domain_empty(is_int, l, u, P.feas_tol))
       __hip_atomic_store(&P.ctrl->infeasible, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reset_stripes(Problem P) {
+  const size_t total = (size_t)kStripes * P.n_hot;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
+    P.stripes[i] = make_double2(-__builtin_inf(), __builtin_inf());
 }
 
 __global__ __launch_bounds__(kBlock) void k_unpack(Problem P, double* __restrict__ ulb,
@@ -920,6 +952,9 @@ hipError_t launch_init(const Problem& P, hipStream_t s) {
 
 hipError_t launch_pack(const Problem& P, const double* lb, const double* ub, hipStream_t s) {
   hipLaunchKernelGGL(k_pack, dim3(blocks_for(P.n, kBlock, 4096)), dim3(kBlock), 0, s, P, lb, ub);
+  if (P.n_hot)
+    hipLaunchKernelGGL(k_reset_stripes, dim3(blocks_for((int64_t)kStripes * P.n_hot, kBlock, 1024)),
+                       dim3(kBlock), 0, s, P);
   return hipGetLastError();
 }
 

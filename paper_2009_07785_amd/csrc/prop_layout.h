@@ -37,6 +37,15 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 // the variable's integrality in bit 31.
 constexpr int32_t kColMask = 0x7fffffff;
 
+// Candidates for the most used variables (relabelled to 0 .. n_hot-1) go
+// to kStripes copies of their bound pairs, copy = block index mod kStripes,
+// instead of one shared pair; the commit merges the copies.  Rows of a
+// power-law matrix send tens of thousands of candidates to one such
+// variable in a round, and same-address atomics serialise.
+constexpr int kStripes = 64;
+constexpr int kMaxHot = 8192;
+constexpr int kHotDegree = 512;
+
 // run outcome codes (match PROP_CONVERGED / PROP_INFEASIBLE / PROP_MAX_ROUNDS)
 constexpr int kConverged = 0;
 constexpr int kInfeasible = 1;
@@ -102,6 +111,9 @@ struct Problem {
   int32_t instance_infeasible;
   // state: bnd[0] = start-of-round bounds, bnd[1] = candidate target
   double2* bnd[2];
+  double2* stripes;         // [kStripes][n_hot] candidate targets of hot variables
+  int32_t n_hot;
+  int32_t pad_hot;
   Ctrl* ctrl;
   // parameters
   double eps_int, cont_rel_tol, feas_tol;

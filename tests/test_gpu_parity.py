@@ -98,6 +98,19 @@ def test_layout_mix(lib, seed):
     assert ref.status == oracle.CONVERGED
 
 
+def test_powerlaw_hot_variables(lib):
+    """Power-law columns: dozens of variables above the degree at which the
+    kernels spread their candidate targets over stripe copies."""
+    inst = synth.config3_matrix(50_000, 25_000)
+    deg = np.bincount(inst.col_idx, minlength=inst.n)
+    assert (deg >= 512).sum() >= 10
+    ref = check_against_oracle(lib, inst)
+    assert ref.rounds >= 3  # slow continuous convergence: the root hits the round limit
+    nodes = [synth.node_bounds(inst, 21_000 + k) for k in range(4)]
+    for lb, ub in nodes:
+        check_against_oracle(lib, inst, lb=lb, ub=ub, loops=("stream",))
+
+
 def test_random_small(lib):
     for s in range(40):
         inst = synth.random_small(s, m=int(3 + s % 9), n=int(3 + s % 7), box=6,
