@@ -88,6 +88,13 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched branch-and-bound node comparison")
     ap.add_argument("--batch-nodes", type=int, default=256)
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving leg (open-loop requests over 64 resident instances)")
+    ap.add_argument("--serving-scale", type=float, default=0.1,
+                    help="row-count scale of the 64 serving instances (1.0 = ~360M nnz)")
+    ap.add_argument("--serving-seconds", type=float, default=5.0)
+    ap.add_argument("--serving-rate", type=float, default=2000.0, help="requests per second")
+    ap.add_argument("--serving-budget-gib", type=float, default=16.0)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_config2.json"),
                     help="HBM traffic per launch measured with rocprofv3 counters (JSON)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -209,6 +216,11 @@ def main():
 
     batch = None if args.no_batch else batched_nodes(args.batch_nodes, args.max_rounds)
 
+    serve = None
+    if not args.no_serving:
+        serve = serving(args.serving_scale, args.serving_seconds, args.serving_rate,
+                        int(args.serving_budget_gib * (1 << 30)))
+
     base = cpu_baseline(inst, args.no_cpu_baseline)
 
     out = {
@@ -250,6 +262,7 @@ def main():
         },
         "round_loops": loops,
         "batched": batch,
+        "serving": serve,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)
@@ -330,6 +343,97 @@ def batched_nodes(count: int, max_rounds: int):
     }
     log(f"batched nodes: {out}")
     prob.close()
+    return out
+
+
+def serving(scale: float, seconds: float, rate: float, budget: int, variants: int = 8,
+            max_rounds: int = 50):
+    """Open-loop serving: Poisson arrivals at `rate` per second for `seconds`,
+    each request a bound vector (0-5% of all variables fixed to a feasible
+    point's values) on one of 64 resident instances drawn uniformly.  Every
+    result is compared bitwise with the same request run alone; latency is
+    the server's (submission to result ready)."""
+    import threading
+
+    import numpy as np
+
+    import synth
+    from paper_2009_07785_amd import Problem, binding
+
+    log(f"generating the 64 serving instances (scale {scale})")
+    t0 = time.perf_counter()
+    pool = synth.config4_pool(scale=scale)
+    probs = [Problem.from_instance(i) for i in pool]
+    total_nnz = int(sum(i.nnz for i in pool))
+    log(f"serving pool ready: {total_nnz} nnz in {time.perf_counter() - t0:.1f} s")
+    # `variants` distinct requests per instance; arrivals pick one by seed
+    bounds = [[synth.request_bounds(inst, 1000 * k + v) for v in range(variants)]
+              for k, inst in enumerate(pool)]
+    alone = [[probs[k].run(lb, ub, max_rounds) for lb, ub in bounds[k]]
+             for k in range(len(pool))]
+    arrivals = synth.config4_requests(pool, rate=rate, duration=seconds)
+    log(f"{len(arrivals)} arrivals over {seconds} s; alone results ready")
+
+    srv = binding.Server(budget, max_slots=256)
+    for p in probs:
+        srv.add_instance(p)
+    # warm the server: one request per instance
+    for k in range(len(pool)):
+        lb, ub = bounds[k][0]
+        t = srv.submit(k, lb, ub, max_rounds)
+        srv.wait(t, pool[k].n, timeout_ms=60_000)
+    srv.reset_stats()
+
+    tickets = []
+    lag = [0.0]
+
+    def producer():
+        start = time.perf_counter()
+        for (ta, k, seed) in arrivals:
+            now = time.perf_counter() - start
+            if ta > now:
+                time.sleep(ta - now)
+            else:
+                lag[0] = max(lag[0], now - ta)
+            v = seed % variants
+            lb, ub = bounds[k][v]
+            tickets.append((srv.submit(k, lb, ub, max_rounds), k, v))
+
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    ok = 0
+    for t, k, v in tickets:
+        res, lb, ub = srv.wait(t, pool[k].n, timeout_ms=120_000)
+        r1, lb1, ub1 = alone[k][v]
+        same = (res.status, res.rounds) == (r1.status, r1.rounds) and (
+            r1.status == 1 or (np.array_equal(lb, lb1) and np.array_equal(ub, ub1)))
+        ok += bool(same)
+    st = srv.stats()
+    srv.close()
+    for p in probs:
+        p.close()
+    rounds = [r[0].rounds for row in alone for r in row]
+    out = {
+        "workload": f"config4: 64 instances at row scale {scale} ({total_nnz} nnz resident), "
+                    f"open-loop Poisson {rate:g} req/s for {seconds:g} s, 0-5% of the variables "
+                    f"fixed per request, max_rounds {max_rounds}",
+        "requests": len(tickets),
+        "completed": st["completed"],
+        "req_per_s": st["req_per_s"],
+        "p50_ms": st["p50_ms"],
+        "p99_ms": st["p99_ms"],
+        "mean_ms": st["mean_ms"],
+        "max_ms": st["max_ms"],
+        "verified_fraction": ok / max(1, len(tickets)),
+        "verified_against": "the same request run alone (prop_run), bitwise",
+        "alone_rounds_mean": float(np.mean(rounds)),
+        "submit_lag_max_ms": lag[0] * 1e3,
+        "peak_device_bytes": st["peak_device_bytes"],
+        "budget_bytes": budget,
+        "round_steps": st["steps"],
+    }
+    log(f"serving: {out}")
     return out
 
 

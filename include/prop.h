@@ -64,6 +64,7 @@ extern "C" {
 #define PROP_EINVAL (-1)  /* invalid argument or input outside the domain above */
 #define PROP_ENOMEM (-2)  /* device or host allocation failed */
 #define PROP_EDEVICE (-3) /* HIP runtime error, no usable GPU, or device timeout */
+#define PROP_EBUSY (-4)   /* serving: the request queue is full */
 
 /* vartype values */
 #define PROP_CONTINUOUS 0
@@ -169,6 +170,95 @@ int prop_last_kernel_timing(const prop_problem* p, double* ms, int32_t* launches
 
 /* Releases the problem (NULL is allowed). */
 void prop_destroy(prop_problem* p);
+
+/* ------------------------------------------------------------------------
+ * Serving: many propagation requests over resident problems.
+ *
+ * A request is one bound vector (a node of a search, a what-if query) to be
+ * propagated on a problem added to the server.  Requests on the same problem
+ * share its node slots, laid out as by prop_run_batch_device, and run with
+ * continuous batching: a request enters a free slot at the next round
+ * boundary of its problem, advances one round per round of that problem,
+ * and leaves when it converges, becomes infeasible or reaches its own round
+ * limit, while the other requests keep running.  Each request's status,
+ * rounds and bounds are bitwise those prop_run returns for the same problem
+ * and input.
+ *
+ * Admission by device-memory footprint: slots come in groups of 8, each
+ * group holding 384 * n bytes (start-of-round and candidate bound pairs,
+ * and the request's input/output staging); groups are allocated when a
+ * request finds no free slot and the budget has room, and idle groups are
+ * released when another problem needs the room.  Each added problem also
+ * holds 28 * max_slots bytes of per-slot state plus 64 * max_slots bytes
+ * per long-row segment.  A request waits in its problem's queue (first in,
+ * first out) while neither a slot nor room is available.
+ *
+ * One host thread per server schedules; each problem's work is queued on a
+ * HIP stream of its own (default priority), so problems overlap on the
+ * device.  The server reads only a problem's matrix and keeps its own
+ * control state: prop_run calls on an added problem stay allowed, from one
+ * thread at a time as always.  Destroy the server before its problems.
+ * Server calls are thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct prop_server prop_server; /* opaque */
+
+typedef struct {
+  int64_t budget_bytes;    /* device bytes for slot groups and per-problem state, > 0 */
+  int32_t max_slots;       /* slots per problem, a multiple of 8 (0: 256) */
+  int32_t rounds_per_step; /* rounds queued between status reads (0: 2) */
+  int32_t max_pending;     /* requests held (queued, running or unread) before
+                              prop_srv_submit returns PROP_EBUSY (0: 1 << 20) */
+} prop_srv_config;
+
+typedef struct {
+  int64_t submitted;          /* accepted by prop_srv_submit */
+  int64_t completed;          /* results ready */
+  int64_t queued;             /* waiting for a slot */
+  int64_t running;            /* in a slot */
+  int64_t device_bytes;       /* device memory the server holds now */
+  int64_t peak_device_bytes;  /* most it has held */
+  int64_t steps;              /* round steps queued over all problems */
+  double p50_ms, p99_ms;      /* latency, submission to result ready */
+  double mean_ms, max_ms;
+  double wall_s;              /* first submission to last completion */
+  double req_per_s;           /* completed / wall_s */
+} prop_srv_stats;
+
+/* Starts a server (and its scheduler thread; no device work yet). */
+int prop_srv_create(const prop_srv_config* cfg, prop_server** out);
+
+/* Makes problem p servable under the id stored in *id (0, 1, ...).  The
+ * problem must outlive the server.  Returns PROP_ENOMEM when its per-problem
+ * state does not fit the remaining budget. */
+int prop_srv_add_instance(prop_server* s, prop_problem* p, int32_t* id);
+
+/* Queues a request: lb[n], ub[n] (host, copied before the call returns;
+ * the caller keeps them) under the input domain of prop_run, and a round
+ * limit >= 0.  Stores a ticket in *ticket.  PROP_EINVAL for an unknown id
+ * or an invalid bound, PROP_ENOMEM when one slot group of the problem
+ * cannot fit the budget at all, PROP_EBUSY when max_pending requests are
+ * held. */
+int prop_srv_submit(prop_server* s, int32_t id, const double* lb, const double* ub,
+                    int32_t max_rounds, int64_t* ticket);
+
+/* Returns 1 and fills *out, lb[n], ub[n] (host, caller-owned; either may be
+ * NULL to skip it) when the request has finished, releasing the ticket; 0
+ * while it is pending; a negative code for an unknown ticket or when the
+ * server failed (the request is then lost). */
+int prop_srv_poll(prop_server* s, int64_t ticket, prop_result* out, double* lb, double* ub);
+
+/* As prop_srv_poll, waiting up to timeout_ms milliseconds (< 0: no limit). */
+int prop_srv_wait(prop_server* s, int64_t ticket, int32_t timeout_ms, prop_result* out, double* lb,
+                  double* ub);
+
+/* Counters and latency percentiles since the server started or the last
+ * prop_srv_reset_stats. */
+int prop_srv_get_stats(prop_server* s, prop_srv_stats* out);
+int prop_srv_reset_stats(prop_server* s);
+
+/* Stops the scheduler, waits for queued device work and releases the
+ * server's memory (NULL is allowed).  Unread results are discarded. */
+void prop_srv_destroy(prop_server* s);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char* prop_last_error(void);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libprop.so")
 
 CONVERGED, INFEASIBLE, MAX_ROUNDS = 0, 1, 2
 STATUS_NAMES = {CONVERGED: "CONVERGED", INFEASIBLE: "INFEASIBLE", MAX_ROUNDS: "MAX_ROUNDS"}
-OK, EINVAL, ENOMEM, EDEVICE = 0, -1, -2, -3
+OK, EINVAL, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4
 LOOP_PERSISTENT, LOOP_STREAM, LOOP_HOST = 0, 1, 2
 LOOP_NAMES = {"persistent": LOOP_PERSISTENT, "stream": LOOP_STREAM, "host": LOOP_HOST}
 
@@ -26,7 +26,9 @@ LOOP_NAMES = {"persistent": LOOP_PERSISTENT, "stream": LOOP_STREAM, "host": LOOP
 EXPORTED = ("prop_create", "prop_run", "prop_run_device", "prop_run_batch_device",
             "prop_set_loop", "prop_get_info",
             "prop_last_timing", "prop_set_kernel_timing", "prop_last_kernel_timing",
-            "prop_destroy", "prop_last_error")
+            "prop_destroy", "prop_last_error",
+            "prop_srv_create", "prop_srv_add_instance", "prop_srv_submit", "prop_srv_poll",
+            "prop_srv_wait", "prop_srv_get_stats", "prop_srv_reset_stats", "prop_srv_destroy")
 
 
 class PropError(RuntimeError):
@@ -56,6 +58,21 @@ class _Info(ctypes.Structure):
                 ("n_long_rows", ctypes.c_int32), ("n_segments", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("alg_bytes_round", ctypes.c_int64)]
+
+
+class _SrvConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("rounds_per_step", ctypes.c_int32), ("max_pending", ctypes.c_int32)]
+
+
+class _SrvStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("peak_device_bytes", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("wall_s", ctypes.c_double),
+                ("req_per_s", ctypes.c_double)]
 
 
 def _load():
@@ -97,6 +114,23 @@ def _load():
     lib.prop_destroy.restype = None
     lib.prop_last_error.argtypes = []
     lib.prop_last_error.restype = ctypes.c_char_p
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.prop_srv_create.argtypes = [ctypes.POINTER(_SrvConfig), ctypes.POINTER(P)]
+    lib.prop_srv_create.restype = ctypes.c_int
+    lib.prop_srv_add_instance.argtypes = [P, P, ctypes.POINTER(i32)]
+    lib.prop_srv_add_instance.restype = ctypes.c_int
+    lib.prop_srv_submit.argtypes = [P, i32, P, P, i32, i64p]
+    lib.prop_srv_submit.restype = ctypes.c_int
+    lib.prop_srv_poll.argtypes = [P, ctypes.c_int64, ctypes.POINTER(_Result), P, P]
+    lib.prop_srv_poll.restype = ctypes.c_int
+    lib.prop_srv_wait.argtypes = [P, ctypes.c_int64, i32, ctypes.POINTER(_Result), P, P]
+    lib.prop_srv_wait.restype = ctypes.c_int
+    lib.prop_srv_get_stats.argtypes = [P, ctypes.POINTER(_SrvStats)]
+    lib.prop_srv_get_stats.restype = ctypes.c_int
+    lib.prop_srv_reset_stats.argtypes = [P]
+    lib.prop_srv_reset_stats.restype = ctypes.c_int
+    lib.prop_srv_destroy.argtypes = [P]
+    lib.prop_srv_destroy.restype = None
     return lib
 
 
@@ -265,4 +299,92 @@ def create_raw(csr_args, lhs, rhs, vartype, params=None):
     h = ctypes.c_void_p()
     rc = lib.prop_create(ctypes.byref(csr), _ptr(lh), _ptr(rh), _ptr(vt), ctypes.byref(prm),
                          ctypes.byref(h))
+    return rc, h
+
+
+class Server:
+    """Continuous-batching server over problems resident on the device
+    (prop_srv_* in the C ABI).  Problems added must outlive the server."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 0, rounds_per_step: int = 0,
+                 max_pending: int = 0):
+        self._h = None
+        cfg = _SrvConfig(int(budget_bytes), int(max_slots), int(rounds_per_step),
+                         int(max_pending))
+        h = ctypes.c_void_p()
+        _check(lib.prop_srv_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._n = []          # n of each added problem
+        self._problems = []   # keeps the problems alive while the server is
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib.prop_srv_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def add_instance(self, problem: Problem) -> int:
+        i = ctypes.c_int32()
+        _check(lib.prop_srv_add_instance(self._h, problem._h, ctypes.byref(i)))
+        self._n.append(problem.n)
+        self._problems.append(problem)
+        return i.value
+
+    def submit(self, inst: int, lb, ub, max_rounds: int = 100) -> int:
+        lb = np.ascontiguousarray(lb, dtype=np.float64)
+        ub = np.ascontiguousarray(ub, dtype=np.float64)
+        n = self._n[inst] if 0 <= inst < len(self._n) else -1
+        if lb.shape != (n,) or ub.shape != (n,):
+            if n >= 0:
+                raise ValueError("bounds must have shape (n,) of the instance")
+        t = ctypes.c_int64()
+        _check(lib.prop_srv_submit(self._h, int(inst), _ptr(lb), _ptr(ub), int(max_rounds),
+                                   ctypes.byref(t)))
+        return t.value
+
+    def _take(self, fn, ticket, *extra, n):
+        lb = np.empty(n)
+        ub = np.empty(n)
+        res = _Result()
+        rc = fn(self._h, ctypes.c_int64(ticket), *extra, ctypes.byref(res), _ptr(lb), _ptr(ub))
+        if rc < 0:
+            raise PropError(rc, last_error())
+        if rc == 0:
+            return None
+        return RunResult(res.status, res.rounds), lb, ub
+
+    def poll(self, ticket: int, n: int):
+        """(RunResult, lb, ub) once finished (releasing the ticket), else None.
+        n is the instance's variable count."""
+        return self._take(lib.prop_srv_poll, ticket, n=n)
+
+    def wait(self, ticket: int, n: int, timeout_ms: int = -1):
+        return self._take(lib.prop_srv_wait, ticket, ctypes.c_int32(int(timeout_ms)), n=n)
+
+    def stats(self) -> dict:
+        st = _SrvStats()
+        _check(lib.prop_srv_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _SrvStats._fields_}
+
+    def reset_stats(self):
+        _check(lib.prop_srv_reset_stats(self._h))
+
+
+def srv_create_raw(budget_bytes, max_slots=0, rounds_per_step=0, max_pending=0):
+    """Calls prop_srv_create; returns (rc, handle).  For tests of argument
+    checks, which need no device."""
+    cfg = _SrvConfig(int(budget_bytes), int(max_slots), int(rounds_per_step), int(max_pending))
+    h = ctypes.c_void_p()
+    rc = lib.prop_srv_create(ctypes.byref(cfg), ctypes.byref(h))
     return rc, h

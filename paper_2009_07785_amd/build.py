@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libprop.so")
-SOURCES = ["prop_kernels.hip", "prop_host.cpp"]
+SOURCES = ["prop_kernels.hip", "prop_host.cpp", "prop_serve.cpp"]
 ARCH = "gfx950"
 
 
@@ -29,7 +29,7 @@ def build(verbose: bool = False) -> str:
         # vector register tuple makes every guarded step copy the whole tuple
         "-mllvm", "-amdgpu-promote-alloca-to-vector-limit=1",
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-Wall", "-Wno-unused-function",
+        "-Wall", "-Wno-unused-function", "-pthread",
         "-I", os.path.join(os.path.dirname(HERE), "include"),
         *[os.path.join(CSRC, s) for s in SOURCES],
         "-o", tmp,

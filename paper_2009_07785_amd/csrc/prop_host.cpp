@@ -14,12 +14,13 @@
 #include <vector>
 
 #include "prop.h"
+#include "prop_handle.h"
 #include "prop_launch.h"
 #include "prop_layout.h"
 
 using namespace prop;
 
-namespace {
+namespace prop {
 
 thread_local std::string g_error;
 
@@ -33,13 +34,9 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                                    \
-  do {                                                                                   \
-    hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail(e_ == hipErrorOutOfMemory ? PROP_ENOMEM : PROP_EDEVICE, "%s: %s", #expr, \
-                  hipGetErrorString(e_));                                                \
-  } while (0)
+}  // namespace prop
+
+namespace {
 
 const double kHugeValue = std::ldexp(1.0, 200);
 const double kCoefMin = std::ldexp(1.0, -64);
@@ -58,39 +55,6 @@ struct DevBuf {
 };
 
 }  // namespace
-
-struct prop_problem {
-  int device = 0;
-  int32_t m = 0, n = 0;
-  int64_t nnz = 0, nnz_stored = 0;
-  int32_t n_long_rows = 0;
-  int grid = 0;
-  int loop_mode = PROP_LOOP_STREAM;
-  bool instance_infeasible = false;
-  prop_params params{1e-6, 1e-6, 1e-6};
-  Problem P{};
-  // device allocations
-  std::vector<void*> allocs;
-  int64_t device_bytes = 0;
-  double* d_stage_lb = nullptr;  // staging for prop_run (host arrays)
-  double* d_stage_ub = nullptr;
-  Ctrl* h_ctrl = nullptr;        // pinned host copy of the control block
-  uint32_t* h_done = nullptr;    // pinned done flags of the stream driver's batches
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t ev_batch[2] = {nullptr, nullptr};
-  int batch_rounds = 4;          // rounds queued per batch by the stream driver
-  bool kernel_timing = false;    // events around every round-kernel launch
-  std::vector<hipEvent_t> kev;   // kev[2r], kev[2r+1] bracket round r's matrix kernel
-  int kev_used = 0;              // rounds bracketed in the last run
-  double last_kernel_ms = 0.0;
-  float last_loop_ms = 0.f, last_total_ms = 0.f;
-  // batch workspace (grown on demand, kept until destroy)
-  Batch bt{};
-  int32_t batch_capacity = 0;
-  std::vector<void*> batch_allocs;
-  int32_t* h_bstatus = nullptr;  // pinned copies of per-node status / rounds
-  int32_t* h_brounds = nullptr;
-};
 
 namespace {
 
@@ -490,8 +454,23 @@ int ensure_batch(prop_problem* p, int32_t nodes) {
   };
   Batch b{};
   int rc;
-  if ((rc = alloc((void**)&b.A, pairs * sizeof(double2)))) return rc;
-  if ((rc = alloc((void**)&b.B, pairs * sizeof(double2)))) return rc;
+  double2 *A = nullptr, *B = nullptr;
+  double2** tables = nullptr;
+  if ((rc = alloc((void**)&A, pairs * sizeof(double2)))) return rc;
+  if ((rc = alloc((void**)&B, pairs * sizeof(double2)))) return rc;
+  if ((rc = alloc((void**)&tables, 2 * (size_t)groups * sizeof(double2*)))) return rc;
+  {
+    // group g's [n][8] block starts at g * n * 8 in the two pair arrays
+    std::vector<double2*> h((size_t)2 * groups);
+    const size_t per_group = (size_t)kNodeGroup * (size_t)(p->n > 0 ? p->n : 1);
+    for (int32_t g = 0; g < groups; ++g) {
+      h[g] = A + g * per_group;
+      h[groups + g] = B + g * per_group;
+    }
+    HIP_TRY(hipMemcpy(tables, h.data(), h.size() * sizeof(double2*), hipMemcpyHostToDevice));
+    b.gA = tables;
+    b.gB = tables + groups;
+  }
   if ((rc = alloc((void**)&b.partials,
                   (size_t)(p->P.n_segs > 0 ? p->P.n_segs : 1) * nodes * sizeof(SegPartial))))
     return rc;
@@ -501,6 +480,9 @@ int ensure_batch(prop_problem* p, int32_t nodes) {
   if ((rc = alloc((void**)&b.changed, nodes * sizeof(uint32_t)))) return rc;
   if ((rc = alloc((void**)&b.infeasible, nodes * sizeof(uint32_t)))) return rc;
   if ((rc = alloc((void**)&b.invalid, nodes * sizeof(uint32_t)))) return rc;
+  if ((rc = alloc((void**)&b.maxr, nodes * sizeof(int32_t)))) return rc;
+  HIP_TRY(hipMemset(b.invalid, 0, nodes * sizeof(uint32_t)));
+  HIP_TRY(hipMemset(b.infeasible, 0, nodes * sizeof(uint32_t)));
   if (hipHostMalloc((void**)&p->h_bstatus, nodes * sizeof(int32_t), hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc((void**)&p->h_brounds, nodes * sizeof(int32_t), hipHostMallocDefault) !=
@@ -646,8 +628,8 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
   HIP_TRY(launch_init(P, s));
   HIP_TRY(hipMemsetAsync(bt.invalid, 0, nodes * sizeof(uint32_t), s));
   HIP_TRY(hipMemsetAsync(bt.infeasible, 0, nodes * sizeof(uint32_t), s));
-  HIP_TRY(launch_pack_batch(P, bt, d_lb, d_ub, s));
-  HIP_TRY(launch_start_batch(P, bt, max_rounds, s));
+  HIP_TRY(launch_pack_batch(P, bt, d_lb, d_ub, 0, nodes, s));
+  HIP_TRY(launch_start_batch(P, bt, max_rounds, 0, nodes, true, s));
   HIP_TRY(hipEventRecord(p->ev[1], s));
   // rounds in batches; the done flag is read one batch behind (see the
   // stream driver of single runs)
@@ -655,7 +637,7 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
   bool pending[2] = {false, false};
   for (int r = 1; r <= max_rounds;) {
     const int last = std::min(max_rounds, r + p->batch_rounds - 1);
-    for (; r <= last; ++r) HIP_TRY(launch_round_batch(P, bt, r, max_rounds, s));
+    for (; r <= last; ++r) HIP_TRY(launch_round_batch(P, bt, s));
     HIP_TRY(hipMemcpyAsync(&p->h_done[slot], &P.ctrl->done, sizeof(uint32_t),
                            hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(p->ev_batch[slot], s));
@@ -668,14 +650,11 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
     }
   }
   HIP_TRY(hipEventRecord(p->ev[2], s));
-  HIP_TRY(launch_unpack_batch(P, bt, d_lb, d_ub, s));
+  HIP_TRY(launch_unpack_batch(P, bt, d_lb, d_ub, 0, nodes, s));
   HIP_TRY(hipMemcpyAsync(p->h_bstatus, bt.status, nodes * sizeof(int32_t), hipMemcpyDeviceToHost,
                          s));
   HIP_TRY(hipMemcpyAsync(p->h_brounds, bt.rounds, nodes * sizeof(int32_t), hipMemcpyDeviceToHost,
                          s));
-  std::vector<uint32_t> invalid(nodes);
-  HIP_TRY(hipMemcpyAsync(invalid.data(), bt.invalid, nodes * sizeof(uint32_t),
-                         hipMemcpyDeviceToHost, s));
   HIP_TRY(hipEventRecord(p->ev[3], s));
   HIP_TRY(hipStreamSynchronize(s));
   hipEventElapsedTime(&p->last_loop_ms, p->ev[1], p->ev[2]);
@@ -683,7 +662,7 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
   p->kev_used = 0;
   p->last_kernel_ms = 0.0;
   for (int32_t k = 0; k < nodes; ++k)
-    if (invalid[k])
+    if (p->h_bstatus[k] == kInvalidInput)
       return fail(PROP_EINVAL, "node %d: a bound is NaN, +inf as lower, -inf as upper, or beyond 2^200", k);
   for (int32_t k = 0; k < nodes; ++k) {
     out[k].status = p->h_bstatus[k];

@@ -81,10 +81,13 @@ __device__ __forceinline__ void dd_add(DD& s, double yhi, double ylo) {
 
 __device__ __forceinline__ double dd_value(const DD& s) { return (s.hi + s.lo) + 0.0; }
 
-template <int KLOG>
-__device__ __forceinline__ void group_reduce(DD& smin, DD& smax, int& cmin, int& cmax) {
+// Combines the partial sums of the 2^klog lanes of each row (klog is the
+// same in every lane of the wave, so the branches are uniform).
+__device__ __forceinline__ void group_reduce(DD& smin, DD& smax, int& cmin, int& cmax, int klog) {
 #pragma unroll
-  for (int off = 1; off < (1 << KLOG); off <<= 1) {
+  for (int i = 0; i < 6; ++i) {
+    if (i >= klog) break;
+    const int off = 1 << i;
     double a = __shfl_xor(smin.hi, off, kWave);
     double b = __shfl_xor(smin.lo, off, kWave);
     double c = __shfl_xor(smax.hi, off, kWave);
@@ -288,15 +291,15 @@ __device__ __forceinline__ void entry_candidates(const Problem& P, const RowStat
 // The chunk's matrix data is loaded once and reused for every active node
 // of the group (bit t of node_mask).
 // ---------------------------------------------------------------------------
-template <int KLOG>
 __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd,
                                             const double2* __restrict__ cur,
                                             double2* __restrict__ nxt, uint32_t stride,
                                             uint32_t node_mask) {
   const int lane = threadIdx.x & (kWave - 1);
+  const int klog = cd.meta & 7;
   const int W = (cd.meta >> 8) & 0xff;
   const int nrows = (cd.meta >> 16) & 0xff;
-  const int r = lane >> KLOG;
+  const int r = lane >> klog;
   const size_t base = (size_t)cd.off64 * kWave + lane;
   double a[kMaxSteps];
   int32_t jj[kMaxSteps];
@@ -330,7 +333,7 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
 #pragma unroll
     for (int w = 0; w < kMaxSteps; ++w)
       if (w < W) accumulate(a[w], l[w], u[w], smin, smax, cmin, cmax);
-    group_reduce<KLOG>(smin, smax, cmin, cmax);
+    group_reduce(smin, smax, cmin, cmax, klog);
     if (!row_ok) continue;
     const RowState R = make_row_state(smin, smax, cmin, cmax, lhs, rhs);
     if (!(R.min_side || R.max_side)) continue;
@@ -346,16 +349,7 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
 __device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const double2* cur,
                                                double2* nxt, uint32_t stride,
                                                uint32_t node_mask) {
-  const ChunkDesc cd = P.chunks[c];
-  switch (cd.meta & 7) {
-    case 0: chunk_round<0>(P, cd, cur, nxt, stride, node_mask); break;
-    case 1: chunk_round<1>(P, cd, cur, nxt, stride, node_mask); break;
-    case 2: chunk_round<2>(P, cd, cur, nxt, stride, node_mask); break;
-    case 3: chunk_round<3>(P, cd, cur, nxt, stride, node_mask); break;
-    case 4: chunk_round<4>(P, cd, cur, nxt, stride, node_mask); break;
-    case 5: chunk_round<5>(P, cd, cur, nxt, stride, node_mask); break;
-    default: chunk_round<6>(P, cd, cur, nxt, stride, node_mask); break;
-  }
+  chunk_round(P, P.chunks[c], cur, nxt, stride, node_mask);
 }
 
 // ---------------------------------------------------------------------------
@@ -396,7 +390,7 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
         tmax = t2 > tmax ? t2 : tmax;
       }
     }
-    group_reduce<6>(smin, smax, cmin, cmax);
+    group_reduce(smin, smax, cmin, cmax, 6);
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
       const double o1 = __shfl_xor(tmin, off, kWave);
@@ -436,7 +430,7 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
     cmin += pp.min_inf;
     cmax += pp.max_inf;
   }
-  group_reduce<6>(smin, smax, cmin, cmax);
+  group_reduce(smin, smax, cmin, cmax, 6);
   const RowState R = make_row_state(smin, smax, cmin, cmax, P.lhs[sd.row], P.rhs[sd.row]);
   const SegPartial own = parts[(size_t)s * pstride + node];
   bool need = false;
@@ -764,14 +758,17 @@ __device__ __forceinline__ uint32_t group_mask(const Batch& Bt, int g) {
   return mask;
 }
 
+// Packs nodes [k0, k0 + cnt) from node-major arrays (row q = node k0 + q).
 __global__ __launch_bounds__(kBlock) void k_pack_batch(Problem P, Batch Bt,
                                                        const double* __restrict__ ulb,
-                                                       const double* __restrict__ uub) {
-  const size_t total = (size_t)Bt.nodes * P.n;
+                                                       const double* __restrict__ uub, int k0,
+                                                       int cnt) {
+  const size_t total = (size_t)cnt * P.n;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    const int k = (int)(i / (size_t)P.n);
-    const int v = (int)(i - (size_t)k * P.n);
+    const int q = (int)(i / (size_t)P.n);
+    const int k = k0 + q;
+    const int v = (int)(i - (size_t)q * P.n);
     double l = ulb[i], u = uub[i];
     const bool bad = __builtin_isnan(l) || __builtin_isnan(u) || l == __builtin_inf() ||
                      u == -__builtin_inf() ||
@@ -786,26 +783,28 @@ __global__ __launch_bounds__(kBlock) void k_pack_batch(Problem P, Batch Bt,
     }
     l = l + 0.0;
     u = u + 0.0;
-    const size_t dst = ((size_t)(k / kNodeGroup) * P.n + j) * kNodeGroup + (k % kNodeGroup);
+    const size_t dst = (size_t)j * kNodeGroup + (k % kNodeGroup);
     const double2 b = make_double2(l, u);
-    Bt.A[dst] = b;
-    Bt.B[dst] = b;
+    Bt.gA[k / kNodeGroup][dst] = b;
+    Bt.gB[k / kNodeGroup][dst] = b;
     if (domain_empty(is_int, l, u, P.feas_tol))
       __hip_atomic_store(&Bt.infeasible[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
+// Unpacks nodes [k0, k0 + cnt) into node-major arrays (row q = node k0 + q).
 __global__ __launch_bounds__(kBlock) void k_unpack_batch(Problem P, Batch Bt,
                                                          double* __restrict__ ulb,
-                                                         double* __restrict__ uub) {
-  const size_t total = (size_t)Bt.nodes * P.n;
+                                                         double* __restrict__ uub, int k0,
+                                                         int cnt) {
+  const size_t total = (size_t)cnt * P.n;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    const int k = (int)(i / (size_t)P.n);
-    const int v = (int)(i - (size_t)k * P.n);
-    const size_t src =
-        ((size_t)(k / kNodeGroup) * P.n + P.perm[v]) * kNodeGroup + (k % kNodeGroup);
-    const double2 b = Bt.A[src];
+    const int q = (int)(i / (size_t)P.n);
+    const int k = k0 + q;
+    const int v = (int)(i - (size_t)q * P.n);
+    const size_t src = (size_t)P.perm[v] * kNodeGroup + (k % kNodeGroup);
+    const double2 b = Bt.gA[k / kNodeGroup][src];
     ulb[i] = b.x;
     uub[i] = b.y;
   }
@@ -818,12 +817,17 @@ __device__ __forceinline__ void batch_set_done(const Problem& P, uint32_t my_act
   if (threadIdx.x == 0) P.ctrl->done = my_active == 0 ? 1u : 0u;
 }
 
-// One block: round-0 decision per node.
-__global__ __launch_bounds__(kBlock) void k_start_batch(Problem P, Batch Bt, int max_rounds) {
+// One block: round-0 decision for nodes [k0, k0 + cnt); with `whole`, the
+// done flag reflects the whole batch, otherwise it is cleared (a node joins
+// a running batch).
+__global__ __launch_bounds__(kBlock) void k_start_batch(Problem P, Batch Bt, int max_rounds,
+                                                        int k0, int cnt, int whole) {
   uint32_t act = 0;
-  for (int k = threadIdx.x; k < Bt.nodes; k += blockDim.x) {
+  for (int k = k0 + threadIdx.x; k < k0 + cnt; k += blockDim.x) {
     uint32_t a = 0;
-    if (Bt.invalid[k] || Bt.infeasible[k] || P.instance_infeasible) {
+    if (Bt.invalid[k]) {
+      Bt.status[k] = kInvalidInput;
+    } else if (Bt.infeasible[k] || P.instance_infeasible) {
       Bt.status[k] = kInfeasible;
     } else if (max_rounds == 0) {
       Bt.status[k] = kMaxRounds;
@@ -832,12 +836,15 @@ __global__ __launch_bounds__(kBlock) void k_start_batch(Problem P, Batch Bt, int
       a = 1;
     }
     Bt.rounds[k] = 0;
+    Bt.maxr[k] = max_rounds;
     Bt.active[k] = a;
     Bt.changed[k] = 0;
     Bt.infeasible[k] = 0;
+    Bt.invalid[k] = 0;
     act += a;
   }
-  batch_set_done(P, act);
+  if (whole) batch_set_done(P, act);
+  else if (threadIdx.x == 0) P.ctrl->done = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_round_batch(Problem P, Batch Bt) {
@@ -849,11 +856,10 @@ __global__ __launch_bounds__(kBlock) void k_round_batch(Problem P, Batch Bt) {
   if (unit >= P.n_segs + P.n_chunks) return;
   const uint32_t mask = group_mask(Bt, g);
   if (!mask) return;
-  const size_t base = (size_t)g * P.n * kNodeGroup;
   if (unit < P.n_segs)
-    seg_phase1(P, unit, Bt.A + base, kNodeGroup, mask, Bt.partials, Bt.nodes, g * kNodeGroup);
+    seg_phase1(P, unit, Bt.gA[g], kNodeGroup, mask, Bt.partials, Bt.nodes, g * kNodeGroup);
   else
-    chunk_dispatch(P, unit - P.n_segs, Bt.A + base, Bt.B + base, kNodeGroup, mask);
+    chunk_dispatch(P, unit - P.n_segs, Bt.gA[g], Bt.gB[g], kNodeGroup, mask);
 }
 
 __global__ __launch_bounds__(kBlock) void k_round_long_batch(Problem P, Batch Bt) {
@@ -863,9 +869,8 @@ __global__ __launch_bounds__(kBlock) void k_round_long_batch(Problem P, Batch Bt
   const int s = (int)(wid / Bt.nodes);
   const int k = (int)(wid - (int64_t)s * Bt.nodes);
   if (s >= P.n_segs || !Bt.active[k]) return;
-  const size_t base = (size_t)(k / kNodeGroup) * P.n * kNodeGroup;
-  seg_phase2(P, s, Bt.A + base, Bt.B + base, kNodeGroup, k % kNodeGroup, Bt.partials, Bt.nodes,
-             k);
+  const int g = k / kNodeGroup;
+  seg_phase2(P, s, Bt.gA[g], Bt.gB[g], kNodeGroup, k % kNodeGroup, Bt.partials, Bt.nodes, k);
 }
 
 // Commit per (variable, node) of group blockIdx.y, with per-node counts.
@@ -880,8 +885,8 @@ __global__ __launch_bounds__(kBlock) void k_commit_batch(Problem P, Batch Bt) {
   const int g = blockIdx.y;
   const uint32_t mask = group_mask(Bt, g);
   if (mask) {
-    double2* A = Bt.A + (size_t)g * P.n * kNodeGroup;
-    const double2* B = Bt.B + (size_t)g * P.n * kNodeGroup;
+    double2* A = Bt.gA[g];
+    const double2* B = Bt.gB[g];
     const size_t total = (size_t)P.n * kNodeGroup;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
@@ -907,23 +912,23 @@ __global__ __launch_bounds__(kBlock) void k_commit_batch(Problem P, Batch Bt) {
   }
 }
 
-// One block: per-node status after round r.
-__global__ __launch_bounds__(kBlock) void k_end_batch(Problem P, Batch Bt, int r,
-                                                      int max_rounds) {
+// One block: per-node status after the round each active node just ran
+// (node k's own round count: nodes may have joined at different times).
+__global__ __launch_bounds__(kBlock) void k_end_batch(Problem P, Batch Bt) {
   if (u32_load(&P.ctrl->done)) return;
   uint32_t act = 0;
   for (int k = threadIdx.x; k < Bt.nodes; k += blockDim.x) {
     if (!Bt.active[k]) continue;
+    const int r = Bt.rounds[k] + 1;
+    const int max_rounds = Bt.maxr[k];
     uint32_t a = 0;
+    Bt.rounds[k] = r;
     if (Bt.infeasible[k]) {
       Bt.status[k] = kInfeasible;
-      Bt.rounds[k] = r;
     } else if (Bt.changed[k] == 0) {
       Bt.status[k] = kConverged;
-      Bt.rounds[k] = r;
     } else if (r >= max_rounds) {
       Bt.status[k] = kMaxRounds;
-      Bt.rounds[k] = r;
     } else {
       a = 1;
     }
@@ -997,26 +1002,27 @@ hipError_t launch_round(const Problem& P, int r, int max_rounds, hipStream_t s, 
 }
 
 hipError_t launch_pack_batch(const Problem& P, const Batch& Bt, const double* lb, const double* ub,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_pack_batch, dim3(blocks_for((int64_t)Bt.nodes * P.n, kBlock, 16384)),
-                     dim3(kBlock), 0, s, P, Bt, lb, ub);
+                             int k0, int cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_batch, dim3(blocks_for((int64_t)cnt * P.n, kBlock, 16384)),
+                     dim3(kBlock), 0, s, P, Bt, lb, ub, k0, cnt);
   return hipGetLastError();
 }
 
-hipError_t launch_unpack_batch(const Problem& P, const Batch& Bt, double* lb, double* ub,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_unpack_batch, dim3(blocks_for((int64_t)Bt.nodes * P.n, kBlock, 16384)),
-                     dim3(kBlock), 0, s, P, Bt, lb, ub);
+hipError_t launch_unpack_batch(const Problem& P, const Batch& Bt, double* lb, double* ub, int k0,
+                               int cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack_batch, dim3(blocks_for((int64_t)cnt * P.n, kBlock, 16384)),
+                     dim3(kBlock), 0, s, P, Bt, lb, ub, k0, cnt);
   return hipGetLastError();
 }
 
-hipError_t launch_start_batch(const Problem& P, const Batch& Bt, int max_rounds, hipStream_t s) {
-  hipLaunchKernelGGL(k_start_batch, dim3(1), dim3(kBlock), 0, s, P, Bt, max_rounds);
+hipError_t launch_start_batch(const Problem& P, const Batch& Bt, int max_rounds, int k0, int cnt,
+                              bool whole, hipStream_t s) {
+  hipLaunchKernelGGL(k_start_batch, dim3(1), dim3(kBlock), 0, s, P, Bt, max_rounds, k0, cnt,
+                     whole ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_round_batch(const Problem& P, const Batch& Bt, int r, int max_rounds,
-                              hipStream_t s) {
+hipError_t launch_round_batch(const Problem& P, const Batch& Bt, hipStream_t s) {
   const int64_t waves = (int64_t)(P.n_chunks + P.n_segs) * Bt.groups;
   hipLaunchKernelGGL(k_round_batch, dim3(blocks_for(waves, kWavesPerBlock, 1 << 30)),
                      dim3(kBlock), 0, s, P, Bt);
@@ -1027,7 +1033,7 @@ hipError_t launch_round_batch(const Problem& P, const Batch& Bt, int r, int max_
   hipLaunchKernelGGL(k_commit_batch,
                      dim3(blocks_for((int64_t)P.n * kNodeGroup, kBlock, 256), Bt.groups),
                      dim3(kBlock), 0, s, P, Bt);
-  hipLaunchKernelGGL(k_end_batch, dim3(1), dim3(kBlock), 0, s, P, Bt, r, max_rounds);
+  hipLaunchKernelGGL(k_end_batch, dim3(1), dim3(kBlock), 0, s, P, Bt);
   return hipGetLastError();
 }
 

@@ -18,14 +18,15 @@ hipError_t launch_start(const Problem& P, int max_rounds, hipStream_t s);
 hipError_t launch_round(const Problem& P, int r, int max_rounds, hipStream_t s, hipEvent_t e0,
                         hipEvent_t e1);
 
-// Batched nodes: pack / unpack the caller's node-major arrays, and the
-// per-round kernels (matrix, long rows, commit, per-node status).
+// Batched nodes: pack / unpack nodes [k0, k0 + cnt) of the caller's
+// node-major arrays, round-0 decision for such a range (whole = the range is
+// the whole batch), and one round of every active node.
 hipError_t launch_pack_batch(const Problem& P, const Batch& Bt, const double* lb, const double* ub,
-                             hipStream_t s);
-hipError_t launch_unpack_batch(const Problem& P, const Batch& Bt, double* lb, double* ub,
-                               hipStream_t s);
-hipError_t launch_start_batch(const Problem& P, const Batch& Bt, int max_rounds, hipStream_t s);
-hipError_t launch_round_batch(const Problem& P, const Batch& Bt, int r, int max_rounds,
-                              hipStream_t s);
+                             int k0, int cnt, hipStream_t s);
+hipError_t launch_unpack_batch(const Problem& P, const Batch& Bt, double* lb, double* ub, int k0,
+                               int cnt, hipStream_t s);
+hipError_t launch_start_batch(const Problem& P, const Batch& Bt, int max_rounds, int k0, int cnt,
+                              bool whole, hipStream_t s);
+hipError_t launch_round_batch(const Problem& P, const Batch& Bt, hipStream_t s);
 
 }  // namespace prop

@@ -50,6 +50,7 @@ constexpr int kHotDegree = 512;
 constexpr int kConverged = 0;
 constexpr int kInfeasible = 1;
 constexpr int kMaxRounds = 2;
+constexpr int kInvalidInput = -1;  // batch node status: an input bound failed validation
 
 // One chunk of short/medium rows.
 struct ChunkDesc {
@@ -124,16 +125,19 @@ struct Problem {
 // group share each variable's 128-byte line.
 constexpr int kNodeGroup = 8;
 
+// Node slots in groups of kNodeGroup; each group's bound pairs live in their
+// own [n][8] block so that groups can be allocated and released one by one.
 struct Batch {
-  double2* A;              // start-of-round bounds, [groups][n][8]
-  double2* B;              // candidate targets, same layout
+  double2* const* gA;      // [groups] -> start-of-round bounds of the group, [n][8]
+  double2* const* gB;      // [groups] -> candidate targets, same layout
   SegPartial* partials;    // [segments][nodes]
   uint32_t* active;        // [nodes] still propagating
   int32_t* status;         // [nodes]
   int32_t* rounds;         // [nodes]
   uint32_t* changed;       // [nodes] pairs changed in the current round
   uint32_t* infeasible;    // [nodes] empty domain seen
-  uint32_t* invalid;       // [nodes] bound failed validation
+  uint32_t* invalid;       // [nodes] bound failed validation (cleared by the start kernel)
+  int32_t* maxr;           // [nodes] round limit of each node
   int32_t nodes;
   int32_t groups;
 };

@@ -95,3 +95,30 @@ def test_null_problem_calls():
     assert b.lib.prop_run(None, None, None, 10, ctypes.byref(res)) == b.EINVAL
     assert b.lib.prop_set_loop(None, 0) == b.EINVAL
     b.lib.prop_destroy(None)
+
+
+def test_server_argument_checks():
+    """prop_srv_create / submit / poll reject bad arguments without a device."""
+    import ctypes
+
+    for cfg, why in (((0,), "zero budget"), ((1 << 20, 7), "slots not a multiple of 8"),
+                     ((1 << 20, 0, 65), "rounds_per_step > 64"),
+                     ((1 << 20, 0, 0, -1), "negative max_pending")):
+        rc, _ = b.srv_create_raw(*cfg)
+        assert rc == b.EINVAL, why
+    rc, h = b.srv_create_raw(1 << 20)
+    assert rc == b.OK, b.last_error()
+    try:
+        t = ctypes.c_int64()
+        assert b.lib.prop_srv_submit(h, 0, None, None, 5, ctypes.byref(t)) == b.EINVAL
+        assert b.lib.prop_srv_submit(h, 0, None, None, -1, ctypes.byref(t)) == b.EINVAL
+        assert b.lib.prop_srv_poll(h, 1, None, None, None) == b.EINVAL
+        assert b.lib.prop_srv_wait(h, 1, 0, None, None, None) == b.EINVAL
+        assert b.lib.prop_srv_add_instance(h, None, ctypes.byref(ctypes.c_int32())) == b.EINVAL
+        st = b._SrvStats()
+        assert b.lib.prop_srv_get_stats(h, ctypes.byref(st)) == b.OK
+        assert st.submitted == 0 and st.device_bytes == 0
+        assert b.lib.prop_srv_reset_stats(h) == b.OK
+    finally:
+        b.lib.prop_srv_destroy(h)
+    b.lib.prop_srv_destroy(None)
