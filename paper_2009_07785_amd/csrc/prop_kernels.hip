@@ -283,13 +283,57 @@ __device__ __forceinline__ void entry_candidates(const Problem& P, const RowStat
   }
 }
 
+// Skip code of one entry side for the chunk filter: a float c with
+// "slack >= c" implying "slack > thr" (thr from side_threshold), so a side
+// skipped by the code is one the exact test skips too.  Finite thresholds
+// round up to the next float strictly above them; thresholds below 2^-100
+// map to 2^-100 (no subnormal floats are involved); W <= 0 (skipped iff the
+// slack is >= 0) maps to 0; "never skip" stays +inf.
+__device__ __forceinline__ float skip_code(double thr) {
+  if (thr < 0.0) return 0.0f;
+  if (!(thr < __builtin_inf())) return __builtin_inff();
+  if (thr < 0x1p-100) return 0x1p-100f;
+  float f = (float)thr;
+  if ((double)f <= thr) f = __int_as_float(__float_as_int(f) + 1);
+  return f;
+}
+
+// Both skip codes of an entry: the rhs side (through the min activity) and
+// the lhs side (through the max activity).  NaN marks the entry whose bound
+// makes that side's activity infinite: with exactly one infinite
+// contribution only that entry gets a candidate.
+__device__ __forceinline__ void entry_codes(double a, double l, double u, int32_t cw, double tau,
+                                            float& emin, float& emax) {
+  const bool is_int = cw < 0, pos = a > 0.0;
+  const double bmin = pos ? l : u, bmax = pos ? u : l;
+  emin = is_inf(bmin) ? __builtin_nanf("") : skip_code(side_threshold(a, l, u, is_int, pos, tau));
+  emax = is_inf(bmax) ? __builtin_nanf("") : skip_code(side_threshold(a, l, u, is_int, !pos, tau));
+}
+
+// Conservative form of entry_sides from the codes: true for every entry
+// with a side that entry_sides would keep.  Entries without a coefficient
+// carry -inf codes and never pass.
+__device__ __forceinline__ bool entry_passes(const RowState& R, float emin, float emax) {
+  bool p = false;
+  if (R.min_side) p |= R.cmin == 0 ? !(R.smn >= (double)emin) : __builtin_isnan(emin);
+  if (R.max_side) p |= R.cmax == 0 ? !((-R.smx) >= (double)emax) : __builtin_isnan(emax);
+  return p;
+}
+
 // ---------------------------------------------------------------------------
 // one chunk: activities and candidates for 64/K rows, K lanes per row
 //
 // Bound arrays are addressed as base[var * stride + node]: stride 1 for a
 // single problem, 8 for a batch (8 nodes share each variable's cache line).
-// The chunk's matrix data is loaded once and reused for every active node
-// of the group (bit t of node_mask).
+// Per active node (bit t of node_mask) each step loads its coefficient and
+// column word, gathers the bounds, adds the entry to the activities and
+// keeps only the entry's two skip codes; after the row reduction, the
+// entries whose codes do not rule them out reload their data and go through
+// the exact candidate test.  Holding two floats per step instead of the
+// entry's coefficient, column and bounds keeps the wave's register count,
+// and with it the number of resident waves hiding the gather latency, in
+// line with a plain sparse product.  In a batch, nodes after the first find
+// the chunk's matrix data in cache.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd,
                                             const double2* __restrict__ cur,
@@ -301,48 +345,45 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
   const int nrows = (cd.meta >> 16) & 0xff;
   const int r = lane >> klog;
   const size_t base = (size_t)cd.off64 * kWave + lane;
-  double a[kMaxSteps];
-  int32_t jj[kMaxSteps];
-#pragma unroll
-  for (int w = 0; w < kMaxSteps; ++w) {
-    a[w] = 0.0;
-    jj[w] = 0;
-    if (w < W) {
-      a[w] = __builtin_nontemporal_load(P.vals + base + (size_t)w * kWave);
-      jj[w] = __builtin_nontemporal_load(P.cols + base + (size_t)w * kWave);
-    }
-  }
   const bool row_ok = r < nrows;
   const int row = cd.row0 + (row_ok ? r : 0);
   const double lhs = P.lhs[row], rhs = P.rhs[row];
   for (uint32_t mask = node_mask; mask; mask &= mask - 1) {
     const uint32_t t = __builtin_ctz(mask);
-    double l[kMaxSteps], u[kMaxSteps];
-#pragma unroll
-    for (int w = 0; w < kMaxSteps; ++w) {
-      l[w] = 0.0;
-      u[w] = 0.0;
-      if (w < W && a[w] != 0.0) {
-        const double2 b = cur[(size_t)(jj[w] & kColMask) * stride + t];
-        l[w] = b.x;
-        u[w] = b.y;
-      }
-    }
+    float emin[kMaxSteps], emax[kMaxSteps];
     DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
     int cmin = 0, cmax = 0;
 #pragma unroll
-    for (int w = 0; w < kMaxSteps; ++w)
-      if (w < W) accumulate(a[w], l[w], u[w], smin, smax, cmin, cmax);
+    for (int w = 0; w < kMaxSteps; ++w) {
+      emin[w] = -__builtin_inff();
+      emax[w] = -__builtin_inff();
+      if (w < W) {
+        const size_t e = base + (size_t)w * kWave;
+        // a single run reads the matrix once: stream it past the caches
+        const double a = stride == 1 ? __builtin_nontemporal_load(P.vals + e) : P.vals[e];
+        const int32_t cw = stride == 1 ? __builtin_nontemporal_load(P.cols + e) : P.cols[e];
+        if (a != 0.0) {
+          const double2 b = cur[(size_t)(cw & kColMask) * stride + t];
+          accumulate(a, b.x, b.y, smin, smax, cmin, cmax);
+          entry_codes(a, b.x, b.y, cw, P.cont_rel_tol, emin[w], emax[w]);
+        }
+      }
+    }
     group_reduce(smin, smax, cmin, cmax, klog);
     if (!row_ok) continue;
     const RowState R = make_row_state(smin, smax, cmin, cmax, lhs, rhs);
     if (!(R.min_side || R.max_side)) continue;
-    // cheap filter first; the full candidate arithmetic runs only for the
-    // entries that pass it (a step no lane needs is skipped by the wave)
+    // a step no lane needs is skipped by the wave
 #pragma unroll
-    for (int w = 0; w < kMaxSteps; ++w)
-      if (w < W && entry_wanted(R, a[w], l[w], u[w], jj[w], P.cont_rel_tol))
-        entry_candidates(P, R, a[w], l[w], u[w], jj[w], nxt + t, stride, stride == 1);
+    for (int w = 0; w < kMaxSteps; ++w) {
+      if (w < W && entry_passes(R, emin[w], emax[w])) {
+        const size_t e = base + (size_t)w * kWave;
+        const double a = P.vals[e];
+        const int32_t cw = P.cols[e];
+        const double2 b = cur[(size_t)(cw & kColMask) * stride + t];
+        entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride, stride == 1);
+      }
+    }
   }
 }
 
