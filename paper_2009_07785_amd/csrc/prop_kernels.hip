@@ -394,6 +394,141 @@ __device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const do
 }
 
 // ---------------------------------------------------------------------------
+// node-parallel lanes for batches of 8 nodes
+//
+// In a batch the 8 nodes of a group keep each variable's (l, u) pairs in one
+// 128-byte line ([n][8] layout).  Lane e * 8 + t serves entry slot e of an
+// 8-entry block for node t, so the 8 lanes of an entry read one line with a
+// single request and the matrix data is read once for the group.  The
+// chunk layout is the single-run one: a 64-entry step is walked as 8 blocks
+// of 8 entry lanes.  Rows of K <= 8 lanes sit inside one block (their lanes
+// are the block's slots, summed in the single-run order); rows of K >= 16
+// lanes span K / 8 blocks, whose entries each slot sums one after another.
+//
+// Instead of one code per entry, a lane keeps the largest skip code of its
+// entries per side (and whether it holds the entry that owns the side's
+// only infinite contribution): "slack >= largest code" skips every entry of
+// the lane, so only lanes with an entry that may count revisit their
+// entries, with the exact test.
+// ---------------------------------------------------------------------------
+struct LaneAcc {
+  DD smin, smax;
+  int cmin, cmax;
+  float amin, amax;  // largest finite skip code per side
+  bool omin, omax;   // holds the owner of the side's infinite contribution
+};
+
+__device__ __forceinline__ void lane_acc_init(LaneAcc& L) {
+  L.smin = {0.0, 0.0};
+  L.smax = {0.0, 0.0};
+  L.cmin = L.cmax = 0;
+  L.amin = L.amax = -__builtin_inff();
+  L.omin = L.omax = false;
+}
+
+// Entries idx0 + k * dk (k < count, 1 <= count <= N) for node t: loads of
+// the group, then its gathers, then the arithmetic.  Indices past count
+// re-read the last entry and contribute nothing.
+template <int N>
+__device__ __forceinline__ void node_entries(const Problem& P, const double2* __restrict__ cur,
+                                             uint32_t t, bool on, size_t idx0, size_t dk,
+                                             int count, LaneAcc& L) {
+  double av[N];
+  int32_t cv[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const size_t idx = idx0 + (size_t)(k < count ? k : count - 1) * dk;
+    av[k] = P.vals[idx];
+    cv[k] = P.cols[idx];
+  }
+  double2 bv[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) bv[k] = cur[(size_t)(cv[k] & kColMask) * kNodeGroup + t];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    if (k < count && on && av[k] != 0.0) {
+      accumulate(av[k], bv[k].x, bv[k].y, L.smin, L.smax, L.cmin, L.cmax);
+      float c1, c2;
+      entry_codes(av[k], bv[k].x, bv[k].y, cv[k], P.cont_rel_tol, c1, c2);
+      if (__builtin_isnan(c1)) L.omin = true;
+      else L.amin = c1 > L.amin ? c1 : L.amin;
+      if (__builtin_isnan(c2)) L.omax = true;
+      else L.amax = c2 > L.amax ? c2 : L.amax;
+    }
+  }
+}
+
+// Sums over the entry slots of a row: xor over the slot bits (lane bits 3..)
+// below `levels`, with the symmetric combine.
+__device__ __forceinline__ void slot_reduce(LaneAcc& L, int levels) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (i >= levels) break;
+    const int off = 8 << i;
+    double a = __shfl_xor(L.smin.hi, off, kWave);
+    double b = __shfl_xor(L.smin.lo, off, kWave);
+    double c = __shfl_xor(L.smax.hi, off, kWave);
+    double d = __shfl_xor(L.smax.lo, off, kWave);
+    int e = __shfl_xor(L.cmin, off, kWave);
+    int f = __shfl_xor(L.cmax, off, kWave);
+    dd_add(L.smin, a, b);
+    dd_add(L.smax, c, d);
+    L.cmin += e;
+    L.cmax += f;
+  }
+}
+
+__device__ __forceinline__ bool lane_may_pass(const RowState& R, const LaneAcc& L) {
+  bool p = false;
+  if (R.min_side) p |= R.cmin == 0 ? !(R.smn >= (double)L.amin) : L.omin;
+  if (R.max_side) p |= R.cmax == 0 ? !((-R.smx) >= (double)L.amax) : L.omax;
+  return p;
+}
+
+__device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkDesc cd,
+                                                  const double2* __restrict__ cur,
+                                                  double2* __restrict__ nxt, uint32_t node_mask) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t t = lane & (kNodeGroup - 1);
+  const int e = lane >> 3;
+  const bool on = (node_mask >> t) & 1u;
+  const int klog = cd.meta & 7;
+  const int W = (cd.meta >> 8) & 0xff;
+  const int nrows = (cd.meta >> 16) & 0xff;
+  const int QB = klog > 3 ? 1 << (klog - 3) : 1;       // 8-entry blocks per row block
+  const int per_block = klog > 3 ? 1 : 8 >> klog;      // rows per row block
+  const int nblocks = (nrows + per_block - 1) / per_block;
+  const size_t base = (size_t)cd.off64 * kWave;
+  for (int rb = 0; rb < nblocks; ++rb) {
+    const int r = klog > 3 ? rb : rb * per_block + (e >> klog);
+    LaneAcc L;
+    lane_acc_init(L);
+    for (int qq = 0; qq < QB; ++qq) {
+      const size_t l = (size_t)(rb * QB + qq) * 8 + e;
+      for (int w0 = 0; w0 < W; w0 += 8)
+        node_entries<8>(P, cur, t, on, base + (size_t)w0 * kWave + l, kWave,
+                        W - w0 < 8 ? W - w0 : 8, L);
+    }
+    slot_reduce(L, klog > 3 ? 3 : klog);
+    if (r >= nrows || !on) continue;
+    const int row = cd.row0 + r;
+    const RowState R = make_row_state(L.smin, L.smax, L.cmin, L.cmax, P.lhs[row], P.rhs[row]);
+    if (!lane_may_pass(R, L)) continue;
+    for (int qq = 0; qq < QB; ++qq) {
+      const size_t l = (size_t)(rb * QB + qq) * 8 + e;
+      for (int w = 0; w < W; ++w) {
+        const size_t idx = base + (size_t)w * kWave + l;
+        const double a = P.vals[idx];
+        if (a == 0.0) continue;
+        const int32_t cw = P.cols[idx];
+        const double2 b = cur[(size_t)(cw & kColMask) * kNodeGroup + t];
+        entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, kNodeGroup, false);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // long rows: partials live at partials[segment * pstride + node]
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
@@ -452,6 +587,71 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
       q.pad0 = q.pad1 = 0;
       parts[(size_t)s * pstride + node0 + t] = q;
     }
+  }
+}
+
+// Phase 1 of a segment for the 8 nodes of a group (node-parallel lanes):
+// slot e sums entries e, e + 8, e + 16, ... of the segment for node t.
+__device__ __forceinline__ void seg_phase1_nodes(const Problem& P, int s,
+                                                 const double2* __restrict__ cur,
+                                                 uint32_t node_mask, SegPartial* parts,
+                                                 uint32_t pstride, uint32_t node0) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t t = lane & (kNodeGroup - 1);
+  const int e = lane >> 3;
+  const bool on = (node_mask >> t) & 1u;
+  const SegDesc sd = P.segs[s];
+  const int nblk = (sd.len + 7) / 8;  // the region is padded to whole 64-entry steps
+  LaneAcc L;
+  lane_acc_init(L);
+  double tmin = -0x1p-1074, tmax = -0x1p-1074;
+  for (int i0 = 0; i0 < nblk; i0 += 8) {
+    const int count = nblk - i0 < 8 ? nblk - i0 : 8;
+    // same loads and gathers as node_entries, keeping the double thresholds
+    double av[8];
+    int32_t cv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const size_t idx = (size_t)sd.off + (size_t)(i0 + (k < count ? k : count - 1)) * 8 + e;
+      av[k] = P.vals[idx];
+      cv[k] = P.cols[idx];
+    }
+    double2 bv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) bv[k] = cur[(size_t)(cv[k] & kColMask) * kNodeGroup + t];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k < count && on && av[k] != 0.0) {
+        const double2 b = bv[k];
+        accumulate(av[k], b.x, b.y, L.smin, L.smax, L.cmin, L.cmax);
+        const bool is_int = cv[k] < 0, pos = av[k] > 0.0;
+        const double t1 = side_threshold(av[k], b.x, b.y, is_int, pos, P.cont_rel_tol);
+        const double t2 = side_threshold(av[k], b.x, b.y, is_int, !pos, P.cont_rel_tol);
+        tmin = t1 > tmin ? t1 : tmin;
+        tmax = t2 > tmax ? t2 : tmax;
+      }
+    }
+  }
+  slot_reduce(L, 3);
+#pragma unroll
+  for (int off = 8; off < kWave; off <<= 1) {
+    const double o1 = __shfl_xor(tmin, off, kWave);
+    const double o2 = __shfl_xor(tmax, off, kWave);
+    tmin = o1 > tmin ? o1 : tmin;
+    tmax = o2 > tmax ? o2 : tmax;
+  }
+  if (e == 0 && on) {
+    SegPartial q;
+    q.min_hi = L.smin.hi;
+    q.min_lo = L.smin.lo;
+    q.max_hi = L.smax.hi;
+    q.max_lo = L.smax.lo;
+    q.tmin = tmin;
+    q.tmax = tmax;
+    q.min_inf = L.cmin;
+    q.max_inf = L.cmax;
+    q.pad0 = q.pad1 = 0;
+    parts[(size_t)s * pstride + node0 + t] = q;
   }
 }
 
@@ -897,10 +1097,20 @@ __global__ __launch_bounds__(kBlock) void k_round_batch(Problem P, Batch Bt) {
   if (unit >= P.n_segs + P.n_chunks) return;
   const uint32_t mask = group_mask(Bt, g);
   if (!mask) return;
-  if (unit < P.n_segs)
-    seg_phase1(P, unit, Bt.gA[g], kNodeGroup, mask, Bt.partials, Bt.nodes, g * kNodeGroup);
-  else
-    chunk_dispatch(P, unit - P.n_segs, Bt.gA[g], Bt.gB[g], kNodeGroup, mask);
+  // with few active nodes, node-parallel lanes would mostly idle: loop over
+  // the active nodes with the single-run shape instead
+  const bool few = __builtin_popcount(mask) <= kLoopNodes;
+  if (unit < P.n_segs) {
+    if (few)
+      seg_phase1(P, unit, Bt.gA[g], kNodeGroup, mask, Bt.partials, Bt.nodes, g * kNodeGroup);
+    else
+      seg_phase1_nodes(P, unit, Bt.gA[g], mask, Bt.partials, Bt.nodes, g * kNodeGroup);
+  } else {
+    if (few)
+      chunk_dispatch(P, unit - P.n_segs, Bt.gA[g], Bt.gB[g], kNodeGroup, mask);
+    else
+      chunk_round_nodes(P, P.chunks[unit - P.n_segs], Bt.gA[g], Bt.gB[g], mask);
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_round_long_batch(Problem P, Batch Bt) {

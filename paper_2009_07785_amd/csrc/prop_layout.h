@@ -124,6 +124,8 @@ struct Problem {
 // k = 8 g + t for variable j sit at A[(g * n + j) * 8 + t]: the 8 nodes of a
 // group share each variable's 128-byte line.
 constexpr int kNodeGroup = 8;
+// a group with at most this many active nodes runs them one after another
+constexpr int kLoopNodes = 2;
 
 // Node slots in groups of kNodeGroup; each group's bound pairs live in their
 // own [n][8] block so that groups can be allocated and released one by one.
