@@ -445,7 +445,7 @@ def kernel_source_sha() -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for name in ("prop_kernels.hip", "prop_layout.h"):
+    for name in ("prop_kernels.hip", "prop_device.h", "prop_layout.h"):
         with open(os.path.join(ROOT, "paper_2009_07785_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

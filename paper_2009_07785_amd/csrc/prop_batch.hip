@@ -1,0 +1,262 @@
+// prop_batch.hip -- gfx950 kernels for many bound vectors of one problem:
+// batched branch-and-bound nodes and the serving engine's slots.  Nodes
+// come in groups of 8 whose (l, u) pairs share one 128-byte line per
+// variable; a group with more than kLoopNodes active nodes runs with
+// node-parallel lanes, a smaller one node after node in the single-run
+// shape.  Every node's results are those of its own single run.
+#include <hip/hip_runtime.h>
+
+#include "prop_device.h"
+#include "prop_launch.h"
+#include "prop_layout.h"
+
+#pragma clang fp contract(off)
+
+namespace prop {
+
+// ---------------------------------------------------------------------------
+// batched nodes (one problem, many bound vectors): every node runs exactly
+// the arithmetic of a single run; nodes that finished are masked out
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t group_mask(const Batch& Bt, int g) {
+  uint32_t mask = 0;
+#pragma unroll
+  for (int t = 0; t < kNodeGroup; ++t) {
+    const int k = g * kNodeGroup + t;
+    if (k < Bt.nodes && Bt.active[k]) mask |= 1u << t;
+  }
+  return mask;
+}
+
+// Packs nodes [k0, k0 + cnt) from node-major arrays (row q = node k0 + q).
+__global__ __launch_bounds__(kBlock) void k_pack_batch(Problem P, Batch Bt,
+                                                       const double* __restrict__ ulb,
+                                                       const double* __restrict__ uub, int k0,
+                                                       int cnt) {
+  const size_t total = (size_t)cnt * P.n;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int q = (int)(i / (size_t)P.n);
+    const int k = k0 + q;
+    const int v = (int)(i - (size_t)q * P.n);
+    double l = ulb[i], u = uub[i];
+    const bool bad = __builtin_isnan(l) || __builtin_isnan(u) || l == __builtin_inf() ||
+                     u == -__builtin_inf() ||
+                     (!is_inf(l) && __builtin_fabs(l) > PROP_HUGE) ||
+                     (!is_inf(u) && __builtin_fabs(u) > PROP_HUGE);
+    if (bad) __hip_atomic_store(&Bt.invalid[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t j = P.perm[v];
+    const bool is_int = P.vtype[j] != 0;
+    if (is_int) {
+      l = __builtin_ceil(l - P.eps_int);
+      u = __builtin_floor(u + P.eps_int);
+    }
+    l = l + 0.0;
+    u = u + 0.0;
+    const size_t dst = (size_t)j * kNodeGroup + (k % kNodeGroup);
+    const double2 b = make_double2(l, u);
+    Bt.gA[k / kNodeGroup][dst] = b;
+    Bt.gB[k / kNodeGroup][dst] = b;
+    if (domain_empty(is_int, l, u, P.feas_tol))
+      __hip_atomic_store(&Bt.infeasible[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Unpacks nodes [k0, k0 + cnt) into node-major arrays (row q = node k0 + q).
+__global__ __launch_bounds__(kBlock) void k_unpack_batch(Problem P, Batch Bt,
+                                                         double* __restrict__ ulb,
+                                                         double* __restrict__ uub, int k0,
+                                                         int cnt) {
+  const size_t total = (size_t)cnt * P.n;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int q = (int)(i / (size_t)P.n);
+    const int k = k0 + q;
+    const int v = (int)(i - (size_t)q * P.n);
+    const size_t src = (size_t)P.perm[v] * kNodeGroup + (k % kNodeGroup);
+    const double2 b = Bt.gA[k / kNodeGroup][src];
+    ulb[i] = b.x;
+    uub[i] = b.y;
+  }
+}
+
+// Block-wide count of active nodes after a status update; sets ctrl->done.
+__device__ __forceinline__ void batch_set_done(const Problem& P, uint32_t my_active) {
+  uint32_t dummy = 0;
+  block_sum2(my_active, dummy);
+  if (threadIdx.x == 0) P.ctrl->done = my_active == 0 ? 1u : 0u;
+}
+
+// One block: round-0 decision for nodes [k0, k0 + cnt); with `whole`, the
+// done flag reflects the whole batch, otherwise it is cleared (a node joins
+// a running batch).
+__global__ __launch_bounds__(kBlock) void k_start_batch(Problem P, Batch Bt, int max_rounds,
+                                                        int k0, int cnt, int whole) {
+  uint32_t act = 0;
+  for (int k = k0 + threadIdx.x; k < k0 + cnt; k += blockDim.x) {
+    uint32_t a = 0;
+    if (Bt.invalid[k]) {
+      Bt.status[k] = kInvalidInput;
+    } else if (Bt.infeasible[k] || P.instance_infeasible) {
+      Bt.status[k] = kInfeasible;
+    } else if (max_rounds == 0) {
+      Bt.status[k] = kMaxRounds;
+    } else {
+      Bt.status[k] = kMaxRounds;
+      a = 1;
+    }
+    Bt.rounds[k] = 0;
+    Bt.maxr[k] = max_rounds;
+    Bt.active[k] = a;
+    Bt.changed[k] = 0;
+    Bt.infeasible[k] = 0;
+    Bt.invalid[k] = 0;
+    act += a;
+  }
+  if (whole) batch_set_done(P, act);
+  else if (threadIdx.x == 0) P.ctrl->done = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_round_batch(Problem P, Batch Bt) {
+  if (u32_load(&P.ctrl->done)) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  const int unit = (int)(wid / Bt.groups);
+  const int g = (int)(wid - (int64_t)unit * Bt.groups);
+  if (unit >= P.n_segs + P.n_chunks) return;
+  const uint32_t mask = group_mask(Bt, g);
+  if (!mask) return;
+  // with few active nodes, node-parallel lanes would mostly idle: loop over
+  // the active nodes with the single-run shape instead
+  const bool few = __builtin_popcount(mask) <= kLoopNodes;
+  if (unit < P.n_segs) {
+    if (few)
+      seg_phase1(P, unit, Bt.gA[g], kNodeGroup, mask, Bt.partials, Bt.nodes, g * kNodeGroup);
+    else
+      seg_phase1_nodes(P, unit, Bt.gA[g], mask, Bt.partials, Bt.nodes, g * kNodeGroup);
+  } else {
+    if (few)
+      chunk_dispatch(P, unit - P.n_segs, Bt.gA[g], Bt.gB[g], kNodeGroup, mask);
+    else
+      chunk_round_nodes(P, P.chunks[unit - P.n_segs], Bt.gA[g], Bt.gB[g], mask);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_round_long_batch(Problem P, Batch Bt) {
+  if (u32_load(&P.ctrl->done)) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  const int s = (int)(wid / Bt.nodes);
+  const int k = (int)(wid - (int64_t)s * Bt.nodes);
+  if (s >= P.n_segs || !Bt.active[k]) return;
+  const int g = k / kNodeGroup;
+  seg_phase2(P, s, Bt.gA[g], Bt.gB[g], kNodeGroup, k % kNodeGroup, Bt.partials, Bt.nodes, k);
+}
+
+// Commit per (variable, node) of group blockIdx.y, with per-node counts.
+__global__ __launch_bounds__(kBlock) void k_commit_batch(Problem P, Batch Bt) {
+  if (u32_load(&P.ctrl->done)) return;
+  __shared__ uint32_t ch[kNodeGroup], inf[kNodeGroup];
+  if (threadIdx.x < kNodeGroup) {
+    ch[threadIdx.x] = 0;
+    inf[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  const int g = blockIdx.y;
+  const uint32_t mask = group_mask(Bt, g);
+  if (mask) {
+    double2* A = Bt.gA[g];
+    const double2* B = Bt.gB[g];
+    const size_t total = (size_t)P.n * kNodeGroup;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+      const uint32_t t = (uint32_t)(e % kNodeGroup);
+      if (!((mask >> t) & 1u)) continue;
+      const double2 a = A[e];
+      const double2 b = B[e];
+      if (a.x != b.x || a.y != b.y) {
+        A[e] = b;
+        atomicAdd(&ch[t], 1u);
+        if (domain_empty(P.vtype[e / kNodeGroup] != 0, b.x, b.y, P.feas_tol)) inf[t] = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kNodeGroup) {
+    const int k = g * kNodeGroup + threadIdx.x;
+    if (ch[threadIdx.x])
+      __hip_atomic_fetch_add(&Bt.changed[k], ch[threadIdx.x], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    if (inf[threadIdx.x])
+      __hip_atomic_store(&Bt.infeasible[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// One block: per-node status after the round each active node just ran
+// (node k's own round count: nodes may have joined at different times).
+__global__ __launch_bounds__(kBlock) void k_end_batch(Problem P, Batch Bt) {
+  if (u32_load(&P.ctrl->done)) return;
+  uint32_t act = 0;
+  for (int k = threadIdx.x; k < Bt.nodes; k += blockDim.x) {
+    if (!Bt.active[k]) continue;
+    const int r = Bt.rounds[k] + 1;
+    const int max_rounds = Bt.maxr[k];
+    uint32_t a = 0;
+    Bt.rounds[k] = r;
+    if (Bt.infeasible[k]) {
+      Bt.status[k] = kInfeasible;
+    } else if (Bt.changed[k] == 0) {
+      Bt.status[k] = kConverged;
+    } else if (r >= max_rounds) {
+      Bt.status[k] = kMaxRounds;
+    } else {
+      a = 1;
+    }
+    Bt.active[k] = a;
+    Bt.changed[k] = 0;
+    Bt.infeasible[k] = 0;
+    act += a;
+  }
+  batch_set_done(P, act);
+}
+
+// ---------------------------------------------------------------------------
+// launchers (host side)
+// ---------------------------------------------------------------------------
+hipError_t launch_pack_batch(const Problem& P, const Batch& Bt, const double* lb, const double* ub,
+                             int k0, int cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_batch, dim3(blocks_for((int64_t)cnt * P.n, kBlock, 16384)),
+                     dim3(kBlock), 0, s, P, Bt, lb, ub, k0, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_batch(const Problem& P, const Batch& Bt, double* lb, double* ub, int k0,
+                               int cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack_batch, dim3(blocks_for((int64_t)cnt * P.n, kBlock, 16384)),
+                     dim3(kBlock), 0, s, P, Bt, lb, ub, k0, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_start_batch(const Problem& P, const Batch& Bt, int max_rounds, int k0, int cnt,
+                              bool whole, hipStream_t s) {
+  hipLaunchKernelGGL(k_start_batch, dim3(1), dim3(kBlock), 0, s, P, Bt, max_rounds, k0, cnt,
+                     whole ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_batch(const Problem& P, const Batch& Bt, hipStream_t s) {
+  const int64_t waves = (int64_t)(P.n_chunks + P.n_segs) * Bt.groups;
+  hipLaunchKernelGGL(k_round_batch, dim3(blocks_for(waves, kWavesPerBlock, 1 << 30)),
+                     dim3(kBlock), 0, s, P, Bt);
+  if (P.n_segs)
+    hipLaunchKernelGGL(k_round_long_batch,
+                       dim3(blocks_for((int64_t)P.n_segs * Bt.nodes, kWavesPerBlock, 1 << 30)),
+                       dim3(kBlock), 0, s, P, Bt);
+  hipLaunchKernelGGL(k_commit_batch,
+                     dim3(blocks_for((int64_t)P.n * kNodeGroup, kBlock, 256), Bt.groups),
+                     dim3(kBlock), 0, s, P, Bt);
+  hipLaunchKernelGGL(k_end_batch, dim3(1), dim3(kBlock), 0, s, P, Bt);
+  return hipGetLastError();
+}
+
+}  // namespace prop
