@@ -189,13 +189,16 @@ void prop_destroy(prop_problem* p);
  * and the request's input/output staging); groups are allocated when a
  * request finds no free slot and the budget has room, and idle groups are
  * released when another problem needs the room.  Each added problem also
- * holds 28 * max_slots bytes of per-slot state plus 64 * max_slots bytes
- * per long-row segment.  A request waits in its problem's queue (first in,
- * first out) while neither a slot nor room is available.
+ * holds 32 * max_slots bytes of per-slot state plus 64 * max_slots bytes
+ * per long-row segment, and the server about 100 KB of its own; this fixed
+ * state is never released.  A request waits in its problem's queue (first
+ * in, first out) while neither a slot nor room is available.
  *
- * One host thread per server schedules; each problem's work is queued on a
- * HIP stream of its own (default priority), so problems overlap on the
- * device.  The server reads only a problem's matrix and keeps its own
+ * One host thread per server schedules.  All device work goes to one HIP
+ * stream of the server (default priority): each round of every problem with
+ * running requests is one launch per phase, so the host's launch count does
+ * not grow with the number of problems.  At most 256 problems per server,
+ * all on one device.  The server reads only a problem's matrix and keeps its own
  * control state: prop_run calls on an added problem stay allowed, from one
  * thread at a time as always.  Destroy the server before its problems.
  * Server calls are thread-safe.
@@ -229,15 +232,16 @@ int prop_srv_create(const prop_srv_config* cfg, prop_server** out);
 
 /* Makes problem p servable under the id stored in *id (0, 1, ...).  The
  * problem must outlive the server.  Returns PROP_ENOMEM when its per-problem
- * state does not fit the remaining budget. */
+ * state does not fit the remaining budget, PROP_EINVAL beyond 256 problems
+ * or for a problem on another device than the first one. */
 int prop_srv_add_instance(prop_server* s, prop_problem* p, int32_t* id);
 
 /* Queues a request: lb[n], ub[n] (host, copied before the call returns;
  * the caller keeps them) under the input domain of prop_run, and a round
  * limit >= 0.  Stores a ticket in *ticket.  PROP_EINVAL for an unknown id
  * or an invalid bound, PROP_ENOMEM when one slot group of the problem
- * cannot fit the budget at all, PROP_EBUSY when max_pending requests are
- * held. */
+ * cannot fit the budget beside the fixed state of the server and its
+ * problems, PROP_EBUSY when max_pending requests are held. */
 int prop_srv_submit(prop_server* s, int32_t id, const double* lb, const double* ub,
                     int32_t max_rounds, int64_t* ticket);
 

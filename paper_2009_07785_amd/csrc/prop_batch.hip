@@ -111,18 +111,17 @@ __global__ __launch_bounds__(kBlock) void k_start_batch(Problem P, Batch Bt, int
     Bt.changed[k] = 0;
     Bt.infeasible[k] = 0;
     Bt.invalid[k] = 0;
+    if (Bt.live) Bt.live[k] = 1;
     act += a;
   }
   if (whole) batch_set_done(P, act);
   else if (threadIdx.x == 0) P.ctrl->done = 0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_round_batch(Problem P, Batch Bt) {
-  if (u32_load(&P.ctrl->done)) return;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-  const int unit = (int)(wid / Bt.groups);
-  const int g = (int)(wid - (int64_t)unit * Bt.groups);
+// ---- bodies shared by the batch kernels and the serving kernels ----------
+
+// One wave: work unit `unit` (long-row segment, then chunk) of group g.
+__device__ __forceinline__ void round_unit(const Problem& P, const Batch& Bt, int unit, int g) {
   if (unit >= P.n_segs + P.n_chunks) return;
   const uint32_t mask = group_mask(Bt, g);
   if (!mask) return;
@@ -142,34 +141,29 @@ __global__ __launch_bounds__(kBlock) void k_round_batch(Problem P, Batch Bt) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_round_long_batch(Problem P, Batch Bt) {
-  if (u32_load(&P.ctrl->done)) return;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-  const int s = (int)(wid / Bt.nodes);
-  const int k = (int)(wid - (int64_t)s * Bt.nodes);
+// One wave: phase 2 of segment s for node k.
+__device__ __forceinline__ void long_unit(const Problem& P, const Batch& Bt, int s, int k) {
   if (s >= P.n_segs || !Bt.active[k]) return;
   const int g = k / kNodeGroup;
   seg_phase2(P, s, Bt.gA[g], Bt.gB[g], kNodeGroup, k % kNodeGroup, Bt.partials, Bt.nodes, k);
 }
 
-// Commit per (variable, node) of group blockIdx.y, with per-node counts.
-__global__ __launch_bounds__(kBlock) void k_commit_batch(Problem P, Batch Bt) {
-  if (u32_load(&P.ctrl->done)) return;
-  __shared__ uint32_t ch[kNodeGroup], inf[kNodeGroup];
+// Block bx of nbx over group g's (variable, node) pairs: copy changed pairs
+// B -> A, count them and check their domains per node (ch, inf: shared).
+__device__ __forceinline__ void commit_part(const Problem& P, const Batch& Bt, int g, uint32_t bx,
+                                            uint32_t nbx, uint32_t* ch, uint32_t* inf) {
   if (threadIdx.x < kNodeGroup) {
     ch[threadIdx.x] = 0;
     inf[threadIdx.x] = 0;
   }
   __syncthreads();
-  const int g = blockIdx.y;
   const uint32_t mask = group_mask(Bt, g);
   if (mask) {
     double2* A = Bt.gA[g];
     const double2* B = Bt.gB[g];
     const size_t total = (size_t)P.n * kNodeGroup;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const size_t stride = (size_t)nbx * blockDim.x;
+    for (size_t e = (size_t)bx * blockDim.x + threadIdx.x; e < total; e += stride) {
       const uint32_t t = (uint32_t)(e % kNodeGroup);
       if (!((mask >> t) & 1u)) continue;
       const double2 a = A[e];
@@ -192,13 +186,31 @@ __global__ __launch_bounds__(kBlock) void k_commit_batch(Problem P, Batch Bt) {
   }
 }
 
-// One block: per-node status after the round each active node just ran
-// (node k's own round count: nodes may have joined at different times).
-__global__ __launch_bounds__(kBlock) void k_end_batch(Problem P, Batch Bt) {
-  if (u32_load(&P.ctrl->done)) return;
+// Appends slot k's outcome to the step's completion list; a slot that finds
+// the list full stays unreported (live) and is reported in a later round.
+__device__ __forceinline__ void report_slot(const Batch& Bt, SrvStep* S, int inst, int k) {
+  const uint32_t i = atomicAdd(&S->n_done, 1u);
+  if (i < (uint32_t)kSrvStepDone) {
+    S->done[i].inst = inst;
+    S->done[i].slot = k;
+    S->done[i].status = Bt.status[k];
+    S->done[i].rounds = Bt.rounds[k];
+    Bt.live[k] = 0;
+  }
+}
+
+// One block: status of every active node after the round it just ran (its
+// own round count: nodes may have joined at different times).  With a step
+// (serving), finished slots are reported, including slots that finished at
+// their start and slots a full list left unreported.
+__device__ __forceinline__ void end_slots(const Problem& P, const Batch& Bt, SrvStep* S,
+                                          int inst) {
   uint32_t act = 0;
   for (int k = threadIdx.x; k < Bt.nodes; k += blockDim.x) {
-    if (!Bt.active[k]) continue;
+    if (!Bt.active[k]) {
+      if (S && Bt.live[k]) report_slot(Bt, S, inst, k);
+      continue;
+    }
     const int r = Bt.rounds[k] + 1;
     const int max_rounds = Bt.maxr[k];
     uint32_t a = 0;
@@ -216,8 +228,114 @@ __global__ __launch_bounds__(kBlock) void k_end_batch(Problem P, Batch Bt) {
     Bt.changed[k] = 0;
     Bt.infeasible[k] = 0;
     act += a;
+    if (S && !a) report_slot(Bt, S, inst, k);
   }
   batch_set_done(P, act);
+}
+
+// ---- batch kernels (one problem) ------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_round_batch(Problem P, Batch Bt) {
+  if (u32_load(&P.ctrl->done)) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  const int unit = (int)(wid / Bt.groups);
+  const int g = (int)(wid - (int64_t)unit * Bt.groups);
+  round_unit(P, Bt, unit, g);
+}
+
+__global__ __launch_bounds__(kBlock) void k_round_long_batch(Problem P, Batch Bt) {
+  if (u32_load(&P.ctrl->done)) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  const int s = (int)(wid / Bt.nodes);
+  const int k = (int)(wid - (int64_t)s * Bt.nodes);
+  long_unit(P, Bt, s, k);
+}
+
+// Commit per (variable, node) of group blockIdx.y, with per-node counts.
+__global__ __launch_bounds__(kBlock) void k_commit_batch(Problem P, Batch Bt) {
+  if (u32_load(&P.ctrl->done)) return;
+  __shared__ uint32_t ch[kNodeGroup], inf[kNodeGroup];
+  commit_part(P, Bt, blockIdx.y, blockIdx.x, gridDim.x, ch, inf);
+}
+
+__global__ __launch_bounds__(kBlock) void k_end_batch(Problem P, Batch Bt) {
+  if (u32_load(&P.ctrl->done)) return;
+  end_slots(P, Bt, nullptr, 0);
+}
+
+// ---- serving kernels: every instance of a step in one launch per phase -----
+
+// Entry of the step holding work item x of a phase (0 round waves, 1
+// long-row waves, 2 commit blocks): the last entry whose first item is <= x.
+__device__ __forceinline__ int step_entry(const SrvStep* S, int64_t x, int which) {
+  int lo = 0, hi = S->n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const SrvEntry& E = S->e[mid];
+    const int64_t base = which == 0 ? E.round_base : which == 1 ? E.long_base : E.commit_base;
+    if (base <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ Batch step_batch(const SrvInst* I, const SrvEntry& E) {
+  Batch Bt = I[E.inst].bt;
+  Bt.groups = E.groups;
+  Bt.nodes = E.groups * kNodeGroup;
+  return Bt;
+}
+
+__global__ __launch_bounds__(kBlock) void k_srv_round(const SrvInst* __restrict__ I,
+                                                      const SrvStep* __restrict__ S) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  if (wid >= S->round_total) return;
+  const SrvEntry E = S->e[step_entry(S, wid, 0)];
+  const Problem P = I[E.inst].P;
+  if (u32_load(&P.ctrl->done)) return;
+  const Batch Bt = step_batch(I, E);
+  const int64_t local = wid - E.round_base;
+  const int unit = (int)(local / E.groups);
+  round_unit(P, Bt, unit, (int)(local - (int64_t)unit * E.groups));
+}
+
+__global__ __launch_bounds__(kBlock) void k_srv_long(const SrvInst* __restrict__ I,
+                                                     const SrvStep* __restrict__ S) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  if (wid >= S->long_total) return;
+  const SrvEntry E = S->e[step_entry(S, wid, 1)];
+  const Problem P = I[E.inst].P;
+  if (u32_load(&P.ctrl->done)) return;
+  const Batch Bt = step_batch(I, E);
+  const int64_t local = wid - E.long_base;
+  const int s = (int)(local / Bt.nodes);
+  long_unit(P, Bt, s, (int)(local - (int64_t)s * Bt.nodes));
+}
+
+__global__ __launch_bounds__(kBlock) void k_srv_commit(const SrvInst* __restrict__ I,
+                                                       const SrvStep* __restrict__ S) {
+  __shared__ uint32_t ch[kNodeGroup], inf[kNodeGroup];
+  if ((int64_t)blockIdx.x >= S->commit_total) return;
+  const SrvEntry E = S->e[step_entry(S, blockIdx.x, 2)];
+  const Problem P = I[E.inst].P;
+  if (u32_load(&P.ctrl->done)) return;
+  const Batch Bt = step_batch(I, E);
+  const int local = (int)((int64_t)blockIdx.x - E.commit_base);
+  const int g = local / E.commit_blocks;
+  commit_part(P, Bt, g, local - g * E.commit_blocks, E.commit_blocks, ch, inf);
+}
+
+// One block per entry.  No early exit on the done flag: slots finished at
+// their start, or left unreported by a full list, are reported here.
+__global__ __launch_bounds__(kBlock) void k_srv_end(const SrvInst* __restrict__ I,
+                                                    SrvStep* __restrict__ S) {
+  if ((int)blockIdx.x >= S->n) return;
+  const SrvEntry E = S->e[blockIdx.x];
+  const Problem P = I[E.inst].P;
+  end_slots(P, step_batch(I, E), S, E.inst);
 }
 
 // ---------------------------------------------------------------------------
@@ -256,6 +374,19 @@ hipError_t launch_round_batch(const Problem& P, const Batch& Bt, hipStream_t s) 
                      dim3(blocks_for((int64_t)P.n * kNodeGroup, kBlock, 256), Bt.groups),
                      dim3(kBlock), 0, s, P, Bt);
   hipLaunchKernelGGL(k_end_batch, dim3(1), dim3(kBlock), 0, s, P, Bt);
+  return hipGetLastError();
+}
+
+hipError_t launch_srv_round(const SrvInst* I, SrvStep* S, const SrvStep& H, hipStream_t s) {
+  if (H.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_srv_round, dim3(blocks_for(H.round_total, kWavesPerBlock, 1 << 30)),
+                     dim3(kBlock), 0, s, I, S);
+  if (H.long_total)
+    hipLaunchKernelGGL(k_srv_long, dim3(blocks_for(H.long_total, kWavesPerBlock, 1 << 30)),
+                       dim3(kBlock), 0, s, I, S);
+  hipLaunchKernelGGL(k_srv_commit, dim3(blocks_for(H.commit_total, 1, 1 << 30)), dim3(kBlock), 0,
+                     s, I, S);
+  hipLaunchKernelGGL(k_srv_end, dim3(H.n), dim3(kBlock), 0, s, I, S);
   return hipGetLastError();
 }
 

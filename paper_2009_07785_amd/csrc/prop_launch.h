@@ -29,4 +29,8 @@ hipError_t launch_start_batch(const Problem& P, const Batch& Bt, int max_rounds,
                               bool whole, hipStream_t s);
 hipError_t launch_round_batch(const Problem& P, const Batch& Bt, hipStream_t s);
 
+// Serving: one round of every instance listed in step S (device copy; H is
+// the host copy it was uploaded from, for the grid sizes).
+hipError_t launch_srv_round(const SrvInst* I, SrvStep* S, const SrvStep& H, hipStream_t s);
+
 }  // namespace prop

@@ -140,8 +140,41 @@ struct Batch {
   uint32_t* infeasible;    // [nodes] empty domain seen
   uint32_t* invalid;       // [nodes] bound failed validation (cleared by the start kernel)
   int32_t* maxr;           // [nodes] round limit of each node
+  uint32_t* live;          // [nodes] serving only (else null): finished, not yet reported
   int32_t nodes;
   int32_t groups;
+};
+
+// ---------------------------------------------------------------------------
+// Serving: one launch per phase covers every instance with running slots.
+// ---------------------------------------------------------------------------
+struct SrvInst {           // per instance, device resident
+  Problem P;               // matrix of the instance, control block of the server's
+  Batch bt;                // slot state (nodes / groups are set per step)
+};
+
+struct SrvDone {           // a slot whose request finished
+  int32_t inst, slot, status, rounds;
+};
+
+struct SrvEntry {          // an instance in a step, with the first work item of each phase
+  int32_t inst, groups;
+  int64_t round_base;      // waves of the round kernel
+  int64_t long_base;       // waves of the long-row kernel
+  int64_t commit_base;     // blocks of the commit kernel
+  int32_t commit_blocks;   // commit blocks per group
+  int32_t pad;
+};
+
+constexpr int kSrvStepDone = 512;     // completions a step can report (more wait a round)
+constexpr int kSrvMaxInstances = 256;
+
+struct SrvStep {
+  int32_t n;               // entries
+  uint32_t n_done;         // completions reported (may exceed kSrvStepDone)
+  int64_t round_total, long_total, commit_total;
+  SrvDone done[kSrvStepDone];
+  SrvEntry e[kSrvMaxInstances];
 };
 
 }  // namespace prop

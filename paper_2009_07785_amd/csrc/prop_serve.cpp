@@ -6,15 +6,17 @@
 // start-of-round and candidate bound pairs, reached through a device table
 // of group pointers so that groups can be allocated and released one by one.
 // A request is packed into a free slot and started (its own round counter
-// and round limit) between two rounds of its instance; from then on every
-// round kernel of the instance advances it.  The host reads the per-slot
-// state (active, status, rounds) once per step of a few rounds; a slot that
-// went inactive is unpacked into its staging area, copied to the host, and
-// freed once that copy has landed.
+// and round limit) between two rounds; from then on every round advances
+// it.  A step is a few rounds of every instance with running slots, one
+// launch per phase for all of them (the step table lists the instances and
+// where each one's work items start); the end-of-round kernel reports the
+// slots that finished in the step's completion list, which the host reads
+// back with the step.  A finished slot is unpacked into its staging area,
+// copied to the host, and freed once that copy has landed.
 //
-// Everything for an instance is queued on its own stream, so the host
-// staging of a slot is only rewritten after the device work that read or
-// wrote it has completed (its completion was observed through an event).
+// All device work is queued on the server's one stream, so the host staging
+// of a slot, and a step's host copy, are only rewritten after the device
+// work that used them has completed (observed through an event).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +24,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
+#include <cstddef>
 #include <deque>
 #include <memory>
 #include <mutex>
@@ -41,7 +44,7 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr int kStepRing = 2;  // round steps in flight per instance
+constexpr int kStepRing = 2;  // round steps in flight
 
 enum ReqState { kQueued, kRunning, kDraining, kDone, kFailed };
 
@@ -54,7 +57,6 @@ struct Request {
   int state = kQueued;
   int err = 0;
   int32_t slot = -1;
-  uint64_t admit_step = 0;  // status reads of later steps include this request
   Clock::time_point t_submit;
 };
 
@@ -69,20 +71,17 @@ struct SlotGroup {
 
 struct Instance {
   prop_problem* h = nullptr;
+  int32_t id = 0;
   int32_t n = 0;
   Problem P{};            // the problem's matrix with the server's control block
   Batch bt{};             // per-slot state; gA/gB point to the device table
-  hipStream_t stream = nullptr;
   int32_t cap = 0;        // slots
   void* d_state = nullptr;            // per-slot arrays, partials, tables, control
   std::vector<SlotGroup> groups;      // cap / 8 entries; A == nullptr when absent
   double2** h_table = nullptr;        // pinned host copy of the group tables (gA then gB)
   double2** d_table = nullptr;
   std::vector<Request*> slot_req;     // cap entries
-  int32_t* h_state[kStepRing] = {};   // pinned [active | status | rounds] x cap
-  hipEvent_t step_ev[kStepRing] = {};
-  uint64_t steps_queued = 0, steps_done = 0;
-  int running = 0;                    // requests in slots not yet seen finished
+  int running = 0;                    // requests in slots not yet reported finished
   std::deque<Request*> pending;
   int64_t fixed_bytes = 0;
   int32_t hi_groups = 0;              // 1 + highest allocated group
@@ -117,20 +116,29 @@ struct prop_server {
   int64_t next_ticket = 1;
   int64_t held = 0;                  // requests not yet read back by the caller
   int64_t device_bytes = 0, peak_bytes = 0;
+  int64_t fixed_bytes = 0;           // server and per-instance state, never released
   // statistics (under mu)
   int64_t n_submitted = 0, n_completed = 0, n_queued = 0, n_running = 0, n_steps = 0;
   std::vector<double> lat_ms;
   bool have_first = false;
   Clock::time_point t_first, t_last;
   std::thread worker;
+  // device side, created with the first instance
+  hipStream_t stream = nullptr;
+  SrvInst* d_insts = nullptr;         // kSrvMaxInstances descriptors
+  SrvStep* d_step[kStepRing] = {};
+  SrvStep* h_step[kStepRing] = {};    // pinned: the step table up, completions down
+  hipEvent_t step_ev[kStepRing] = {};
+  uint64_t steps_queued = 0, steps_done = 0;
 
   void loop();
-  bool service(Instance& I);
+  bool poll_steps();
+  bool poll_drains(Instance& I);
+  int queue_step();
   int admit(Instance& I);
   int alloc_group(Instance& I, int g);
   void free_group(Instance& I, int g);
   bool reclaim(const Instance& need);
-  int queue_step(Instance& I);
   void finish(Request* r, int state, int err);
   void fail_all(int code, const char* what);
   void charge(int64_t bytes) {
@@ -202,9 +210,9 @@ int prop_server::alloc_group(Instance& I, int g) {
   I.h_table[g] = G.A;
   I.h_table[G8 + g] = G.B;
   SRV_TRY(hipMemcpyAsync(I.d_table + g, &I.h_table[g], sizeof(double2*), hipMemcpyHostToDevice,
-                         I.stream));
+                         stream));
   SRV_TRY(hipMemcpyAsync(I.d_table + G8 + g, &I.h_table[G8 + g], sizeof(double2*),
-                         hipMemcpyHostToDevice, I.stream));
+                         hipMemcpyHostToDevice, stream));
   I.hi_groups = std::max(I.hi_groups, g + 1);
   return PROP_OK;
 }
@@ -222,7 +230,7 @@ void release_group(SlotGroup& G) {
 }
 
 void prop_server::free_group(Instance& I, int g) {
-  hipStreamSynchronize(I.stream);
+  hipStreamSynchronize(stream);
   release_group(I.groups[g]);
   const int32_t G8 = I.cap / kNodeGroup;
   I.h_table[g] = nullptr;
@@ -286,15 +294,14 @@ int prop_server::admit(Instance& I) {
     if (n) {
       std::memcpy(h, r->lb.data(), n * sizeof(double));
       std::memcpy(h + n, r->ub.data(), n * sizeof(double));
-      SRV_TRY(hipMemcpyAsync(d, h, 2 * n * sizeof(double), hipMemcpyHostToDevice, I.stream));
+      SRV_TRY(hipMemcpyAsync(d, h, 2 * n * sizeof(double), hipMemcpyHostToDevice, stream));
     }
     Batch bt = I.bt;
     bt.groups = I.hi_groups;
     bt.nodes = I.hi_groups * kNodeGroup;
-    SRV_TRY(launch_pack_batch(I.P, bt, d, d + n, slot, 1, I.stream));
-    SRV_TRY(launch_start_batch(I.P, bt, r->max_rounds, slot, 1, false, I.stream));
+    SRV_TRY(launch_pack_batch(I.P, bt, d, d + n, slot, 1, stream));
+    SRV_TRY(launch_start_batch(I.P, bt, r->max_rounds, slot, 1, false, stream));
     r->slot = slot;
-    r->admit_step = I.steps_queued;
     I.slot_req[slot] = r;
     ++G.used;
     ++I.running;
@@ -309,56 +316,80 @@ int prop_server::admit(Instance& I) {
   return admitted;
 }
 
-int prop_server::queue_step(Instance& I) {
-  Batch bt = I.bt;
-  bt.groups = I.hi_groups;
-  bt.nodes = I.hi_groups * kNodeGroup;
-  const int rounds = cfg.rounds_per_step;
-  for (int k = 0; k < rounds; ++k) SRV_TRY(launch_round_batch(I.P, bt, I.stream));
-  const int ring = (int)(I.steps_queued % kStepRing);
-  // active, status and rounds are consecutive arrays of cap entries
-  SRV_TRY(hipMemcpyAsync(I.h_state[ring], I.bt.active, 3 * (size_t)I.cap * sizeof(int32_t),
-                         hipMemcpyDeviceToHost, I.stream));
-  SRV_TRY(hipEventRecord(I.step_ev[ring], I.stream));
-  ++I.steps_queued;
+// Queues one step: the step table of every instance with running slots,
+// rounds_per_step rounds of all of them, and the step's completions back.
+int prop_server::queue_step() {
+  const int ring = (int)(steps_queued % kStepRing);
+  SrvStep& H = *h_step[ring];
+  H.n = 0;
+  H.n_done = 0;
+  int64_t rw = 0, lw = 0, cb = 0;
+  for (Instance* ip : live) {
+    Instance& I = *ip;
+    if (I.running == 0 || I.hi_groups == 0) continue;
+    SrvEntry& E = H.e[H.n++];
+    E.inst = I.id;
+    E.groups = I.hi_groups;
+    E.round_base = rw;
+    E.long_base = lw;
+    E.commit_base = cb;
+    E.commit_blocks = (int32_t)std::min<int64_t>(256, ((int64_t)I.n * kNodeGroup + kBlock - 1) / kBlock);
+    if (E.commit_blocks < 1) E.commit_blocks = 1;
+    E.pad = 0;
+    rw += (int64_t)(I.P.n_chunks + I.P.n_segs) * E.groups;
+    lw += (int64_t)I.P.n_segs * E.groups * kNodeGroup;
+    cb += (int64_t)E.commit_blocks * E.groups;
+  }
+  H.round_total = rw;
+  H.long_total = lw;
+  H.commit_total = cb;
+  if (H.n == 0) return PROP_OK;
+  SRV_TRY(hipMemcpyAsync(d_step[ring], &H, offsetof(SrvStep, e) + (size_t)H.n * sizeof(SrvEntry),
+                         hipMemcpyHostToDevice, stream));
+  for (int k = 0; k < cfg.rounds_per_step; ++k)
+    SRV_TRY(launch_srv_round(d_insts, d_step[ring], H, stream));
+  SRV_TRY(hipMemcpyAsync(&H, d_step[ring], offsetof(SrvStep, e), hipMemcpyDeviceToHost, stream));
+  SRV_TRY(hipEventRecord(step_ev[ring], stream));
+  ++steps_queued;
   std::lock_guard<std::mutex> lk(mu);
   ++n_steps;
   return PROP_OK;
 }
 
-// One pass over an instance; returns true when anything moved.
-bool prop_server::service(Instance& I) {
+// Finished steps: every reported slot is unpacked and copied out.
+bool prop_server::poll_steps() {
   bool moved = false;
-  const size_t n = (size_t)I.n;
-  // 1. finished steps: slots that went inactive are unpacked and copied out
-  while (I.steps_done < I.steps_queued) {
-    const int ring = (int)(I.steps_done % kStepRing);
-    hipError_t q = hipEventQuery(I.step_ev[ring]);
+  while (steps_done < steps_queued) {
+    const int ring = (int)(steps_done % kStepRing);
+    hipError_t q = hipEventQuery(step_ev[ring]);
     if (q == hipErrorNotReady) break;
     if (q != hipSuccess) {
       fail_all(PROP_EDEVICE, hipGetErrorString(q));
       return false;
     }
-    const uint64_t T = ++I.steps_done;  // status after step number T
-    const int32_t* act = I.h_state[ring];
-    const int32_t* st = act + I.cap;
-    const int32_t* rd = st + I.cap;
-    for (int slot = 0; slot < I.hi_groups * kNodeGroup; ++slot) {
-      Request* r = I.slot_req[slot];
-      if (!r || r->state != kRunning || r->admit_step >= T || act[slot] != 0) continue;
-      r->res.status = st[slot];
-      r->res.rounds = rd[slot];
-      const int g = slot / kNodeGroup, t = slot % kNodeGroup;
+    const SrvStep& H = *h_step[ring];
+    const uint32_t nd = std::min<uint32_t>(H.n_done, (uint32_t)kSrvStepDone);
+    for (uint32_t i = 0; i < nd; ++i) {
+      const SrvDone& D = H.done[i];
+      if (D.inst < 0 || D.inst >= (int32_t)live.size()) continue;
+      Instance& I = *live[D.inst];
+      if (D.slot < 0 || D.slot >= I.cap) continue;
+      Request* r = I.slot_req[D.slot];
+      if (!r || r->state != kRunning) continue;
+      r->res.status = D.status;
+      r->res.rounds = D.rounds;
+      const size_t n = (size_t)I.n;
+      const int g = D.slot / kNodeGroup, t = D.slot % kNodeGroup;
       SlotGroup& G = I.groups[g];
       double* d = G.d_io + (size_t)t * 2 * n;
       Batch bt = I.bt;
       bt.groups = I.hi_groups;
       bt.nodes = I.hi_groups * kNodeGroup;
-      hipError_t e = launch_unpack_batch(I.P, bt, d, d + n, slot, 1, I.stream);
+      hipError_t e = launch_unpack_batch(I.P, bt, d, d + n, D.slot, 1, stream);
       if (e == hipSuccess && n)
         e = hipMemcpyAsync(G.h_io + (size_t)t * 2 * n, d, 2 * n * sizeof(double),
-                           hipMemcpyDeviceToHost, I.stream);
-      if (e == hipSuccess) e = hipEventRecord(G.drain[t], I.stream);
+                           hipMemcpyDeviceToHost, stream);
+      if (e == hipSuccess) e = hipEventRecord(G.drain[t], stream);
       if (e != hipSuccess) {
         fail_all(PROP_EDEVICE, hipGetErrorString(e));
         return false;
@@ -366,9 +397,16 @@ bool prop_server::service(Instance& I) {
       r->state = kDraining;
       --I.running;
     }
+    ++steps_done;
     moved = true;
   }
-  // 2. drained slots: results to the request, slot freed
+  return moved;
+}
+
+// Drained slots: results to the request, slot freed.
+bool prop_server::poll_drains(Instance& I) {
+  bool moved = false;
+  const size_t n = (size_t)I.n;
   for (int slot = 0; slot < I.hi_groups * kNodeGroup; ++slot) {
     Request* r = I.slot_req[slot];
     if (!r || r->state != kDraining) continue;
@@ -394,21 +432,6 @@ bool prop_server::service(Instance& I) {
     finish(r, state, err);
     moved = true;
   }
-  // 3. admissions at this round boundary
-  const int a = admit(I);
-  if (a < 0) {
-    fail_all(a, g_error.c_str());
-    return false;
-  }
-  moved |= a > 0;
-  // 4. keep the instance's rounds going while requests run
-  if (I.running > 0 && I.steps_queued - I.steps_done < (uint64_t)kStepRing) {
-    if (queue_step(I)) {
-      fail_all(PROP_EDEVICE, g_error.c_str());
-      return false;
-    }
-    moved = true;
-  }
   return moved;
 }
 
@@ -429,12 +452,29 @@ void prop_server::loop() {
     bool moved = false;
     bool busy = false;
     if (!broken) {
+      moved |= poll_steps();
       for (Instance* ip : live) {
-        Instance& I = *ip;
-        moved |= service(I);
-        busy |= I.running > 0 || I.steps_done < I.steps_queued || !I.pending.empty();
-        for (Request* r : I.slot_req) busy |= r && r->state == kDraining;
         if (broken) break;
+        Instance& I = *ip;
+        moved |= poll_drains(I);
+        if (broken) break;
+        const int a = admit(I);
+        if (a < 0) {
+          fail_all(a, g_error.c_str());
+          break;
+        }
+        moved |= a > 0;
+      }
+      bool running = false;
+      for (Instance* ip : live) {
+        running |= ip->running > 0;
+        busy |= ip->running > 0 || !ip->pending.empty();
+        for (Request* r : ip->slot_req) busy |= r && r->state == kDraining;
+      }
+      busy |= steps_done < steps_queued;
+      if (!broken && running && steps_queued - steps_done < (uint64_t)kStepRing) {
+        if (queue_step()) fail_all(PROP_EDEVICE, g_error.c_str());
+        moved = true;
       }
     }
     lk.lock();
@@ -476,17 +516,51 @@ int prop_srv_create(const prop_srv_config* cfg, prop_server** out) {
   return PROP_OK;
 }
 
+// Device-wide state of the server, created with its first instance.
+static int srv_device_init(prop_server* s) {
+  if (s->stream) return PROP_OK;
+  const int64_t bytes = kSrvMaxInstances * sizeof(SrvInst) + kStepRing * sizeof(SrvStep);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->device_bytes + bytes > s->cfg.budget_bytes)
+      return fail(PROP_ENOMEM, "server state (%lld bytes) exceeds the budget", (long long)bytes);
+  }
+  HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+  HIP_TRY(hipMalloc((void**)&s->d_insts, kSrvMaxInstances * sizeof(SrvInst)));
+  for (int i = 0; i < kStepRing; ++i) {
+    HIP_TRY(hipMalloc((void**)&s->d_step[i], sizeof(SrvStep)));
+    HIP_TRY(hipHostMalloc((void**)&s->h_step[i], sizeof(SrvStep), hipHostMallocDefault));
+    std::memset(s->h_step[i], 0, sizeof(SrvStep));
+    HIP_TRY(hipEventCreateWithFlags(&s->step_ev[i], hipEventDisableTiming));
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->device_bytes += bytes;
+  s->fixed_bytes += bytes;
+  s->peak_bytes = std::max(s->peak_bytes, s->device_bytes);
+  return PROP_OK;
+}
+
 int prop_srv_add_instance(prop_server* s, prop_problem* p, int32_t* id) {
   if (!s || !p || !id) return fail(PROP_EINVAL, "NULL argument");
   HIP_TRY(hipSetDevice(p->device));
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->broken) return fail(s->broken, "server failed: %s", s->broken_msg.c_str());
+    if ((int)s->insts.size() >= kSrvMaxInstances)
+      return fail(PROP_EINVAL, "a server holds at most %d instances", kSrvMaxInstances);
+    if (!s->insts.empty() && s->insts[0]->h->device != p->device)
+      return fail(PROP_EINVAL, "every instance of a server must live on one device");
+  }
+  int rc = srv_device_init(s);
+  if (rc) return rc;
   auto I = std::make_unique<Instance>();
   I->h = p;
   I->n = p->n;
   I->cap = s->cfg.max_slots;
   const int32_t cap = I->cap, G8 = cap / kNodeGroup;
   const int32_t segs = p->P.n_segs;
-  // one allocation: 7 per-slot arrays, partials, the two group tables, control
-  const size_t slot_arrays = 7 * (size_t)cap * sizeof(int32_t);
+  // one allocation: 8 per-slot arrays, partials, the two group tables, control
+  const size_t slot_arrays = 8 * (size_t)cap * sizeof(int32_t);
   const size_t part_off = (slot_arrays + 255) & ~(size_t)255;
   const size_t part_bytes = (size_t)(segs > 0 ? segs : 1) * cap * sizeof(SegPartial);
   const size_t table_off = (part_off + part_bytes + 255) & ~(size_t)255;
@@ -494,19 +568,12 @@ int prop_srv_add_instance(prop_server* s, prop_problem* p, int32_t* id) {
   const size_t total = ctrl_off + sizeof(Ctrl);
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->broken) return fail(s->broken, "server failed: %s", s->broken_msg.c_str());
     if (s->device_bytes + (int64_t)total > s->cfg.budget_bytes)
       return fail(PROP_ENOMEM, "instance state (%zu bytes) exceeds the remaining budget", total);
   }
-  HIP_TRY(hipStreamCreateWithFlags(&I->stream, hipStreamNonBlocking));
   auto cleanup = [&]() {
     if (I->d_state) hipFree(I->d_state);
     if (I->h_table) hipHostFree(I->h_table);
-    for (auto& h : I->h_state)
-      if (h) hipHostFree(h);
-    for (auto& e : I->step_ev)
-      if (e) hipEventDestroy(e);
-    hipStreamDestroy(I->stream);
   };
   if (hipMalloc(&I->d_state, total) != hipSuccess) {
     cleanup();
@@ -526,36 +593,39 @@ int prop_srv_add_instance(prop_server* s, prop_problem* p, int32_t* id) {
   bt.infeasible = reinterpret_cast<uint32_t*>(arr + 4 * cap);
   bt.invalid = reinterpret_cast<uint32_t*>(arr + 5 * cap);
   bt.maxr = arr + 6 * cap;
+  bt.live = reinterpret_cast<uint32_t*>(arr + 7 * cap);
   bt.partials = reinterpret_cast<SegPartial*>(base + part_off);
   I->d_table = reinterpret_cast<double2**>(base + table_off);
   bt.gA = I->d_table;
   bt.gB = I->d_table + G8;
+  bt.nodes = cap;
+  bt.groups = G8;
   I->P = p->P;
   I->P.ctrl = reinterpret_cast<Ctrl*>(base + ctrl_off);
   I->groups.resize(G8);
   I->slot_req.assign(cap, nullptr);
   I->fixed_bytes = (int64_t)total;
-  for (auto& h : I->h_state)
-    if (hipHostMalloc((void**)&h, 3 * (size_t)cap * sizeof(int32_t), hipHostMallocDefault) !=
-        hipSuccess) {
-      cleanup();
-      return fail(PROP_ENOMEM, "pinned host allocation failed");
-    }
   if (hipHostMalloc((void**)&I->h_table, 2 * (size_t)G8 * sizeof(double2*),
                     hipHostMallocDefault) != hipSuccess) {
     cleanup();
     return fail(PROP_ENOMEM, "pinned host allocation failed");
   }
   std::memset(I->h_table, 0, 2 * (size_t)G8 * sizeof(double2*));
-  for (auto& e : I->step_ev)
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-      cleanup();
-      return fail(PROP_EDEVICE, "hipEventCreate failed");
-    }
   std::lock_guard<std::mutex> lk(s->mu);
+  I->id = (int32_t)s->insts.size();
+  // the descriptor the serving kernels read; written before the instance is
+  // visible to the scheduler, so no queued kernel can read this entry yet
+  SrvInst desc;
+  desc.P = I->P;
+  desc.bt = I->bt;
+  if (hipMemcpy(s->d_insts + I->id, &desc, sizeof(SrvInst), hipMemcpyHostToDevice) != hipSuccess) {
+    cleanup();
+    return fail(PROP_EDEVICE, "upload of the instance descriptor failed");
+  }
   s->device_bytes += (int64_t)total;
+  s->fixed_bytes += (int64_t)total;
   s->peak_bytes = std::max(s->peak_bytes, s->device_bytes);
-  *id = (int32_t)s->insts.size();
+  *id = I->id;
   s->insts.push_back(std::move(I));
   g_error.clear();
   return PROP_OK;
@@ -570,9 +640,13 @@ int prop_srv_submit(prop_server* s, int32_t id, const double* lb, const double* 
     std::lock_guard<std::mutex> lk(s->mu);
     if (id < 0 || id >= (int32_t)s->insts.size()) return fail(PROP_EINVAL, "unknown instance %d", id);
     n = s->insts[id]->n;
-    if (group_bytes(n) + s->insts[id]->fixed_bytes > s->cfg.budget_bytes)
-      return fail(PROP_ENOMEM, "one slot group of instance %d (%lld bytes) exceeds the budget", id,
-                  (long long)group_bytes(n));
+    // the state of the server and of every instance is never released: a
+    // group must fit beside it, or the request could never be admitted
+    if (group_bytes(n) + s->fixed_bytes > s->cfg.budget_bytes)
+      return fail(PROP_ENOMEM,
+                  "one slot group of instance %d (%lld bytes) does not fit the budget beside "
+                  "the server's fixed state (%lld bytes)",
+                  id, (long long)group_bytes(n), (long long)s->fixed_bytes);
   }
   if (n > 0 && (!lb || !ub)) return fail(PROP_EINVAL, "bound arrays are NULL");
   for (int32_t j = 0; j < n; ++j)
@@ -700,19 +774,21 @@ void prop_srv_destroy(prop_server* s) {
     s->cv_work.notify_all();
   }
   if (s->worker.joinable()) s->worker.join();
+  if (!s->insts.empty()) hipSetDevice(s->insts[0]->h->device);
+  if (s->stream) hipStreamSynchronize(s->stream);
   for (auto& up : s->insts) {
     Instance& I = *up;
-    hipSetDevice(I.h->device);
-    hipStreamSynchronize(I.stream);
     for (auto& G : I.groups) release_group(G);
     if (I.d_state) hipFree(I.d_state);
     if (I.h_table) hipHostFree(I.h_table);
-    for (auto& h : I.h_state)
-      if (h) hipHostFree(h);
-    for (auto& e : I.step_ev)
-      if (e) hipEventDestroy(e);
-    hipStreamDestroy(I.stream);
   }
+  if (s->d_insts) hipFree(s->d_insts);
+  for (int i = 0; i < kStepRing; ++i) {
+    if (s->d_step[i]) hipFree(s->d_step[i]);
+    if (s->h_step[i]) hipHostFree(s->h_step[i]);
+    if (s->step_ev[i]) hipEventDestroy(s->step_ev[i]);
+  }
+  if (s->stream) hipStreamDestroy(s->stream);
   delete s;
 }
 
