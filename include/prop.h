@@ -152,6 +152,21 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
 /* Selects the round-loop driver (PROP_LOOP_*) for later runs. */
 int prop_set_loop(prop_problem* p, int32_t mode);
 
+/* Marked rounds (enable != 0; off by default), for prop_run and
+ * prop_run_device with the stream or host driver (the persistent driver and
+ * batches ignore it).  A row is then processed in round r >= 2 only when
+ * one of its variables changed in round r - 1: a row whose variables did
+ * not change would compute the activities and candidates of the previous
+ * round, against the same bounds, and those changed nothing (a candidate
+ * that counted would have changed its variable).  Results, status and round
+ * counts are bitwise those of unmarked rounds; when more than n / 32
+ * variables changed, the next round processes every row.  This is the
+ * constraint marking of the paper's sequential Algorithm 1 applied to the
+ * synchronous rounds of Algorithm 2.  The first enable uploads the rows of
+ * every variable (4 bytes per nonzero, 8 per variable) and a row stamp per
+ * row; these stay until prop_destroy. */
+int prop_set_marking(prop_problem* p, int32_t enable);
+
 /* Fills *out with the problem's sizes. */
 int prop_get_info(const prop_problem* p, prop_info* out);
 

@@ -24,7 +24,7 @@ LOOP_NAMES = {"persistent": LOOP_PERSISTENT, "stream": LOOP_STREAM, "host": LOOP
 
 # every function the header declares
 EXPORTED = ("prop_create", "prop_run", "prop_run_device", "prop_run_batch_device",
-            "prop_set_loop", "prop_get_info",
+            "prop_set_loop", "prop_set_marking", "prop_get_info",
             "prop_last_timing", "prop_set_kernel_timing", "prop_last_kernel_timing",
             "prop_destroy", "prop_last_error",
             "prop_srv_create", "prop_srv_add_instance", "prop_srv_submit", "prop_srv_poll",
@@ -100,6 +100,8 @@ def _load():
     lib.prop_run_batch_device.restype = ctypes.c_int
     lib.prop_set_loop.argtypes = [P, i32]
     lib.prop_set_loop.restype = ctypes.c_int
+    lib.prop_set_marking.argtypes = [P, i32]
+    lib.prop_set_marking.restype = ctypes.c_int
     lib.prop_get_info.argtypes = [P, ctypes.POINTER(_Info)]
     lib.prop_get_info.restype = ctypes.c_int
     lib.prop_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double),
@@ -261,6 +263,11 @@ class Problem:
         if isinstance(mode, str):
             mode = LOOP_NAMES[mode]
         _check(lib.prop_set_loop(self._h, int(mode)))
+
+    def set_marking(self, enable: bool):
+        """Marked rounds: skip rows none of whose variables changed in the
+        previous round (results unchanged)."""
+        _check(lib.prop_set_marking(self._h, 1 if enable else 0))
 
     def info(self) -> dict:
         inf = _Info()

@@ -339,10 +339,15 @@ __device__ __forceinline__ bool entry_passes(const RowState& R, float emin, floa
 // line with a plain sparse product.  In a batch, nodes after the first find
 // the chunk's matrix data in cache.
 // ---------------------------------------------------------------------------
+// With `marked` (single runs in marked rounds), rows not stamped with round
+// r are skipped: none of their variables changed in the previous round, so
+// their activities and candidates are those of that round, which changed
+// nothing.
 __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd,
                                             const double2* __restrict__ cur,
                                             double2* __restrict__ nxt, uint32_t stride,
-                                            uint32_t node_mask) {
+                                            uint32_t node_mask, bool marked = false,
+                                            int r_round = 0) {
   const int lane = threadIdx.x & (kWave - 1);
   const int klog = cd.meta & 7;
   const int W = (cd.meta >> 8) & 0xff;
@@ -351,6 +356,8 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
   const size_t base = (size_t)cd.off64 * kWave + lane;
   const bool row_ok = r < nrows;
   const int row = cd.row0 + (row_ok ? r : 0);
+  const bool want = !marked || (row_ok && P.row_mark[row] == r_round);
+  if (marked && __ballot(want) == 0) return;
   const double lhs = P.lhs[row], rhs = P.rhs[row];
   for (uint32_t mask = node_mask; mask; mask &= mask - 1) {
     const uint32_t t = __builtin_ctz(mask);
@@ -361,7 +368,7 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
     for (int w = 0; w < kMaxSteps; ++w) {
       emin[w] = -__builtin_inff();
       emax[w] = -__builtin_inff();
-      if (w < W) {
+      if (w < W && want) {
         const size_t e = base + (size_t)w * kWave;
         // a single run reads the matrix once: stream it past the caches
         const double a = stride == 1 ? __builtin_nontemporal_load(P.vals + e) : P.vals[e];
@@ -374,7 +381,7 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
       }
     }
     group_reduce(smin, smax, cmin, cmax, klog);
-    if (!row_ok) continue;
+    if (!row_ok || !want) continue;
     const RowState R = make_row_state(smin, smax, cmin, cmax, lhs, rhs);
     if (!(R.min_side || R.max_side)) continue;
     // a step no lane needs is skipped by the wave
@@ -393,8 +400,9 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
 
 __device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const double2* cur,
                                                double2* nxt, uint32_t stride,
-                                               uint32_t node_mask) {
-  chunk_round(P, P.chunks[c], cur, nxt, stride, node_mask);
+                                               uint32_t node_mask, bool marked = false,
+                                               int r_round = 0) {
+  chunk_round(P, P.chunks[c], cur, nxt, stride, node_mask, marked, r_round);
 }
 
 // ---------------------------------------------------------------------------
@@ -538,9 +546,11 @@ __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkD
 __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
                                            const double2* __restrict__ cur, uint32_t stride,
                                            uint32_t node_mask, SegPartial* parts,
-                                           uint32_t pstride, uint32_t node0) {
+                                           uint32_t pstride, uint32_t node0, bool marked = false,
+                                           int r_round = 0) {
   const int lane = threadIdx.x & (kWave - 1);
   const SegDesc sd = P.segs[s];
+  if (marked && P.row_mark[sd.row] != r_round) return;
   double a[kMaxSteps];
   int32_t jj[kMaxSteps];
 #pragma unroll
@@ -663,9 +673,10 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
                                            const double2* __restrict__ cur,
                                            double2* __restrict__ nxt, uint32_t stride, uint32_t t,
                                            const SegPartial* parts, uint32_t pstride,
-                                           uint32_t node) {
+                                           uint32_t node, bool marked = false, int r_round = 0) {
   const int lane = threadIdx.x & (kWave - 1);
   const SegDesc sd = P.segs[s];
+  if (marked && P.row_mark[sd.row] != r_round) return;
   DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
   int cmin = 0, cmax = 0;
   for (int q = lane; q < sd.nseg; q += kWave) {
@@ -700,35 +711,62 @@ __device__ __forceinline__ uint32_t u32_load(const uint32_t* p) {
 }
 
 // Per-thread part over a grid-stride range.
+// In marked rounds every changed variable is appended to the round's list,
+// one entry per kMarkPiece of its rows; the loop keeps the 64 lanes of a
+// wave together (consecutive variables) so that the wave can add its
+// entries with one atomic.
 __device__ __forceinline__ void commit_range(const Problem& P, uint32_t tid, uint32_t nthreads,
                                              uint32_t& changed, uint32_t& infeasible) {
   double2* A = P.bnd[0];
   double2* B = P.bnd[1];
-  for (uint32_t v = tid; v < (uint32_t)P.n; v += nthreads) {
-    const double2 a = A[v];
-    double2 b;
-    if (v < (uint32_t)P.n_hot) {
-      // a hot variable's candidates sit in its stripe copies (B is not a
-      // target for it): merge them into the committed pair, reset them
-      b = a;
-      double2* st = P.stripes + v;
+  const uint32_t lane = tid & (kWave - 1);
+  for (uint32_t v0 = tid - lane; v0 < (uint32_t)P.n; v0 += nthreads) {
+    const uint32_t v = v0 + lane;
+    bool chg = false;
+    if (v < (uint32_t)P.n) {
+      const double2 a = A[v];
+      double2 b;
+      if (v < (uint32_t)P.n_hot) {
+        // a hot variable's candidates sit in its stripe copies (B is not a
+        // target for it): merge them into the committed pair, reset them
+        b = a;
+        double2* st = P.stripes + v;
 #pragma unroll 8
-      for (int c = 0; c < kStripes; ++c) {
-        const double2 q = st[(size_t)c * P.n_hot];
-        b.x = q.x > b.x ? q.x : b.x;
-        b.y = q.y < b.y ? q.y : b.y;
+        for (int c = 0; c < kStripes; ++c) {
+          const double2 q = st[(size_t)c * P.n_hot];
+          b.x = q.x > b.x ? q.x : b.x;
+          b.y = q.y < b.y ? q.y : b.y;
+        }
+#pragma unroll 8
+        for (int c = 0; c < kStripes; ++c)
+          st[(size_t)c * P.n_hot] = make_double2(-__builtin_inf(), __builtin_inf());
+      } else {
+        b = B[v];
       }
-#pragma unroll 8
-      for (int c = 0; c < kStripes; ++c)
-        st[(size_t)c * P.n_hot] = make_double2(-__builtin_inf(), __builtin_inf());
-    } else {
-      b = B[v];
+      if (a.x != b.x || a.y != b.y) {
+        A[v] = b;
+        B[v] = b;
+        ++changed;
+        chg = true;
+        if (domain_empty(P.vtype[v] != 0, b.x, b.y, P.feas_tol)) infeasible = 1;
+      }
     }
-    if (a.x != b.x || a.y != b.y) {
-      A[v] = b;
-      B[v] = b;
-      ++changed;
-      if (domain_empty(P.vtype[v] != 0, b.x, b.y, P.feas_tol)) infeasible = 1;
+    if (P.marking) {
+      uint32_t np = 0;
+      if (chg) np = (uint32_t)((P.var_ptr[v + 1] - P.var_ptr[v] + kMarkPiece - 1) / kMarkPiece);
+      uint32_t x = np;  // inclusive prefix over the wave
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, kWave);
+        if (lane >= (uint32_t)off) x += y;
+      }
+      const uint32_t total = __shfl(x, kWave - 1, kWave);
+      if (total) {
+        uint32_t base = 0;
+        if (lane == kWave - 1) base = atomicAdd(&P.ctrl->n_chg, total);
+        base = __shfl(base, kWave - 1, kWave) + (x - np);
+        for (uint32_t q = 0; q < np; ++q) P.chg_list[base + q] = ((uint64_t)v << 32) | q;
+      }
     }
   }
 }
@@ -762,6 +800,11 @@ __device__ __forceinline__ void end_of_round(const Problem& P, int r, int max_ro
                                              uint32_t changed, uint32_t infeasible) {
   Ctrl* C = P.ctrl;
   C->round = r + 1;
+  if (P.marking)
+    C->mark_all = __hip_atomic_load(&C->n_chg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >
+                          (uint32_t)(P.n / kMarkAllDiv)
+                      ? 1u
+                      : 0u;
   if (infeasible) {
     C->status = kInfeasible;
     C->rounds = r;

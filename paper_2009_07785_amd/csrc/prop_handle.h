@@ -57,4 +57,10 @@ struct prop_problem {
   std::vector<void*> batch_allocs;
   int32_t* h_bstatus = nullptr;  // pinned copies of per-node status / rounds
   int32_t* h_brounds = nullptr;
+  // marked rounds: rows of each variable (internal orders), uploaded on the
+  // first prop_set_marking(p, 1)
+  bool marking = false;
+  bool mark_ready = false;
+  std::vector<int64_t> h_var_ptr;
+  std::vector<int32_t> h_var_rows;
 };

@@ -306,6 +306,29 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   if ((int64_t)h_lhs.size() != n_rows_internal)
     return fail(PROP_EINVAL, "internal layout check failed (rows)");
 
+  // rows of each variable in the internal orders, for marked rounds
+  {
+    std::vector<int64_t>& vp = p->h_var_ptr;
+    std::vector<int32_t>& vr = p->h_var_rows;
+    vp.assign((size_t)n + 1, 0);
+    auto each_entry = [&](auto&& fn) {
+      for (const ChunkDesc& d : h_chunks) {
+        const int W = (d.meta >> 8) & 0xff, kl = d.meta & 7;
+        const int64_t b = (int64_t)d.off64 * kWave;
+        for (int64_t q = 0; q < (int64_t)W * kWave; ++q)
+          if (h_vals[b + q] != 0.0) fn(h_cols[b + q] & kColMask, d.row0 + (int32_t)((q % kWave) >> kl));
+      }
+      for (const SegDesc& d : h_segs)
+        for (int64_t q = d.off; q < d.off + d.len; ++q)
+          if (h_vals[q] != 0.0) fn(h_cols[q] & kColMask, d.row);
+    };
+    each_entry([&](int32_t v, int32_t) { ++vp[(size_t)v + 1]; });
+    for (int32_t j = 0; j < n; ++j) vp[(size_t)j + 1] += vp[j];
+    vr.assign((size_t)vp[n], 0);
+    std::vector<int64_t> fill(vp.begin(), vp.end() - 1);
+    each_entry([&](int32_t v, int32_t row) { vr[(size_t)fill[v]++] = row; });
+  }
+
   Problem& P = p->P;
   int rc;
   double* d_vals;
@@ -340,6 +363,8 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   if ((rc = dev_alloc(p, &p->d_stage_ub, (size_t)n))) return rc;
 
   P.vals = d_vals;
+  P.n_rows = (int32_t)n_rows_internal;
+  P.marking = 0;
   P.cols = d_cols;
   P.chunks = d_chunks;
   P.segs = d_segs;
@@ -557,6 +582,8 @@ int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rou
   if (p->n > 0 && (!d_lb || !d_ub)) return fail(PROP_EINVAL, "bound arrays are NULL");
   HIP_TRY(hipSetDevice(p->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // marked rounds need the per-round kernel sequence of the stream / host drivers
+  p->P.marking = (p->marking && p->loop_mode != PROP_LOOP_PERSISTENT) ? 1 : 0;
   const Problem& P = p->P;
   HIP_TRY(hipEventRecord(p->ev[0], s));
   HIP_TRY(launch_init(P, s));
@@ -619,6 +646,7 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
   HIP_TRY(hipSetDevice(p->device));
   int rc = ensure_batch(p, nodes);
   if (rc) return rc;
+  p->P.marking = 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Problem& P = p->P;
   Batch bt = p->bt;
@@ -677,6 +705,34 @@ int prop_set_loop(prop_problem* p, int32_t mode) {
   if (mode != PROP_LOOP_PERSISTENT && mode != PROP_LOOP_STREAM && mode != PROP_LOOP_HOST)
     return fail(PROP_EINVAL, "unknown loop mode %d", mode);
   p->loop_mode = mode;
+  return PROP_OK;
+}
+
+int prop_set_marking(prop_problem* p, int32_t enable) {
+  if (!p) return fail(PROP_EINVAL, "NULL problem");
+  if (enable && !p->mark_ready) {
+    HIP_TRY(hipSetDevice(p->device));
+    Problem& P = p->P;
+    int64_t* vp;
+    int32_t *vr, *marks;
+    uint64_t* list;
+    int rc;
+    if ((rc = dev_upload(p, &vp, p->h_var_ptr))) return rc;
+    if ((rc = dev_upload(p, &vr, p->h_var_rows))) return rc;
+    if ((rc = dev_alloc(p, &marks, (size_t)(P.n_rows > 0 ? P.n_rows : 1)))) return rc;
+    HIP_TRY(hipMemset(marks, 0, sizeof(int32_t) * (size_t)(P.n_rows > 0 ? P.n_rows : 1)));
+    // a round lists each changed variable once, one entry per kMarkPiece rows
+    const size_t cap = (size_t)p->n + (size_t)(p->h_var_rows.size() / kMarkPiece) + kWave;
+    if ((rc = dev_alloc(p, &list, cap))) return rc;
+    P.var_ptr = vp;
+    P.var_rows = vr;
+    P.row_mark = marks;
+    P.chg_list = list;
+    std::vector<int64_t>().swap(p->h_var_ptr);
+    std::vector<int32_t>().swap(p->h_var_rows);
+    p->mark_ready = true;
+  }
+  p->marking = enable != 0;
   return PROP_OK;
 }
 

@@ -29,6 +29,8 @@ __global__ void k_init(Problem P) {
     C->bar_count = 0;
     C->bar_gen = 0;
     C->abort = 0;
+    C->n_chg = 0;
+    C->mark_all = 1;
   }
 }
 
@@ -117,20 +119,45 @@ __global__ void k_start(Problem P, int max_rounds) {
   if (blockIdx.x == 0 && threadIdx.x == 0) start_status(P, max_rounds);
 }
 
-__global__ __launch_bounds__(kBlock) void k_round(Problem P) {
+// Marked rounds: whether round r skips unstamped rows (read once per wave).
+__device__ __forceinline__ bool marked_round(const Problem& P) {
+  return P.marking && !u32_load(&P.ctrl->mark_all);
+}
+
+__global__ __launch_bounds__(kBlock) void k_round(Problem P, int r) {
+  if (P.marking && blockIdx.x == 0 && threadIdx.x == 0) P.ctrl->n_chg = 0;  // list of round r
   if (u32_load(&P.ctrl->done)) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = blockIdx.x * kWavesPerBlock + wave;
-  if (item < P.n_segs) seg_phase1(P, item, P.bnd[0], 1, 1, P.partials, 1, 0);
+  const bool marked = marked_round(P);
+  if (item < P.n_segs) seg_phase1(P, item, P.bnd[0], 1, 1, P.partials, 1, 0, marked, r);
   else if (item - P.n_segs < P.n_chunks)
-    chunk_dispatch(P, item - P.n_segs, P.bnd[0], P.bnd[1], 1, 1);
+    chunk_dispatch(P, item - P.n_segs, P.bnd[0], P.bnd[1], 1, 1, marked, r);
 }
 
-__global__ __launch_bounds__(kBlock) void k_round_long(Problem P) {
+__global__ __launch_bounds__(kBlock) void k_round_long(Problem P, int r) {
   if (u32_load(&P.ctrl->done)) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int s = blockIdx.x * kWavesPerBlock + wave;
-  if (s < P.n_segs) seg_phase2(P, s, P.bnd[0], P.bnd[1], 1, 0, P.partials, 1, 0);
+  if (s < P.n_segs) seg_phase2(P, s, P.bnd[0], P.bnd[1], 1, 0, P.partials, 1, 0, marked_round(P), r);
+}
+
+// Marked rounds, after the commit of round r: stamps the rows of every
+// changed variable with r + 1 (one wave per list entry), unless the next
+// round runs over every row anyway.
+__global__ __launch_bounds__(kBlock) void k_mark(Problem P, int r) {
+  const Ctrl* C = P.ctrl;
+  if (u32_load(&C->done) || u32_load(&C->mark_all)) return;
+  const uint32_t cnt = u32_load(&C->n_chg);
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t nw = gridDim.x * kWavesPerBlock;
+  for (uint32_t e = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); e < cnt; e += nw) {
+    const uint64_t item = P.chg_list[e];
+    const uint32_t v = (uint32_t)(item >> 32), piece = (uint32_t)item;
+    const int64_t start = P.var_ptr[v] + (int64_t)piece * kMarkPiece;
+    const int64_t stop = P.var_ptr[v + 1] < start + kMarkPiece ? P.var_ptr[v + 1] : start + kMarkPiece;
+    for (int64_t i = start + lane; i < stop; i += kWave) P.row_mark[P.var_rows[i]] = r + 1;
+  }
 }
 
 // Commit of round r; the last block to finish decides the status.
@@ -198,14 +225,16 @@ hipError_t launch_round(const Problem& P, int r, int max_rounds, hipStream_t s, 
   const int items = P.n_chunks + P.n_segs;
   if (e0) hipEventRecord(e0, s);
   hipLaunchKernelGGL(k_round, dim3(blocks_for(items, kWavesPerBlock, 1 << 30)), dim3(kBlock), 0,
-                     s, P);
+                     s, P, r);
   if (e1) hipEventRecord(e1, s);
   if (P.n_segs)
     hipLaunchKernelGGL(k_round_long, dim3(blocks_for(P.n_segs, kWavesPerBlock, 1 << 30)),
-                       dim3(kBlock), 0, s, P);
+                       dim3(kBlock), 0, s, P, r);
   // at most 65535 blocks: the packed commit counter keeps 16 bits per field
   hipLaunchKernelGGL(k_commit, dim3(blocks_for(P.n, kBlock, 1024)), dim3(kBlock), 0, s, P, r,
                      max_rounds);
+  if (P.marking)
+    hipLaunchKernelGGL(k_mark, dim3(1024), dim3(kBlock), 0, s, P, r);
   return hipGetLastError();
 }
 

@@ -91,7 +91,9 @@ struct Ctrl {
   uint32_t bar_count;      // grid barrier arrival counter
   uint32_t bar_gen;        // grid barrier generation
   uint32_t abort;          // barrier wait gave up (device timeout)
-  uint32_t pad[5];
+  uint32_t n_chg;          // marked rounds: entries in the changed-variable list
+  uint32_t mark_all;       // marked rounds: the next round processes every row
+  uint32_t pad[3];
 };
 
 // Everything a kernel needs, passed by value.
@@ -118,7 +120,20 @@ struct Problem {
   Ctrl* ctrl;
   // parameters
   double eps_int, cont_rel_tol, feas_tol;
+  // marked rounds (marking != 0): a row is processed in round r only when
+  // row_mark[row] == r, i.e. one of its variables changed in round r - 1
+  int32_t marking;
+  int32_t n_rows;           // rows of the internal order (chunk rows, then long rows)
+  int32_t* row_mark;        // [n_rows]
+  const int64_t* var_ptr;   // [n + 1] rows of each variable, internal orders
+  const int32_t* var_rows;
+  uint64_t* chg_list;       // (variable << 32 | piece) changed in the current round
 };
+
+// Rows of one variable marked by one wave; a round whose changed variables
+// exceed n / kMarkAllDiv runs the next round over every row instead.
+constexpr int kMarkPiece = 2048;
+constexpr int kMarkAllDiv = 32;
 
 // Batch of branch-and-bound nodes sharing one problem.  Bounds of node
 // k = 8 g + t for variable j sit at A[(g * n + j) * 8 + t]: the 8 nodes of a

@@ -184,6 +184,32 @@ def test_edge_cases(lib):
     check_against_oracle(lib, inst)
 
 
+def test_marked_rounds(lib):
+    """Marked rounds give bitwise the results of unmarked ones (and of the
+    oracle), with the stream and the host driver; the persistent driver
+    ignores the switch."""
+    cases = [synth.config0(), synth.config1(1), synth.layout_mix(0), synth.layout_mix(2),
+             synth.config3_matrix(50_000, 25_000), pins.cascade_instance(99)]
+    for inst in cases:
+        ref = oracle.run(inst, inst.lb, inst.ub, 100)
+        with lib.Problem.from_instance(inst) as p:
+            p.set_marking(True)
+            for loop in ("stream", "host", "persistent"):
+                p.set_loop(loop)
+                say(f"  marked {inst.name} loop={loop}")
+                assert_same(f"marked {inst.name}/{loop}", p.run(inst.lb, inst.ub, 100), ref)
+            # nodes of a search: marked rounds from fixed bounds, then again
+            # after switching marking off and on
+            for k in range(3 if inst.x0 is not None else 0):
+                lb, ub = synth.node_bounds(inst, 31_000 + k, frac_hi=0.2, only_int=False)
+                r1 = oracle.run(inst, lb, ub, 100)
+                p.set_loop("stream")
+                assert_same(f"marked node {inst.name}/{k}", p.run(lb, ub, 100), r1)
+                p.set_marking(False)
+                assert_same(f"unmarked node {inst.name}/{k}", p.run(lb, ub, 100), r1)
+                p.set_marking(True)
+
+
 def test_invalid_bounds_rejected(lib):
     inst = synth.config0()
     with lib.Problem.from_instance(inst) as p:
@@ -250,6 +276,19 @@ def test_config2_full_run_lockstep(lib, big):
     # x0 stays inside
     tol = 1e-6 * np.maximum(1.0, np.abs(inst.x0))
     assert np.all(lb - tol <= inst.x0) and np.all(inst.x0 <= ub + tol)
+
+
+def test_config2_marked_full_run(lib, big):
+    """Marked rounds on the full instance: bitwise the unmarked result."""
+    inst, p = big
+    res0, lb0, ub0 = p.run(inst.lb, inst.ub, 100)
+    p.set_marking(True)
+    try:
+        res1, lb1, ub1 = p.run(inst.lb, inst.ub, 100)
+    finally:
+        p.set_marking(False)
+    assert (res1.status, res1.rounds) == (res0.status, res0.rounds)
+    assert np.array_equal(lb1, lb0) and np.array_equal(ub1, ub0)
 
 
 def test_config2_round2_lockstep(lib, big):

@@ -183,3 +183,26 @@ def test_serving_errors_and_budget(lib, pool):
             srv.poll(t1, inst.n)  # released
         t3 = srv.submit(i, inst.lb, inst.ub, 100)  # room again
         assert srv.wait(t3, inst.n, timeout_ms=60_000) is not None
+
+
+def test_serving_completion_list_overflow(lib, pool):
+    """More requests finish in one round than a step's completion list holds
+    (512): the rest are reported in later rounds, none is lost or repeated."""
+    insts, probs = pool
+    k = int(np.argmin([i.n for i in insts]))
+    inst = insts[k]
+    with lib.Server(1 << 30, max_slots=1024, rounds_per_step=1) as srv:
+        i = srv.add_instance(probs[k])
+        # a zero round limit finishes every request at its start
+        tickets = [srv.submit(i, inst.lb, inst.ub, 0) for _ in range(700)]
+        tickets += [srv.submit(i, inst.lb, inst.ub, 1) for _ in range(300)]
+        res = [srv.wait(t, inst.n, timeout_ms=60_000) for t in tickets]
+        st = srv.stats()
+    assert all(r is not None for r in res)
+    assert [r[0].rounds for r in res] == [0] * 700 + [1] * 300
+    assert all(r[0].status == oracle.MAX_ROUNDS for r in res[:700])
+    assert st["completed"] == 1000 and st["running"] == 0
+    ref = probs[k].run(inst.lb, inst.ub, 1)
+    for r in res[700:]:
+        assert (r[0].status, r[0].rounds) == (ref[0].status, ref[0].rounds)
+        assert np.array_equal(r[1], ref[1]) and np.array_equal(r[2], ref[2])
