@@ -163,8 +163,9 @@ int prop_set_loop(prop_problem* p, int32_t mode);
  * variables changed, the next round processes every row.  This is the
  * constraint marking of the paper's sequential Algorithm 1 applied to the
  * synchronous rounds of Algorithm 2.  The first enable uploads the rows of
- * every variable (4 bytes per nonzero, 8 per variable) and a row stamp per
- * row; these stay until prop_destroy. */
+ * every variable (4 bytes per nonzero, 8 per variable, 12 per piece of 64
+ * rows of a variable), a row stamp per row and a changed-variable bitmap;
+ * these stay until prop_destroy. */
 int prop_set_marking(prop_problem* p, int32_t enable);
 
 /* Fills *out with the problem's sizes. */

@@ -711,10 +711,9 @@ __device__ __forceinline__ uint32_t u32_load(const uint32_t* p) {
 }
 
 // Per-thread part over a grid-stride range.
-// In marked rounds every changed variable is appended to the round's list,
-// one entry per kMarkPiece of its rows; the loop keeps the 64 lanes of a
-// wave together (consecutive variables) so that the wave can add its
-// entries with one atomic.
+// In marked rounds every wave also stores the changed flags of its 64
+// consecutive variables as one word of the round's bitmap; the loop keeps
+// the lanes of a wave together for that.
 __device__ __forceinline__ void commit_range(const Problem& P, uint32_t tid, uint32_t nthreads,
                                              uint32_t& changed, uint32_t& infeasible) {
   double2* A = P.bnd[0];
@@ -752,21 +751,8 @@ __device__ __forceinline__ void commit_range(const Problem& P, uint32_t tid, uin
       }
     }
     if (P.marking) {
-      uint32_t np = 0;
-      if (chg) np = (uint32_t)((P.var_ptr[v + 1] - P.var_ptr[v] + kMarkPiece - 1) / kMarkPiece);
-      uint32_t x = np;  // inclusive prefix over the wave
-#pragma unroll
-      for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off, kWave);
-        if (lane >= (uint32_t)off) x += y;
-      }
-      const uint32_t total = __shfl(x, kWave - 1, kWave);
-      if (total) {
-        uint32_t base = 0;
-        if (lane == kWave - 1) base = atomicAdd(&P.ctrl->n_chg, total);
-        base = __shfl(base, kWave - 1, kWave) + (x - np);
-        for (uint32_t q = 0; q < np; ++q) P.chg_list[base + q] = ((uint64_t)v << 32) | q;
-      }
+      const uint64_t bits = __ballot(chg);
+      if (lane == 0) P.chg_bits[v0 / kWave] = bits;
     }
   }
 }
@@ -800,11 +786,7 @@ __device__ __forceinline__ void end_of_round(const Problem& P, int r, int max_ro
                                              uint32_t changed, uint32_t infeasible) {
   Ctrl* C = P.ctrl;
   C->round = r + 1;
-  if (P.marking)
-    C->mark_all = __hip_atomic_load(&C->n_chg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >
-                          (uint32_t)(P.n / kMarkAllDiv)
-                      ? 1u
-                      : 0u;
+  if (P.marking) C->mark_all = changed > (uint32_t)(P.n / kMarkAllDiv) ? 1u : 0u;
   if (infeasible) {
     C->status = kInfeasible;
     C->rounds = r;

@@ -713,21 +713,32 @@ int prop_set_marking(prop_problem* p, int32_t enable) {
   if (enable && !p->mark_ready) {
     HIP_TRY(hipSetDevice(p->device));
     Problem& P = p->P;
-    int64_t* vp;
-    int32_t *vr, *marks;
-    uint64_t* list;
+    int64_t *vp, *poff;
+    int32_t *vr, *marks, *pvar;
+    uint64_t* bits;
     int rc;
+    // pieces of <= kMarkPiece rows of one variable, one mark-kernel thread each
+    std::vector<int32_t> h_pvar;
+    std::vector<int64_t> h_poff;
+    for (int32_t v = 0; v < p->n; ++v)
+      for (int64_t q = p->h_var_ptr[v]; q < p->h_var_ptr[(size_t)v + 1]; q += kMarkPiece) {
+        h_pvar.push_back(v);
+        h_poff.push_back(q);
+      }
     if ((rc = dev_upload(p, &vp, p->h_var_ptr))) return rc;
     if ((rc = dev_upload(p, &vr, p->h_var_rows))) return rc;
+    if ((rc = dev_upload(p, &pvar, h_pvar))) return rc;
+    if ((rc = dev_upload(p, &poff, h_poff))) return rc;
     if ((rc = dev_alloc(p, &marks, (size_t)(P.n_rows > 0 ? P.n_rows : 1)))) return rc;
     HIP_TRY(hipMemset(marks, 0, sizeof(int32_t) * (size_t)(P.n_rows > 0 ? P.n_rows : 1)));
-    // a round lists each changed variable once, one entry per kMarkPiece rows
-    const size_t cap = (size_t)p->n + (size_t)(p->h_var_rows.size() / kMarkPiece) + kWave;
-    if ((rc = dev_alloc(p, &list, cap))) return rc;
+    if ((rc = dev_alloc(p, &bits, (size_t)(p->n + kWave - 1) / kWave + 1))) return rc;
     P.var_ptr = vp;
     P.var_rows = vr;
     P.row_mark = marks;
-    P.chg_list = list;
+    P.chg_bits = bits;
+    P.piece_var = pvar;
+    P.piece_off = poff;
+    P.n_pieces = (int64_t)h_pvar.size();
     std::vector<int64_t>().swap(p->h_var_ptr);
     std::vector<int32_t>().swap(p->h_var_rows);
     p->mark_ready = true;

@@ -29,7 +29,6 @@ __global__ void k_init(Problem P) {
     C->bar_count = 0;
     C->bar_gen = 0;
     C->abort = 0;
-    C->n_chg = 0;
     C->mark_all = 1;
   }
 }
@@ -125,7 +124,6 @@ __device__ __forceinline__ bool marked_round(const Problem& P) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_round(Problem P, int r) {
-  if (P.marking && blockIdx.x == 0 && threadIdx.x == 0) P.ctrl->n_chg = 0;  // list of round r
   if (u32_load(&P.ctrl->done)) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = blockIdx.x * kWavesPerBlock + wave;
@@ -143,20 +141,18 @@ __global__ __launch_bounds__(kBlock) void k_round_long(Problem P, int r) {
 }
 
 // Marked rounds, after the commit of round r: stamps the rows of every
-// changed variable with r + 1 (one wave per list entry), unless the next
-// round runs over every row anyway.
+// changed variable with r + 1 (a thread per piece of <= kMarkPiece rows of
+// one variable), unless the next round runs over every row anyway.
 __global__ __launch_bounds__(kBlock) void k_mark(Problem P, int r) {
   const Ctrl* C = P.ctrl;
   if (u32_load(&C->done) || u32_load(&C->mark_all)) return;
-  const uint32_t cnt = u32_load(&C->n_chg);
-  const int lane = threadIdx.x & (kWave - 1);
-  const uint32_t nw = gridDim.x * kWavesPerBlock;
-  for (uint32_t e = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); e < cnt; e += nw) {
-    const uint64_t item = P.chg_list[e];
-    const uint32_t v = (uint32_t)(item >> 32), piece = (uint32_t)item;
-    const int64_t start = P.var_ptr[v] + (int64_t)piece * kMarkPiece;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P.n_pieces; q += stride) {
+    const int32_t v = P.piece_var[q];
+    if (!((P.chg_bits[v / kWave] >> (v % kWave)) & 1ull)) continue;
+    const int64_t start = P.piece_off[q];
     const int64_t stop = P.var_ptr[v + 1] < start + kMarkPiece ? P.var_ptr[v + 1] : start + kMarkPiece;
-    for (int64_t i = start + lane; i < stop; i += kWave) P.row_mark[P.var_rows[i]] = r + 1;
+    for (int64_t i = start; i < stop; ++i) P.row_mark[P.var_rows[i]] = r + 1;
   }
 }
 

@@ -91,9 +91,8 @@ struct Ctrl {
   uint32_t bar_count;      // grid barrier arrival counter
   uint32_t bar_gen;        // grid barrier generation
   uint32_t abort;          // barrier wait gave up (device timeout)
-  uint32_t n_chg;          // marked rounds: entries in the changed-variable list
   uint32_t mark_all;       // marked rounds: the next round processes every row
-  uint32_t pad[3];
+  uint32_t pad[4];
 };
 
 // Everything a kernel needs, passed by value.
@@ -127,12 +126,16 @@ struct Problem {
   int32_t* row_mark;        // [n_rows]
   const int64_t* var_ptr;   // [n + 1] rows of each variable, internal orders
   const int32_t* var_rows;
-  uint64_t* chg_list;       // (variable << 32 | piece) changed in the current round
+  uint64_t* chg_bits;       // [ceil(n / 64)] variables changed in the current round
+  const int32_t* piece_var; // [n_pieces] variable of each piece of <= kMarkPiece rows
+  const int64_t* piece_off; // [n_pieces] first entry of the piece in var_rows
+  int64_t n_pieces;
 };
 
-// Rows of one variable marked by one wave; a round whose changed variables
-// exceed n / kMarkAllDiv runs the next round over every row instead.
-constexpr int kMarkPiece = 2048;
+// Rows of a variable that one thread of the mark kernel stamps; a round
+// that changed more than n / kMarkAllDiv variables runs the next round over
+// every row instead.
+constexpr int kMarkPiece = 64;
 constexpr int kMarkAllDiv = 32;
 
 // Batch of branch-and-bound nodes sharing one problem.  Bounds of node
