@@ -76,14 +76,63 @@ def cpu_baseline(inst, skip: bool):
     }
 
 
+def cpu_seq_compare(skip: bool, max_rounds: int):
+    """The paper's comparison (speed-up over sequential propagation with
+    constraint marking, Algorithm 1, one core), on the 200,000 x 100,000
+    lognormal instance: the oracle's Algorithm 1 timed on one host core
+    against full GPU runs of the synchronous rounds.  The oracle sums
+    activities exactly (fixed point), so it is slower than a production
+    sequential propagator: context, not the paper's ratio."""
+    if skip:
+        return None
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from paper_2009_07785_amd import Problem
+
+    inst = synth.cached("config1_1", synth.config1, 1)
+    log("cpu_seq: the oracle's sequential Algorithm 1 on the 200,000 x 100,000 instance")
+    t0 = time.perf_counter()
+    seq = oracle.run_seq(inst, inst.lb, inst.ub)
+    t_seq = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    prob = Problem.from_instance(inst)
+    root_lb = torch.tensor(inst.lb, dtype=torch.float64, device=dev)
+    root_ub = torch.tensor(inst.ub, dtype=torch.float64, device=dev)
+    d_lb, d_ub = torch.empty_like(root_lb), torch.empty_like(root_ub)
+    ts = []
+    for i in range(6):
+        d_lb.copy_(root_lb)
+        d_ub.copy_(root_ub)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = prob.run_device(d_lb, d_ub, max_rounds)
+        torch.cuda.synchronize()
+        if i:
+            ts.append(time.perf_counter() - t0)
+    prob.close()
+    t_gpu = float(np.median(ts))
+    out = {"workload": f"config1: {inst.m}x{inst.n}, {inst.nnz} nnz, from the root bounds",
+           "cpu_seq_s": t_seq, "cpu_seq_sweeps": seq.rounds, "cores": 1,
+           "kind": "oracle Algorithm 1 (exact sums)",
+           "gpu_run_ms": t_gpu * 1e3, "gpu_rounds": r.rounds,
+           "speedup_vs_cpu_seq": t_seq / t_gpu}
+    log(f"cpu_seq: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--max-rounds", type=int, default=100)
-    ap.add_argument("--loop", default="stream", choices=["persistent", "stream", "host"])
+    ap.add_argument("--loop", default="stream", choices=["persistent", "stream", "host", "graph"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-seq", action="store_true",
+                    help="skip the sequential-propagation comparison on the medium instance")
     ap.add_argument("--no-loop-compare", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched branch-and-bound node comparison")
@@ -210,7 +259,7 @@ def main():
 
     loops = {}
     if not args.no_loop_compare:
-        for mode in ("persistent", "stream", "host"):
+        for mode in ("persistent", "stream", "host", "graph"):
             prob.set_loop(mode)
             ts = []
             for _ in range(3):
@@ -252,6 +301,7 @@ def main():
                         int(args.serving_budget_gib * (1 << 30)))
 
     base = cpu_baseline(inst, args.no_cpu_baseline)
+    seq = cpu_seq_compare(args.no_cpu_seq or args.no_cpu_baseline, args.max_rounds)
 
     out = {
         "metric": METRIC,
@@ -295,6 +345,7 @@ def main():
         "batched": batch,
         "serving": serve,
         "cpu_baseline": base,
+        "cpu_seq": seq,
     }
     print(json.dumps(out), flush=True)
     prob.close()

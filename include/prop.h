@@ -75,6 +75,8 @@ extern "C" {
 #define PROP_LOOP_STREAM 1     /* default: per-round kernels queued in batches; the host
                                   reads the device's done flag one batch behind */
 #define PROP_LOOP_HOST 2       /* per-round kernels, host reads the flag every round */
+#define PROP_LOOP_GRAPH 3      /* as STREAM, each batch of rounds one replay of a HIP graph
+                                  captured on the first run (kernels exit early once done) */
 
 typedef struct prop_problem prop_problem; /* opaque */
 

@@ -61,6 +61,10 @@ struct prop_problem {
   // first prop_set_marking(p, 1)
   bool marking = false;
   bool mark_ready = false;
+  // graph driver: one captured batch of rounds per done-flag slot
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;
+  int32_t graph_marking = -1;
   std::vector<int64_t> h_var_ptr;
   std::vector<int32_t> h_var_rows;
 };

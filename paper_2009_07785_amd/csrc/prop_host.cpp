@@ -79,6 +79,13 @@ int dev_upload(prop_problem* p, T** out, const std::vector<T>& host) {
   return PROP_OK;
 }
 
+// Destroys the graph driver's captured rounds.
+void drop_graphs(prop_problem* p) {
+  for (auto& g : p->gexec)
+    if (g) hipGraphExecDestroy(g);
+  p->gexec[0] = p->gexec[1] = nullptr;
+}
+
 void release(prop_problem* p) {
   if (!p) return;
   for (void* a : p->allocs) hipFree(a);
@@ -94,6 +101,8 @@ void release(prop_problem* p) {
   for (void* a : p->batch_allocs) hipFree(a);
   if (p->h_bstatus) hipHostFree(p->h_bstatus);
   if (p->h_brounds) hipHostFree(p->h_brounds);
+  drop_graphs(p);
+  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
   delete p;
 }
 
@@ -402,7 +411,36 @@ int queue_round(prop_problem* p, int r, int32_t max_rounds, hipStream_t s) {
     e1 = p->kev[2 * (r - 1) + 1];
     p->kev_used = r;
   }
-  HIP_TRY(launch_round(p->P, r, max_rounds, s, e0, e1));
+  HIP_TRY(launch_round(p->P, s, e0, e1));
+  return PROP_OK;
+}
+
+// Graph driver: batch_rounds rounds plus the copy of the done flag into
+// h_done[slot], captured once per slot and replayed.  The launches carry
+// the problem by value, so a change of the marking switch recaptures.
+int ensure_graphs(prop_problem* p) {
+  if (p->gexec[0] && p->graph_marking == p->P.marking) return PROP_OK;
+  drop_graphs(p);
+  if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  for (int slot = 0; slot < 2; ++slot) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < p->batch_rounds && e == hipSuccess; ++k)
+      e = launch_round(p->P, p->cap_stream, nullptr, nullptr);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&p->h_done[slot], &p->P.ctrl->done, sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, p->cap_stream);
+    const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->gexec[slot], g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      drop_graphs(p);
+      return fail(PROP_EDEVICE, "round graph capture failed: %s", hipGetErrorString(e));
+    }
+  }
+  p->graph_marking = p->P.marking;
   return PROP_OK;
 }
 
@@ -433,6 +471,27 @@ int run_loop(prop_problem* p, int32_t max_rounds, hipStream_t s) {
         }
         HIP_TRY(hipMemcpyAsync(&p->h_done[slot], &P.ctrl->done, sizeof(uint32_t),
                                hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(p->ev_batch[slot], s));
+        pending[slot] = true;
+        slot ^= 1;
+        if (pending[slot]) {
+          HIP_TRY(hipEventSynchronize(p->ev_batch[slot]));
+          pending[slot] = false;
+          if (p->h_done[slot] == 1) break;
+        }
+      }
+      return PROP_OK;
+    }
+    case PROP_LOOP_GRAPH: {
+      // as the stream driver, with each batch one replay of a captured graph
+      // (rounds past the limit find the done flag set and exit at once)
+      HIP_TRY(launch_start(P, max_rounds, s));
+      const int rc = ensure_graphs(p);
+      if (rc) return rc;
+      int slot = 0;
+      bool pending[2] = {false, false};
+      for (int r = 1; r <= max_rounds; r += p->batch_rounds) {
+        HIP_TRY(hipGraphLaunch(p->gexec[slot], s));
         HIP_TRY(hipEventRecord(p->ev_batch[slot], s));
         pending[slot] = true;
         slot ^= 1;
@@ -702,7 +761,8 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
 
 int prop_set_loop(prop_problem* p, int32_t mode) {
   if (!p) return fail(PROP_EINVAL, "NULL problem");
-  if (mode != PROP_LOOP_PERSISTENT && mode != PROP_LOOP_STREAM && mode != PROP_LOOP_HOST)
+  if (mode != PROP_LOOP_PERSISTENT && mode != PROP_LOOP_STREAM && mode != PROP_LOOP_HOST &&
+      mode != PROP_LOOP_GRAPH)
     return fail(PROP_EINVAL, "unknown loop mode %d", mode);
   p->loop_mode = mode;
   return PROP_OK;

@@ -115,7 +115,17 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Problem P, int max_rounds
 
 // ---- stream / host drivers: one launch per phase, early exit when done ----
 __global__ void k_start(Problem P, int max_rounds) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) start_status(P, max_rounds);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    P.ctrl->max_rounds = max_rounds;
+    start_status(P, max_rounds);
+  }
+}
+
+// The per-round kernels take the round number and the round limit from the
+// control block (the commit of round r sets the next round number), so one
+// captured sequence of rounds can be replayed for every batch of a run.
+__device__ __forceinline__ int round_of(const Problem& P) {
+  return __hip_atomic_load(&P.ctrl->round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Marked rounds: whether round r skips unstamped rows (read once per wave).
@@ -123,8 +133,9 @@ __device__ __forceinline__ bool marked_round(const Problem& P) {
   return P.marking && !u32_load(&P.ctrl->mark_all);
 }
 
-__global__ __launch_bounds__(kBlock) void k_round(Problem P, int r) {
+__global__ __launch_bounds__(kBlock) void k_round(Problem P) {
   if (u32_load(&P.ctrl->done)) return;
+  const int r = round_of(P);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = blockIdx.x * kWavesPerBlock + wave;
   const bool marked = marked_round(P);
@@ -133,33 +144,40 @@ __global__ __launch_bounds__(kBlock) void k_round(Problem P, int r) {
     chunk_dispatch(P, item - P.n_segs, P.bnd[0], P.bnd[1], 1, 1, marked, r);
 }
 
-__global__ __launch_bounds__(kBlock) void k_round_long(Problem P, int r) {
+__global__ __launch_bounds__(kBlock) void k_round_long(Problem P) {
   if (u32_load(&P.ctrl->done)) return;
+  const int r = round_of(P);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int s = blockIdx.x * kWavesPerBlock + wave;
   if (s < P.n_segs) seg_phase2(P, s, P.bnd[0], P.bnd[1], 1, 0, P.partials, 1, 0, marked_round(P), r);
 }
 
 // Marked rounds, after the commit of round r: stamps the rows of every
-// changed variable with r + 1 (a thread per piece of <= kMarkPiece rows of
-// one variable), unless the next round runs over every row anyway.
-__global__ __launch_bounds__(kBlock) void k_mark(Problem P, int r) {
+// changed variable with r + 1, the round the commit has set as the next one
+// (a thread per piece of <= kMarkPiece rows of one variable), unless that
+// round runs over every row anyway.
+__global__ __launch_bounds__(kBlock) void k_mark(Problem P) {
   const Ctrl* C = P.ctrl;
   if (u32_load(&C->done) || u32_load(&C->mark_all)) return;
+  const int next = round_of(P);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P.n_pieces; q += stride) {
     const int32_t v = P.piece_var[q];
     if (!((P.chg_bits[v / kWave] >> (v % kWave)) & 1ull)) continue;
     const int64_t start = P.piece_off[q];
     const int64_t stop = P.var_ptr[v + 1] < start + kMarkPiece ? P.var_ptr[v + 1] : start + kMarkPiece;
-    for (int64_t i = start; i < stop; ++i) P.row_mark[P.var_rows[i]] = r + 1;
+    for (int64_t i = start; i < stop; ++i) P.row_mark[P.var_rows[i]] = next;
   }
 }
 
 // Commit of round r; the last block to finish decides the status.
-__global__ __launch_bounds__(kBlock) void k_commit(Problem P, int r, int max_rounds) {
+__global__ __launch_bounds__(kBlock) void k_commit(Problem P) {
   Ctrl* C = P.ctrl;
   if (u32_load(&C->done)) return;
+  // read before the last block's end_of_round advances them: every other
+  // block has finished by then
+  const int r = round_of(P);
+  const int max_rounds = C->max_rounds;
   uint32_t changed = 0, infeasible = 0;
   commit_range(P, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, changed,
                infeasible);
@@ -216,21 +234,18 @@ hipError_t launch_start(const Problem& P, int max_rounds, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_round(const Problem& P, int r, int max_rounds, hipStream_t s, hipEvent_t e0,
-                        hipEvent_t e1) {
+hipError_t launch_round(const Problem& P, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const int items = P.n_chunks + P.n_segs;
   if (e0) hipEventRecord(e0, s);
   hipLaunchKernelGGL(k_round, dim3(blocks_for(items, kWavesPerBlock, 1 << 30)), dim3(kBlock), 0,
-                     s, P, r);
+                     s, P);
   if (e1) hipEventRecord(e1, s);
   if (P.n_segs)
     hipLaunchKernelGGL(k_round_long, dim3(blocks_for(P.n_segs, kWavesPerBlock, 1 << 30)),
-                       dim3(kBlock), 0, s, P, r);
+                       dim3(kBlock), 0, s, P);
   // at most 65535 blocks: the packed commit counter keeps 16 bits per field
-  hipLaunchKernelGGL(k_commit, dim3(blocks_for(P.n, kBlock, 1024)), dim3(kBlock), 0, s, P, r,
-                     max_rounds);
-  if (P.marking)
-    hipLaunchKernelGGL(k_mark, dim3(1024), dim3(kBlock), 0, s, P, r);
+  hipLaunchKernelGGL(k_commit, dim3(blocks_for(P.n, kBlock, 1024)), dim3(kBlock), 0, s, P);
+  if (P.marking) hipLaunchKernelGGL(k_mark, dim3(1024), dim3(kBlock), 0, s, P);
   return hipGetLastError();
 }
 

@@ -14,9 +14,11 @@ hipError_t persistent_occupancy(int* blocks_per_cu);
 hipError_t launch_persistent(const Problem& P, int max_rounds, int grid, hipStream_t s);
 hipError_t launch_start(const Problem& P, int max_rounds, hipStream_t s);
 // Queues one round: the matrix kernel (bracketed by e0 / e1 when they are
-// not null), the long-row kernel, and the commit.
-hipError_t launch_round(const Problem& P, int r, int max_rounds, hipStream_t s, hipEvent_t e0,
-                        hipEvent_t e1);
+// not null), the long-row kernel, the commit and, in marked rounds, the
+// mark kernel.  The kernels take the round number and limit from the
+// control block (set by the start kernel and each commit), so the same
+// launches can be captured once and replayed.
+hipError_t launch_round(const Problem& P, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 
 // Batched nodes: pack / unpack nodes [k0, k0 + cnt) of the caller's
 // node-major arrays, round-0 decision for such a range (whole = the range is

@@ -92,7 +92,8 @@ struct Ctrl {
   uint32_t bar_gen;        // grid barrier generation
   uint32_t abort;          // barrier wait gave up (device timeout)
   uint32_t mark_all;       // marked rounds: the next round processes every row
-  uint32_t pad[4];
+  int32_t max_rounds;      // round limit of the current run
+  uint32_t pad[3];
 };
 
 // Everything a kernel needs, passed by value.

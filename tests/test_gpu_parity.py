@@ -3,8 +3,9 @@
 Bar: status and rounds identical; bounds bitwise identical (activities are
 exactly rounded on both sides and every other step is the same IEEE
 operation, so no tolerance is needed; the comparison helper still reports
-the largest deviation for diagnosis).  Every run goes through all three
-round-loop drivers.
+the largest deviation for diagnosis).  Runs go through every round-loop
+driver; the graph driver replays its captured rounds many times per run,
+with other drivers' runs in between.
 """
 import math
 import os
@@ -19,7 +20,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-LOOPS = ("persistent", "stream", "host")
+LOOPS = ("persistent", "stream", "host", "graph")
 
 
 @pytest.fixture(scope="module")
@@ -194,7 +195,7 @@ def test_marked_rounds(lib):
         ref = oracle.run(inst, inst.lb, inst.ub, 100)
         with lib.Problem.from_instance(inst) as p:
             p.set_marking(True)
-            for loop in ("stream", "host", "persistent"):
+            for loop in ("stream", "host", "graph", "persistent"):
                 p.set_loop(loop)
                 say(f"  marked {inst.name} loop={loop}")
                 assert_same(f"marked {inst.name}/{loop}", p.run(inst.lb, inst.ub, 100), ref)
