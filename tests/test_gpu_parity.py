@@ -300,3 +300,60 @@ def test_config2_round2_lockstep(lib, big):
     Ln, Un, ch, inf, _ = oracle.round_(inst, lb1, ub1)
     assert np.array_equal(lb2, Ln) and np.array_equal(ub2, Un)
     assert (res.status == oracle.MAX_ROUNDS) == ch
+
+
+def test_round_limits_all_drivers(lib):
+    """Round limits below, at and across the drivers' batch of 4 rounds, with
+    and without marking: status and rounds exact, bounds bitwise."""
+    inst = synth.config0()
+    with lib.Problem.from_instance(inst) as p:
+        for mr in (0, 1, 2, 3, 4, 5, 7, 9):
+            ref = oracle.run(inst, inst.lb, inst.ub, mr)
+            for marking in (False, True):
+                p.set_marking(marking)
+                for loop in LOOPS:
+                    p.set_loop(loop)
+                    assert_same(f"limit {mr} marking={marking} {loop}", p.run(inst.lb, inst.ub, mr),
+                                ref)
+
+
+def test_empty_and_degenerate_shapes(lib, torch_cuda):
+    """No rows, no variables, a single 3,000-entry row (three long-row
+    segments) and a variable in every row, through single runs, marked runs,
+    batches and the device path."""
+    torch = torch_cuda
+    rng = np.random.default_rng(5)
+    cases = [
+        synth.from_rows([], [], [], [0.0, -1.0, 0.0], [1.0, 2.0, 4.0], [1, 0, 1], n=3),
+        synth.from_rows([[(0, 1.0), (1, -1.0)]] * 3, [-1.0, 0.0, -np.inf], [1.0, 2.0, 0.5],
+                        [-3.0, 0.0], [3.0, 1.0], [1, 0], n=2),
+    ]
+    n = 3000
+    row = [(j, float(rng.integers(1, 4))) for j in range(n)]
+    cases.append(synth.from_rows([row], [-np.inf], [10.0], np.zeros(n), np.full(n, 5.0),
+                                 np.ones(n), n=n))
+    cases.append(synth.from_rows([], [], [], [], [], [], n=0))
+    # variable 0 in every row of a small system
+    rows = [[(0, 1.0), (1 + i, 1.0)] for i in range(40)]
+    cases.append(synth.from_rows(rows, [-np.inf] * 40, [3.0] * 40, np.zeros(41),
+                                 np.full(41, 10.0), np.ones(41), n=41))
+    for inst in cases:
+        ref = oracle.run(inst, inst.lb, inst.ub, 100)
+        with lib.Problem.from_instance(inst) as p:
+            for marking in (False, True):
+                p.set_marking(marking)
+                for loop in ("stream", "graph", "host"):
+                    p.set_loop(loop)
+                    assert_same(f"{inst.name} {loop} marking={marking}",
+                                p.run(inst.lb, inst.ub, 100), ref)
+            if inst.n:
+                lbs = np.stack([inst.lb] * 3)
+                ubs = np.stack([inst.ub] * 3)
+                d_lb = torch.tensor(lbs, dtype=torch.float64, device="cuda")
+                d_ub = torch.tensor(ubs, dtype=torch.float64, device="cuda")
+                res = p.run_batch_device(d_lb, d_ub, 100)
+                for k in range(3):
+                    assert (res[k].status, res[k].rounds) == (ref.status, ref.rounds)
+                    if ref.status != oracle.INFEASIBLE:
+                        assert np.array_equal(d_lb[k].cpu().numpy(), ref.lb)
+                        assert np.array_equal(d_ub[k].cpu().numpy(), ref.ub)
