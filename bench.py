@@ -98,6 +98,9 @@ def cpu_seq_compare(skip: bool, max_rounds: int):
     seq = oracle.run_seq(inst, inst.lb, inst.ub)
     t_seq = time.perf_counter() - t0
     dev = torch.device("cuda:0")
+    from paper_2009_07785_amd import autotune
+
+    steps = autotune(inst, inst.lb, inst.ub, max_rounds)  # layout for this shape
     prob = Problem.from_instance(inst)
     root_lb = torch.tensor(inst.lb, dtype=torch.float64, device=dev)
     root_ub = torch.tensor(inst.ub, dtype=torch.float64, device=dev)
@@ -117,7 +120,7 @@ def cpu_seq_compare(skip: bool, max_rounds: int):
     out = {"workload": f"config1: {inst.m}x{inst.n}, {inst.nnz} nnz, from the root bounds",
            "cpu_seq_s": t_seq, "cpu_seq_sweeps": seq.rounds, "cores": 1,
            "kind": "oracle Algorithm 1 (exact sums)",
-           "gpu_run_ms": t_gpu * 1e3, "gpu_rounds": r.rounds,
+           "gpu_run_ms": t_gpu * 1e3, "gpu_rounds": r.rounds, "layout_steps": steps,
            "speedup_vs_cpu_seq": t_seq / t_gpu}
     log(f"cpu_seq: {out}")
     return out
@@ -320,7 +323,7 @@ def main():
             "workload": "config2: single instance, 5,000,000 x 2,000,000, power-law rows "
                         "(pdf exponent 2.2, cap 200,000) and column degrees",
             "m": inst.m, "n": inst.n, "nnz": nnz, "max_rounds": args.max_rounds,
-            "loop": args.loop, "parallelism": "single GPU",
+            "loop": args.loop, "parallelism": "single GPU", "layout_steps": info["steps"],
         },
         "status": ["CONVERGED", "INFEASIBLE", "MAX_ROUNDS"][status],
         "rounds": nrounds,

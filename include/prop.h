@@ -90,11 +90,16 @@ typedef struct {
   const double* vals;
 } prop_csr;
 
-/* Tolerances; a NULL pointer means 1e-6 for each. */
+/* Tolerances and layout; a NULL pointer means 1e-6 for each tolerance and
+ * steps = 0. */
 typedef struct {
   double eps_int;      /* integer rounding slack, >= 0 and < 0.5 */
   double cont_rel_tol; /* relative gain a continuous bound needs, >= 0 */
   double feas_tol;     /* relative crossing a continuous domain may show, >= 0 */
+  int32_t steps;       /* layout: entries per lane of a short row, 4, 8 or 16 (rows longer
+                          than 64 * steps go to 1024-entry segments); 0 = the value
+                          prop_autotune recorded for a matrix of this shape, else 16 */
+  int32_t reserved;    /* must be 0 */
 } prop_params;
 
 typedef struct {
@@ -113,6 +118,8 @@ typedef struct {
   int32_t grid_blocks;     /* blocks of the persistent launch */
   int64_t device_bytes;    /* device memory held by the problem */
   int64_t alg_bytes_round; /* algorithmic bytes per round: 12 nnz + 20 m + 33 n + 4 */
+  int32_t steps;           /* entries per lane of a short row in the layout (4, 8, 16) */
+  int32_t reserved;
 } prop_info;
 
 /* Builds a problem on the current HIP device.  The inputs are copied; the
@@ -123,6 +130,19 @@ typedef struct {
  * Returns PROP_OK and stores the handle in *out, or an error code. */
 int prop_create(const prop_csr* A, const double* lhs, const double* rhs, const uint8_t* vartype,
                 const prop_params* params, prop_problem** out);
+
+/* Autotuner: builds the problem with each layout (steps = 16, 8, 4), times
+ * full propagations from lb[n], ub[n] (host, not modified; max_rounds as
+ * for prop_run) with the stream driver, and stores the fastest steps in
+ * *steps_out and in the tuning cache under the matrix's shape signature
+ * (m, n, nnz and the histogram of row lengths by powers of two), where
+ * prop_create with steps = 0 looks it up.  The cache lives in the process
+ * and, when the environment variable PROP_TUNE_CACHE names a file, in that
+ * file (one "signature steps" line per entry, appended).  Needs the device
+ * memory of two layouts at a time.  Returns like prop_create / prop_run. */
+int prop_autotune(const prop_csr* A, const double* lhs, const double* rhs, const uint8_t* vartype,
+                  const prop_params* params, const double* lb, const double* ub,
+                  int32_t max_rounds, int32_t* steps_out);
 
 /* Propagates host arrays lb[n], ub[n] in place (caller-owned, overwritten
  * with the result; unspecified when the status is PROP_INFEASIBLE).

@@ -10,4 +10,6 @@ from .binding import (  # noqa: F401
     Problem,
     PropError,
     RunResult,
+    Server,
+    autotune,
 )

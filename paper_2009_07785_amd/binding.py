@@ -24,7 +24,7 @@ LOOP_NAMES = {"persistent": LOOP_PERSISTENT, "stream": LOOP_STREAM, "host": LOOP
               "graph": LOOP_GRAPH}
 
 # every function the header declares
-EXPORTED = ("prop_create", "prop_run", "prop_run_device", "prop_run_batch_device",
+EXPORTED = ("prop_create", "prop_autotune", "prop_run", "prop_run_device", "prop_run_batch_device",
             "prop_set_loop", "prop_set_marking", "prop_get_info",
             "prop_last_timing", "prop_set_kernel_timing", "prop_last_kernel_timing",
             "prop_destroy", "prop_last_error",
@@ -46,7 +46,8 @@ class _Csr(ctypes.Structure):
 
 class _Params(ctypes.Structure):
     _fields_ = [("eps_int", ctypes.c_double), ("cont_rel_tol", ctypes.c_double),
-                ("feas_tol", ctypes.c_double)]
+                ("feas_tol", ctypes.c_double), ("steps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -58,7 +59,8 @@ class _Info(ctypes.Structure):
                 ("nnz_stored", ctypes.c_int64), ("n_chunks", ctypes.c_int32),
                 ("n_long_rows", ctypes.c_int32), ("n_segments", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
-                ("alg_bytes_round", ctypes.c_int64)]
+                ("alg_bytes_round", ctypes.c_int64), ("steps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _SrvConfig(ctypes.Structure):
@@ -93,6 +95,9 @@ def _load():
     lib.prop_create.argtypes = [ctypes.POINTER(_Csr), P, P, P, ctypes.POINTER(_Params),
                                 ctypes.POINTER(P)]
     lib.prop_create.restype = ctypes.c_int
+    lib.prop_autotune.argtypes = [ctypes.POINTER(_Csr), P, P, P, ctypes.POINTER(_Params), P, P, i32,
+                                  ctypes.POINTER(i32)]
+    lib.prop_autotune.restype = ctypes.c_int
     lib.prop_run.argtypes = [P, P, P, i32, ctypes.POINTER(_Result)]
     lib.prop_run.restype = ctypes.c_int
     lib.prop_run_device.argtypes = [P, P, P, i32, P, ctypes.POINTER(_Result)]
@@ -167,7 +172,9 @@ class Problem:
     """A constraint system resident on the current HIP device."""
 
     def __init__(self, m, n, row_ptr, col_idx, vals, lhs, rhs, vartype, eps_int=1e-6,
-                 cont_rel_tol=1e-6, feas_tol=1e-6):
+                 cont_rel_tol=1e-6, feas_tol=1e-6, steps=0):
+        """steps: layout entries per lane (4, 8, 16); 0 = the autotuned value
+        for this matrix shape, else 16."""
         self._h = None
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
         ci = np.ascontiguousarray(col_idx, dtype=np.int32)
@@ -180,7 +187,7 @@ class Problem:
         if ci.shape != va.shape or ci.shape[0] != int(rp[-1]):
             raise ValueError("col_idx / vals do not match row_ptr")
         csr = _Csr(int(m), int(n), int(rp[-1]), _ptr(rp).value, _ptr(ci).value, _ptr(va).value)
-        prm = _Params(float(eps_int), float(cont_rel_tol), float(feas_tol))
+        prm = _Params(float(eps_int), float(cont_rel_tol), float(feas_tol), int(steps), 0)
         h = ctypes.c_void_p()
         _check(lib.prop_create(ctypes.byref(csr), _ptr(lh), _ptr(rh), _ptr(vt), ctypes.byref(prm),
                                ctypes.byref(h)))
@@ -291,6 +298,25 @@ class Problem:
         return a.value, b.value
 
 
+def autotune(inst, lb, ub, max_rounds: int = 100) -> int:
+    """Times the layouts (steps 16, 8, 4) on full propagations from (lb, ub)
+    and records the fastest for this matrix shape; returns its steps."""
+    rp = np.ascontiguousarray(inst.row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(inst.col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(inst.vals, dtype=np.float64)
+    lh = np.ascontiguousarray(inst.lhs, dtype=np.float64)
+    rh = np.ascontiguousarray(inst.rhs, dtype=np.float64)
+    vt = np.ascontiguousarray(inst.vartype, dtype=np.uint8)
+    lb = np.ascontiguousarray(lb, dtype=np.float64)
+    ub = np.ascontiguousarray(ub, dtype=np.float64)
+    csr = _Csr(int(inst.m), int(inst.n), int(rp[-1]), _ptr(rp).value, _ptr(ci).value,
+               _ptr(va).value)
+    out = ctypes.c_int32()
+    _check(lib.prop_autotune(ctypes.byref(csr), _ptr(lh), _ptr(rh), _ptr(vt), None, _ptr(lb),
+                             _ptr(ub), int(max_rounds), ctypes.byref(out)))
+    return out.value
+
+
 def create_raw(csr_args, lhs, rhs, vartype, params=None):
     """Calls prop_create with explicit arrays; returns (rc, handle).  For tests
     of the validation path, which runs before any device call."""
@@ -303,7 +329,7 @@ def create_raw(csr_args, lhs, rhs, vartype, params=None):
     vt = np.ascontiguousarray(vartype, dtype=np.uint8)
     csr = _Csr(int(m), int(n), int(rp[-1]) if rp.size else 0, _ptr(rp).value, _ptr(ci).value,
                _ptr(va).value)
-    prm = _Params(*(params or (1e-6, 1e-6, 1e-6)))
+    prm = _Params(*((tuple(params) + (0, 0))[:5] if params else (1e-6, 1e-6, 1e-6, 0, 0)))
     h = ctypes.c_void_p()
     rc = lib.prop_create(ctypes.byref(csr), _ptr(lh), _ptr(rh), _ptr(vt), ctypes.byref(prm),
                          ctypes.byref(h))

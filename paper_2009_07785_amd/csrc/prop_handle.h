@@ -34,7 +34,8 @@ struct prop_problem {
   int grid = 0;
   int loop_mode = PROP_LOOP_STREAM;
   bool instance_infeasible = false;
-  prop_params params{1e-6, 1e-6, 1e-6};
+  prop_params params{1e-6, 1e-6, 1e-6, 0, 0};
+  int32_t steps = prop::kMaxSteps;  // layout: entries per lane of a short row
   prop::Problem P{};
   // device allocations
   std::vector<void*> allocs;

@@ -8,6 +8,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -144,6 +147,9 @@ int validate(const prop_csr* A, const double* lhs, const double* rhs, const uint
       return fail(PROP_EINVAL, "eps_int must lie in [0, 0.5)");
     if (!(prm->cont_rel_tol >= 0.0 && std::isfinite(prm->cont_rel_tol)))
       return fail(PROP_EINVAL, "cont_rel_tol must be finite and >= 0");
+    if (prm->steps != 0 && prm->steps != 4 && prm->steps != 8 && prm->steps != 16)
+      return fail(PROP_EINVAL, "params.steps must be 0, 4, 8 or 16");
+    if (prm->reserved != 0) return fail(PROP_EINVAL, "params.reserved must be 0");
     if (!(prm->feas_tol >= 0.0 && std::isfinite(prm->feas_tol)))
       return fail(PROP_EINVAL, "feas_tol must be finite and >= 0");
   }
@@ -196,12 +202,14 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   std::vector<int32_t> longs;
   for (int32_t i = 0; i < m; ++i) {
     if (len[i] == 0) continue;
-    if (len[i] > kSegLen) {
+    // rows of at most 64 lanes x `steps` entries go to chunks, longer ones
+    // to 1024-entry segments
+    if (len[i] > (int64_t)kWave * p->steps) {
       longs.push_back(i);
       continue;
     }
-    const int64_t steps16 = (len[i] + kMaxSteps - 1) / kMaxSteps;
-    cls[ceil_log2(steps16)].push_back(i);
+    const int64_t lanes = (len[i] + p->steps - 1) / p->steps;
+    cls[ceil_log2(lanes)].push_back(i);
   }
   struct Chunk {
     int klog, W, nrows;
@@ -298,7 +306,7 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   const int64_t n_rows_internal = next_row;
   for (const ChunkDesc& d : h_chunks) {
     const int W = (d.meta >> 8) & 0xff, nr = (d.meta >> 16) & 0xff, kl = d.meta & 7;
-    if (W < 1 || W > kMaxSteps || nr < 1 || nr > (kWave >> kl) ||
+    if (W < 1 || W > p->steps || nr < 1 || nr > (kWave >> kl) ||
         (int64_t)d.off64 * kWave + (int64_t)W * kWave > chunk_entries || d.row0 < 0 ||
         d.row0 + nr > n_rows_internal)
       return fail(PROP_EINVAL, "internal layout check failed (chunk)");
@@ -579,6 +587,76 @@ int ensure_batch(prop_problem* p, int32_t nodes) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// tuning cache: layout steps per matrix shape signature
+// ---------------------------------------------------------------------------
+namespace {
+
+std::mutex g_tune_mu;
+std::map<uint64_t, int32_t> g_tune;  // signature -> steps
+bool g_tune_loaded = false;
+
+// FNV-1a over m, n, nnz and the counts of rows per power-of-two length.
+uint64_t shape_signature(const prop_csr* A) {
+  int64_t hist[40] = {0};
+  int64_t nnz = 0;
+  for (int32_t i = 0; i < A->m; ++i) {
+    int64_t len = 0;
+    for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k) len += A->vals[k] != 0.0;
+    nnz += len;
+    int b = 0;
+    while (b < 39 && (1ll << b) <= len) ++b;
+    ++hist[b];
+  }
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t x) {
+    for (int q = 0; q < 8; ++q) {
+      h ^= (uint64_t)((x >> (8 * q)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  mix(A->m);
+  mix(A->n);
+  mix(nnz);
+  for (int64_t c : hist) mix(c);
+  return h;
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("PROP_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  unsigned long long sig;
+  int steps;
+  while (std::fscanf(f, "%llx %d", &sig, &steps) == 2)
+    if (steps == 4 || steps == 8 || steps == 16) g_tune[(uint64_t)sig] = steps;
+  std::fclose(f);
+}
+
+int32_t tune_lookup(uint64_t sig) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune.find(sig);
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+void tune_store(uint64_t sig, int32_t steps) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  g_tune[sig] = steps;
+  const char* path = std::getenv("PROP_TUNE_CACHE");
+  if (!path || !*path) return;
+  if (std::FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%016llx %d\n", (unsigned long long)sig, (int)steps);
+    std::fclose(f);
+  }
+}
+
+}  // namespace
+
 extern "C" {
 
 int prop_create(const prop_csr* A, const double* lhs, const double* rhs, const uint8_t* vartype,
@@ -594,6 +672,8 @@ int prop_create(const prop_csr* A, const double* lhs, const double* rhs, const u
   prop_problem* p = new (std::nothrow) prop_problem();
   if (!p) return fail(PROP_ENOMEM, "host allocation failed");
   if (params) p->params = *params;
+  p->steps = p->params.steps ? p->params.steps : tune_lookup(shape_signature(A));
+  if (!p->steps) p->steps = kMaxSteps;
   p->m = A->m;
   p->n = A->n;
   if (hipGetDevice(&p->device) != hipSuccess) {
@@ -759,6 +839,59 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
   return PROP_OK;
 }
 
+int prop_autotune(const prop_csr* A, const double* lhs, const double* rhs, const uint8_t* vartype,
+                  const prop_params* params, const double* lb, const double* ub,
+                  int32_t max_rounds, int32_t* steps_out) {
+  if (!steps_out) return fail(PROP_EINVAL, "steps_out is NULL");
+  if (max_rounds < 0) return fail(PROP_EINVAL, "max_rounds < 0");
+  int rc = validate(A, lhs, rhs, vartype, params);
+  if (rc) return rc;
+  if (A->n > 0 && (!lb || !ub)) return fail(PROP_EINVAL, "bound arrays are NULL");
+  const size_t bytes = sizeof(double) * (size_t)A->n;
+  double *d_lb = nullptr, *d_ub = nullptr;
+  if (bytes) {
+    HIP_TRY(hipMalloc((void**)&d_lb, bytes));
+    if (hipMalloc((void**)&d_ub, bytes) != hipSuccess) {
+      hipFree(d_lb);
+      return fail(PROP_ENOMEM, "hipMalloc for the tuning bounds failed");
+    }
+  }
+  prop_params prm = params ? *params : prop_params{1e-6, 1e-6, 1e-6, 0, 0};
+  int32_t best = 0;
+  double best_ms = 0.0;
+  for (int32_t steps : {16, 8, 4}) {
+    prm.steps = steps;
+    prop_problem* p = nullptr;
+    rc = prop_create(A, lhs, rhs, vartype, &prm, &p);
+    if (rc) break;
+    double t[4];
+    for (int k = 0; k < 4 && !rc; ++k) {  // one warm-up run, three timed
+      if (bytes) {
+        if (hipMemcpy(d_lb, lb, bytes, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d_ub, ub, bytes, hipMemcpyHostToDevice) != hipSuccess)
+          rc = fail(PROP_EDEVICE, "copy of the tuning bounds failed");
+      }
+      prop_result res;
+      if (!rc) rc = prop_run_device(p, d_lb, d_ub, max_rounds, nullptr, &res);
+      t[k] = p->last_loop_ms;
+    }
+    prop_destroy(p);
+    if (rc) break;
+    std::sort(t + 1, t + 4);
+    if (!best || t[2] < best_ms) {
+      best = steps;
+      best_ms = t[2];
+    }
+  }
+  if (d_lb) hipFree(d_lb);
+  if (d_ub) hipFree(d_ub);
+  if (rc) return rc;
+  tune_store(shape_signature(A), best);
+  *steps_out = best;
+  g_error.clear();
+  return PROP_OK;
+}
+
 int prop_set_loop(prop_problem* p, int32_t mode) {
   if (!p) return fail(PROP_EINVAL, "NULL problem");
   if (mode != PROP_LOOP_PERSISTENT && mode != PROP_LOOP_STREAM && mode != PROP_LOOP_HOST &&
@@ -819,6 +952,8 @@ int prop_get_info(const prop_problem* p, prop_info* out) {
   out->grid_blocks = p->grid;
   out->device_bytes = p->device_bytes;
   out->alg_bytes_round = 12 * p->nnz + 20 * (int64_t)p->m + 33 * (int64_t)p->n + 4;
+  out->steps = p->steps;
+  out->reserved = 0;
   return PROP_OK;
 }
 

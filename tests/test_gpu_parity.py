@@ -185,6 +185,30 @@ def test_edge_cases(lib):
     check_against_oracle(lib, inst)
 
 
+def test_layout_steps(lib):
+    """Every layout (4, 8 or 16 entries per lane; longer rows to segments)
+    gives the oracle's results bitwise."""
+    for inst in (synth.config0(), synth.layout_mix(0), synth.layout_mix(1), synth.config1(1)):
+        ref = oracle.run(inst, inst.lb, inst.ub, 100)
+        for steps in (4, 8, 16):
+            with lib.Problem.from_instance(inst, steps=steps) as p:
+                assert p.info()["steps"] == steps
+                for loop in ("stream", "persistent"):
+                    p.set_loop(loop)
+                    say(f"  {inst.name} steps={steps} loop={loop}")
+                    assert_same(f"{inst.name}/steps{steps}/{loop}", p.run(inst.lb, inst.ub, 100),
+                                ref)
+
+
+def test_autotune_records_layout(lib):
+    inst = synth.config0(3)
+    steps = lib.autotune(inst, inst.lb, inst.ub, 100)
+    assert steps in (4, 8, 16)
+    with lib.Problem.from_instance(inst) as p:  # steps = 0: the tuned value
+        assert p.info()["steps"] == steps
+        assert_same("tuned", p.run(inst.lb, inst.ub, 100), oracle.run(inst, inst.lb, inst.ub, 100))
+
+
 def test_marked_rounds(lib):
     """Marked rounds give bitwise the results of unmarked ones (and of the
     oracle), with the stream and the host driver; the persistent driver

@@ -63,6 +63,8 @@ def test_valid_input_reaches_device_stage():
     (dict(params=(0.5, 1e-6, 1e-6)), "eps_int >= 0.5"),
     (dict(params=(1e-6, -1.0, 1e-6)), "negative cont_rel_tol"),
     (dict(params=(1e-6, 1e-6, np.nan)), "NaN feas_tol"),
+    (dict(params=(1e-6, 1e-6, 1e-6, 5)), "layout steps 5"),
+    (dict(params=(1e-6, 1e-6, 1e-6, 0, 1)), "reserved field set"),
 ])
 def test_invalid_input_rejected(over, why):
     assert _rc(**over) == b.EINVAL, why
@@ -122,3 +124,27 @@ def test_server_argument_checks():
     finally:
         b.lib.prop_srv_destroy(h)
     b.lib.prop_srv_destroy(None)
+
+
+def test_autotune_argument_checks():
+    import ctypes
+
+    d = _base()
+    m, n, rp, ci, va = d["csr"]
+    rp = np.asarray(rp, dtype=np.int64)
+    ci = np.asarray(ci, dtype=np.int32)
+    va = np.asarray(va, dtype=np.float64)
+    csr = b._Csr(m, n, int(rp[-1]), b._ptr(rp).value, b._ptr(ci).value, b._ptr(va).value)
+    lh = np.asarray(d["lhs"], dtype=np.float64)
+    rh = np.asarray(d["rhs"], dtype=np.float64)
+    vt = np.asarray(d["vt"], dtype=np.uint8)
+    lb = np.zeros(n)
+    ub = np.ones(n)
+    out = ctypes.c_int32()
+    args = (ctypes.byref(csr), b._ptr(lh), b._ptr(rh), b._ptr(vt), None, b._ptr(lb), b._ptr(ub))
+    assert b.lib.prop_autotune(*args, 10, None) == b.EINVAL
+    assert b.lib.prop_autotune(*args, -1, ctypes.byref(out)) == b.EINVAL
+    bad = va.copy()
+    bad[0] = np.nan
+    csr_bad = b._Csr(m, n, int(rp[-1]), b._ptr(rp).value, b._ptr(ci).value, b._ptr(bad).value)
+    assert b.lib.prop_autotune(ctypes.byref(csr_bad), *args[1:], 10, ctypes.byref(out)) == b.EINVAL
