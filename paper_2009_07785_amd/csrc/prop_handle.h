@@ -66,6 +66,8 @@ struct prop_problem {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;
   int32_t graph_marking = -1;
+  hipGraphExec_t bgexec[2] = {nullptr, nullptr};  // batches: rounds of `bgraph_nodes` nodes
+  int32_t bgraph_nodes = -1;
   std::vector<int64_t> h_var_ptr;
   std::vector<int32_t> h_var_rows;
 };

@@ -82,11 +82,19 @@ int dev_upload(prop_problem* p, T** out, const std::vector<T>& host) {
   return PROP_OK;
 }
 
-// Destroys the graph driver's captured rounds.
+// Destroys the graph driver's captured rounds (single runs and batches).
+void drop_batch_graphs(prop_problem* p) {
+  for (auto& g : p->bgexec)
+    if (g) hipGraphExecDestroy(g);
+  p->bgexec[0] = p->bgexec[1] = nullptr;
+  p->bgraph_nodes = -1;
+}
+
 void drop_graphs(prop_problem* p) {
   for (auto& g : p->gexec)
     if (g) hipGraphExecDestroy(g);
   p->gexec[0] = p->gexec[1] = nullptr;
+  drop_batch_graphs(p);
 }
 
 void release(prop_problem* p) {
@@ -452,6 +460,34 @@ int ensure_graphs(prop_problem* p) {
   return PROP_OK;
 }
 
+// The same for batches of `bt.nodes` nodes (the batch kernels carry the
+// workspace by value: a new workspace or node count recaptures).
+int ensure_batch_graphs(prop_problem* p, const Batch& bt) {
+  if (p->bgexec[0] && p->bgraph_nodes == bt.nodes) return PROP_OK;
+  drop_batch_graphs(p);
+  if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  for (int slot = 0; slot < 2; ++slot) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < p->batch_rounds && e == hipSuccess; ++k)
+      e = launch_round_batch(p->P, bt, p->cap_stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&p->h_done[slot], &p->P.ctrl->done, sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, p->cap_stream);
+    const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->bgexec[slot], g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      drop_batch_graphs(p);
+      return fail(PROP_EDEVICE, "batch round graph capture failed: %s", hipGetErrorString(e));
+    }
+  }
+  p->bgraph_nodes = bt.nodes;
+  return PROP_OK;
+}
+
 int run_loop(prop_problem* p, int32_t max_rounds, hipStream_t s) {
   const Problem& P = p->P;
   p->kev_used = 0;
@@ -528,6 +564,7 @@ int run_loop(prop_problem* p, int32_t max_rounds, hipStream_t s) {
 // Makes the batch workspace hold at least `nodes` nodes.
 int ensure_batch(prop_problem* p, int32_t nodes) {
   if (nodes <= p->batch_capacity) return PROP_OK;
+  drop_batch_graphs(p);
   for (void* a : p->batch_allocs) hipFree(a);
   p->batch_allocs.clear();
   if (p->h_bstatus) hipHostFree(p->h_bstatus);
@@ -800,13 +837,24 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
   HIP_TRY(hipEventRecord(p->ev[1], s));
   // rounds in batches; the done flag is read one batch behind (see the
   // stream driver of single runs)
+  const bool graph = p->loop_mode == PROP_LOOP_GRAPH;
+  if (graph) {
+    rc = ensure_batch_graphs(p, bt);
+    if (rc) return rc;
+  }
   int slot = 0;
   bool pending[2] = {false, false};
   for (int r = 1; r <= max_rounds;) {
     const int last = std::min(max_rounds, r + p->batch_rounds - 1);
-    for (; r <= last; ++r) HIP_TRY(launch_round_batch(P, bt, s));
-    HIP_TRY(hipMemcpyAsync(&p->h_done[slot], &P.ctrl->done, sizeof(uint32_t),
-                           hipMemcpyDeviceToHost, s));
+    if (graph) {
+      // one replay: batch_rounds rounds (past the limit they exit at once)
+      HIP_TRY(hipGraphLaunch(p->bgexec[slot], s));
+      r = last + 1;
+    } else {
+      for (; r <= last; ++r) HIP_TRY(launch_round_batch(P, bt, s));
+      HIP_TRY(hipMemcpyAsync(&p->h_done[slot], &P.ctrl->done, sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, s));
+    }
     HIP_TRY(hipEventRecord(p->ev_batch[slot], s));
     pending[slot] = true;
     slot ^= 1;

@@ -44,6 +44,13 @@ def run_batch(torch, p, lbs, ubs, max_rounds=100):
 def check_batch_vs_single(torch, lib, inst, lbs, ubs, max_rounds=100, with_oracle=False):
     with lib.Problem.from_instance(inst) as p:
         res, blb, bub = run_batch(torch, p, lbs, ubs, max_rounds)
+        # the graph driver replays captured rounds: the same results, twice
+        p.set_loop("graph")
+        for _ in range(2):
+            gres, glb, gub = run_batch(torch, p, lbs, ubs, max_rounds)
+            assert [(r.status, r.rounds) for r in gres] == [(r.status, r.rounds) for r in res]
+            assert np.array_equal(glb, blb) and np.array_equal(gub, bub)
+        p.set_loop("stream")
         statuses = set()
         for k in range(lbs.shape[0]):
             r1, lb1, ub1 = p.run(lbs[k], ubs[k], max_rounds)
