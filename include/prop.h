@@ -98,7 +98,9 @@ typedef struct {
   double feas_tol;     /* relative crossing a continuous domain may show, >= 0 */
   int32_t steps;       /* layout: entries per lane of a short row, 4, 8 or 16 (rows longer
                           than 64 * steps go to 1024-entry segments); 0 = the value
-                          prop_autotune recorded for a matrix of this shape, else 16 */
+                          prop_autotune recorded for a matrix of this shape, else by
+                          size: 4 up to 100,000 stored entries, 8 up to 5,000,000,
+                          16 above */
   int32_t reserved;    /* must be 0 */
 } prop_params;
 

@@ -710,7 +710,12 @@ int prop_create(const prop_csr* A, const double* lhs, const double* rhs, const u
   if (!p) return fail(PROP_ENOMEM, "host allocation failed");
   if (params) p->params = *params;
   p->steps = p->params.steps ? p->params.steps : tune_lookup(shape_signature(A));
-  if (!p->steps) p->steps = kMaxSteps;
+  if (!p->steps) {
+    // untuned shapes: by size, as the autotuner chose on the instances it was
+    // measured on (smaller matrices gain from shorter chains per lane)
+    const int64_t nnz = A->m > 0 ? A->row_ptr[A->m] : 0;
+    p->steps = nnz <= 100000 ? 4 : nnz <= 5000000 ? 8 : kMaxSteps;
+  }
   p->m = A->m;
   p->n = A->n;
   if (hipGetDevice(&p->device) != hipSuccess) {
