@@ -116,3 +116,44 @@ def test_batch_reuse_and_invalid(torch_cuda, lib):
         assert e.value.code == lib.EINVAL
         c, clb, cub = run_batch(torch, p, lbs, ubs)  # still usable
         assert [(r.status, r.rounds) for r in c] == [(r.status, r.rounds) for r in a]
+
+
+@pytest.fixture(scope="module")
+def config3(lib):
+    inst = synth.cached("config3", synth.config3_matrix)
+    lbs, ubs = synth.config3_nodes(inst, 256)
+    return inst, lbs, ubs
+
+
+def test_batch_config3_256_nodes(torch_cuda, lib, config3):
+    """The 256 nodes of the 1,000,000 x 500,000 instance in one batch: each
+    node bitwise equal to its own single run.  Against the oracle (a full run
+    per node would take hours on the CPU), rounds are checked one at a time:
+    for sampled nodes, the first round from the node's bounds and the last
+    round before the final state are recomputed by the oracle."""
+    torch = torch_cuda
+    inst, lbs, ubs = config3
+    with lib.Problem.from_instance(inst) as p:
+        res, blb, bub = run_batch(torch, p, lbs, ubs, 100)
+        statuses = set()
+        for k in range(256):
+            r1, lb1, ub1 = p.run(lbs[k], ubs[k], 100)
+            assert (res[k].status, res[k].rounds) == (r1.status, r1.rounds), k
+            statuses.add(r1.status)
+            if r1.status != oracle.INFEASIBLE:
+                assert np.array_equal(blb[k], lb1) and np.array_equal(bub[k], ub1), k
+        assert {oracle.CONVERGED, oracle.INFEASIBLE} <= statuses
+        conv = [k for k in range(256) if res[k].status == oracle.CONVERGED]
+        for k in conv[:2]:
+            # round 1 from the node's bounds (integer-rounded as on entry)
+            lb0 = np.where(inst.vartype == 1, np.ceil(lbs[k] - 1e-6), lbs[k]) + 0.0
+            ub0 = np.where(inst.vartype == 1, np.floor(ubs[k] + 1e-6), ubs[k]) + 0.0
+            r_one, lb_one, ub_one = p.run(lbs[k], ubs[k], 1)
+            Ln, Un, ch, inf, _ = oracle.round_(inst, lb0, ub0)
+            assert np.array_equal(lb_one, Ln) and np.array_equal(ub_one, Un), k
+            # the last round: from the state one round before, the oracle
+            # reproduces the final bounds and reports no change
+            rp, lbp, ubp = p.run(lbs[k], ubs[k], res[k].rounds - 1)
+            Ln, Un, ch, inf, _ = oracle.round_(inst, lbp, ubp)
+            assert not ch and not inf, k
+            assert np.array_equal(Ln, blb[k]) and np.array_equal(Un, bub[k]), k
