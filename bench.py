@@ -62,7 +62,7 @@ def cpu_baseline(inst, skip: bool):
         pass
     log("oracle: one round over the full instance (single thread)")
     t0 = time.perf_counter()
-    oracle.round_(inst, lb, ub)
+    _, _, _, _, flags = oracle.round_(inst, lb, ub)
     dt = time.perf_counter() - t0
     return {
         "value": inst.nnz / dt,
@@ -73,6 +73,7 @@ def cpu_baseline(inst, skip: bool):
                   f"({inst.nnz} nnz) from the root bounds: {dt:.2f} s",
         "host_cpu": host_cpu_model(),
         "host_nproc": os.cpu_count(),
+        "near_integer_candidates": int(flags),
     }
 
 

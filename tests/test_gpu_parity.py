@@ -75,6 +75,10 @@ def check_against_oracle(lib, inst, max_rounds=100, params=None, loops=LOOPS, lb
     lb = inst.lb if lb is None else lb
     ub = inst.ub if ub is None else ub
     ref = oracle.run(inst, lb, ub, max_rounds, params)
+    # candidates within eps_int of an integer before rounding: flagged and
+    # counted; the comparison stays bitwise for them too
+    say(f"  {inst.name}: oracle {oracle.STATUS_NAMES[ref.status]}"
+        f" after {ref.rounds} rounds, near-integer candidates flagged: {ref.flags}")
     for loop in loops:
         say(f"  {inst.name} loop={loop} max_rounds={max_rounds}")
         assert_same(f"{inst.name}/{loop}", gpu_run(lib, inst, lb, ub, max_rounds, loop, params), ref)
