@@ -173,6 +173,16 @@ int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rou
 int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* d_ub,
                           int32_t max_rounds, void* stream, prop_result* out);
 
+/* prop_run_batch_device on host arrays lb[nodes * n], ub[nodes * n]
+ * (caller-owned, node k at [k * n, (k + 1) * n), overwritten with the
+ * result; a node's bounds are unspecified when its status is
+ * PROP_INFEASIBLE).  Copies in, runs on the null stream, copies out and
+ * synchronises.  Besides the batch workspace, the first call with more
+ * nodes than any earlier one allocates device staging of 16 * n * nodes
+ * bytes, kept until prop_destroy. */
+int prop_run_batch(prop_problem* p, int32_t nodes, double* lb, double* ub, int32_t max_rounds,
+                   prop_result* out);
+
 /* Selects the round-loop driver (PROP_LOOP_*) for later runs. */
 int prop_set_loop(prop_problem* p, int32_t mode);
 

@@ -24,7 +24,8 @@ LOOP_NAMES = {"persistent": LOOP_PERSISTENT, "stream": LOOP_STREAM, "host": LOOP
               "graph": LOOP_GRAPH}
 
 # every function the header declares
-EXPORTED = ("prop_create", "prop_autotune", "prop_run", "prop_run_device", "prop_run_batch_device",
+EXPORTED = ("prop_create", "prop_autotune", "prop_run", "prop_run_device", "prop_run_batch",
+            "prop_run_batch_device",
             "prop_set_loop", "prop_set_marking", "prop_get_info",
             "prop_last_timing", "prop_set_kernel_timing", "prop_last_kernel_timing",
             "prop_destroy", "prop_last_error",
@@ -102,6 +103,8 @@ def _load():
     lib.prop_run.restype = ctypes.c_int
     lib.prop_run_device.argtypes = [P, P, P, i32, P, ctypes.POINTER(_Result)]
     lib.prop_run_device.restype = ctypes.c_int
+    lib.prop_run_batch.argtypes = [P, i32, P, P, i32, ctypes.POINTER(_Result)]
+    lib.prop_run_batch.restype = ctypes.c_int
     lib.prop_run_batch_device.argtypes = [P, i32, P, P, i32, P, ctypes.POINTER(_Result)]
     lib.prop_run_batch_device.restype = ctypes.c_int
     lib.prop_set_loop.argtypes = [P, i32]
@@ -245,6 +248,20 @@ class Problem:
                                    ctypes.c_void_p(d_ub.data_ptr()), int(max_rounds),
                                    ctypes.c_void_p(int(raw) if raw else 0), ctypes.byref(res)))
         return RunResult(res.status, res.rounds)
+
+    def run_batch(self, lbs, ubs, max_rounds: int = 100):
+        """Batched nodes on host arrays of shape (nodes, n): (list of
+        RunResult, lbs, ubs) out; the inputs are not modified."""
+        lbs = np.array(lbs, dtype=np.float64, copy=True, order="C")
+        ubs = np.array(ubs, dtype=np.float64, copy=True, order="C")
+        if lbs.ndim != 2 or lbs.shape[1] != self.n or ubs.shape != lbs.shape:
+            raise ValueError("bounds must have shape (nodes, n), the same for lb and ub")
+        nodes = int(lbs.shape[0])
+        if nodes < 1:
+            raise ValueError("at least one node")
+        res = (_Result * nodes)()
+        _check(lib.prop_run_batch(self._h, nodes, _ptr(lbs), _ptr(ubs), int(max_rounds), res))
+        return [RunResult(r.status, r.rounds) for r in res], lbs, ubs
 
     def run_batch_device(self, d_lb, d_ub, max_rounds: int = 100, stream=None):
         """Batched nodes: device tensors of shape (nodes, n), float64, updated

@@ -58,6 +58,10 @@ struct prop_problem {
   std::vector<void*> batch_allocs;
   int32_t* h_bstatus = nullptr;  // pinned copies of per-node status / rounds
   int32_t* h_brounds = nullptr;
+  // staging for prop_run_batch (host arrays), grown on demand
+  double* d_bstage_lb = nullptr;
+  double* d_bstage_ub = nullptr;
+  int32_t bstage_capacity = 0;
   // marked rounds: rows of each variable (internal orders), uploaded on the
   // first prop_set_marking(p, 1)
   bool marking = false;

@@ -112,6 +112,8 @@ void release(prop_problem* p) {
   for (void* a : p->batch_allocs) hipFree(a);
   if (p->h_bstatus) hipHostFree(p->h_bstatus);
   if (p->h_brounds) hipHostFree(p->h_brounds);
+  if (p->d_bstage_lb) hipFree(p->d_bstage_lb);
+  if (p->d_bstage_ub) hipFree(p->d_bstage_ub);
   drop_graphs(p);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
   delete p;
@@ -889,6 +891,37 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
     out[k].rounds = p->h_brounds[k];
   }
   g_error.clear();
+  return PROP_OK;
+}
+
+int prop_run_batch(prop_problem* p, int32_t nodes, double* lb, double* ub, int32_t max_rounds,
+                   prop_result* out) {
+  if (!p || !out) return fail(PROP_EINVAL, "NULL argument");
+  if (nodes < 1) return fail(PROP_EINVAL, "nodes < 1");
+  if (p->n > 0 && (!lb || !ub)) return fail(PROP_EINVAL, "bound arrays are NULL");
+  HIP_TRY(hipSetDevice(p->device));
+  const size_t bytes = sizeof(double) * (size_t)p->n * (size_t)nodes;
+  if (nodes > p->bstage_capacity && bytes) {
+    if (p->d_bstage_lb) hipFree(p->d_bstage_lb);
+    if (p->d_bstage_ub) hipFree(p->d_bstage_ub);
+    p->d_bstage_lb = p->d_bstage_ub = nullptr;
+    p->bstage_capacity = 0;
+    if (hipMalloc((void**)&p->d_bstage_lb, bytes) != hipSuccess ||
+        hipMalloc((void**)&p->d_bstage_ub, bytes) != hipSuccess)
+      return fail(PROP_ENOMEM, "staging for %d nodes (2 x %zu bytes) failed", nodes, bytes);
+    p->bstage_capacity = nodes;
+  }
+  if (bytes) {
+    HIP_TRY(hipMemcpy(p->d_bstage_lb, lb, bytes, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->d_bstage_ub, ub, bytes, hipMemcpyHostToDevice));
+  }
+  int rc = prop_run_batch_device(p, nodes, p->d_bstage_lb, p->d_bstage_ub, max_rounds, nullptr,
+                                 out);
+  if (rc) return rc;
+  if (bytes) {
+    HIP_TRY(hipMemcpy(lb, p->d_bstage_lb, bytes, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ub, p->d_bstage_ub, bytes, hipMemcpyDeviceToHost));
+  }
   return PROP_OK;
 }
 

@@ -118,6 +118,25 @@ def test_batch_reuse_and_invalid(torch_cuda, lib):
         assert [(r.status, r.rounds) for r in c] == [(r.status, r.rounds) for r in a]
 
 
+def test_batch_host_arrays(torch_cuda, lib):
+    """prop_run_batch on host arrays equals prop_run_batch_device, also after
+    a larger batch has grown the staging (a smaller call reuses it)."""
+    torch = torch_cuda
+    inst = synth.layout_mix(2)
+    lbs, ubs = node_set(inst, 19, 16_000, frac_hi=0.1, only_int=False)
+    with lib.Problem.from_instance(inst) as p:
+        dev, dlb, dub = run_batch(torch, p, lbs, ubs)
+        for count in (19, 6):
+            res, hlb, hub = p.run_batch(lbs[:count], ubs[:count])
+            assert [(r.status, r.rounds) for r in res] == \
+                [(r.status, r.rounds) for r in dev[:count]]
+            for k in range(count):
+                if res[k].status != oracle.INFEASIBLE:
+                    assert np.array_equal(hlb[k], dlb[k]) and np.array_equal(hub[k], dub[k]), k
+        with pytest.raises(ValueError):
+            p.run_batch(lbs[:, :-1], ubs[:, :-1])
+
+
 @pytest.fixture(scope="module")
 def config3(lib):
     inst = synth.cached("config3", synth.config3_matrix)
