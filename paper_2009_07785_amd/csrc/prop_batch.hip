@@ -145,7 +145,7 @@ __device__ __forceinline__ void round_unit(const Problem& P, const Batch& Bt, in
 __device__ __forceinline__ void long_unit(const Problem& P, const Batch& Bt, int s, int k) {
   if (s >= P.n_segs || !Bt.active[k]) return;
   const int g = k / kNodeGroup;
-  seg_phase2(P, s, Bt.gA[g], Bt.gB[g], kNodeGroup, k % kNodeGroup, Bt.partials, Bt.nodes, k);
+  seg_phase2<true>(P, s, Bt.gA[g], Bt.gB[g], kNodeGroup, k % kNodeGroup, Bt.partials, Bt.nodes, k);
 }
 
 // Block bx of nbx over group g's (variable, node) pairs: copy changed pairs

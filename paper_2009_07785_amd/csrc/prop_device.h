@@ -669,6 +669,15 @@ __device__ __forceinline__ void seg_phase1_nodes(const Problem& P, int s,
   }
 }
 
+// kBatchLoads (kernels that run phase 2 on its own): when a segment needs
+// its candidates, each lane takes its entries kSegBatch at a time, loading
+// all their coefficients and column words, then gathering all their bounds,
+// then testing them, so the lane waits for two memory round trips per
+// kSegBatch entries instead of three per entry.  Positions past the
+// segment's end gather variable 0's pair and are skipped like padding.
+constexpr int kSegBatch = 4;
+
+template <bool kBatchLoads = false>
 __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
                                            const double2* __restrict__ cur,
                                            double2* __restrict__ nxt, uint32_t stride, uint32_t t,
@@ -693,6 +702,27 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
   if (R.min_side) need |= (R.cmin == 0) ? !(R.smn > own.tmin) : (own.min_inf > 0);
   if (R.max_side) need |= (R.cmax == 0) ? !((-R.smx) > own.tmax) : (own.max_inf > 0);
   if (!need) return;
+  if (kBatchLoads) {
+    for (int w0 = 0; w0 < kSegLen / kWave; w0 += kSegBatch) {
+      if (w0 * kWave >= sd.len) break;
+      double av[kSegBatch];
+      int32_t cv[kSegBatch];
+#pragma unroll
+      for (int w = 0; w < kSegBatch; ++w) {
+        const int p = lane + (w0 + w) * kWave;
+        av[w] = p < sd.len ? P.vals[sd.off + p] : 0.0;
+        cv[w] = p < sd.len ? P.cols[sd.off + p] : 0;
+      }
+      double2 bv[kSegBatch];
+#pragma unroll
+      for (int w = 0; w < kSegBatch; ++w) bv[w] = cur[(size_t)(cv[w] & kColMask) * stride + t];
+#pragma unroll
+      for (int w = 0; w < kSegBatch; ++w)
+        if (av[w] != 0.0 && entry_wanted(R, av[w], bv[w].x, bv[w].y, cv[w], P.cont_rel_tol))
+          entry_candidates(P, R, av[w], bv[w].x, bv[w].y, cv[w], nxt + t, stride, stride == 1);
+    }
+    return;
+  }
   for (int p = lane; p < sd.len; p += kWave) {
     const double a = P.vals[sd.off + p];
     if (a == 0.0) continue;
@@ -710,49 +740,117 @@ __device__ __forceinline__ uint32_t u32_load(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Per-thread part over a grid-stride range.
-// In marked rounds every wave also stores the changed flags of its 64
-// consecutive variables as one word of the round's bitmap; the loop keeps
-// the lanes of a wave together for that.
-__device__ __forceinline__ void commit_range(const Problem& P, uint32_t tid, uint32_t nthreads,
-                                             uint32_t& changed, uint32_t& infeasible) {
-  double2* A = P.bnd[0];
-  double2* B = P.bnd[1];
+// Commit of one variable from its merged candidate pair b (b already holds
+// the start-of-round pair folded in).
+__device__ __forceinline__ bool commit_one(const Problem& P, uint32_t v, double2 a, double2 b,
+                                           uint32_t& changed, uint32_t& infeasible) {
+  if (a.x == b.x && a.y == b.y) return false;
+  P.bnd[0][v] = b;
+  P.bnd[1][v] = b;
+  ++changed;
+  if (domain_empty(P.vtype[v] != 0, b.x, b.y, P.feas_tol)) infeasible = 1;
+  return true;
+}
+
+// First part of the commit: variables [0, H), H = n_hot rounded up to a
+// multiple of 64 (at most n), eight lanes per variable.  Each lane takes
+// the max / min over eight of a hot variable's stripe copies (and resets
+// them); lane 0 of the eight also takes the variable's pair in B.  Three
+// butterfly steps combine the eight lanes (max and min are exact, so the
+// grouping does not matter) and lane 0 commits.  In marked rounds a wave
+// covers eight variables and stores their changed flags as one byte of the
+// bitmap; the general part starts at H, so no bitmap word has two writers.
+__device__ __forceinline__ uint32_t hot_end(const Problem& P) {
+  if (P.n_hot <= 0) return 0;
+  const uint32_t h = ((uint32_t)P.n_hot + kWave - 1) / kWave * kWave;
+  return h < (uint32_t)P.n ? h : (uint32_t)P.n;
+}
+
+__device__ __forceinline__ void commit_hot(const Problem& P, uint32_t tid, uint32_t nthreads,
+                                           uint32_t& changed, uint32_t& infeasible) {
+  const uint32_t H = hot_end(P);
+  const uint32_t items = H * 8u;
   const uint32_t lane = tid & (kWave - 1);
-  for (uint32_t v0 = tid - lane; v0 < (uint32_t)P.n; v0 += nthreads) {
-    const uint32_t v = v0 + lane;
-    bool chg = false;
-    if (v < (uint32_t)P.n) {
-      const double2 a = A[v];
-      double2 b;
-      if (v < (uint32_t)P.n_hot) {
-        // a hot variable's candidates sit in its stripe copies (B is not a
-        // target for it): merge them into the committed pair, reset them
-        b = a;
-        double2* st = P.stripes + v;
-#pragma unroll 8
-        for (int c = 0; c < kStripes; ++c) {
-          const double2 q = st[(size_t)c * P.n_hot];
-          b.x = q.x > b.x ? q.x : b.x;
-          b.y = q.y < b.y ? q.y : b.y;
-        }
-#pragma unroll 8
-        for (int c = 0; c < kStripes; ++c)
-          st[(size_t)c * P.n_hot] = make_double2(-__builtin_inf(), __builtin_inf());
-      } else {
-        b = B[v];
-      }
-      if (a.x != b.x || a.y != b.y) {
-        A[v] = b;
-        B[v] = b;
-        ++changed;
-        chg = true;
-        if (domain_empty(P.vtype[v] != 0, b.x, b.y, P.feas_tol)) infeasible = 1;
-      }
+  for (uint32_t q0 = tid - lane; q0 < items; q0 += nthreads) {
+    const uint32_t q = q0 + lane;
+    const bool ok = q < items;
+    const uint32_t v = ok ? q >> 3 : 0;
+    const uint32_t g = q & 7;
+    double lo = -__builtin_inf(), hi = __builtin_inf();
+    if (ok && g == 0) {
+      const double2 b = P.bnd[1][v];
+      lo = b.x;
+      hi = b.y;
     }
+    if (ok && v < (uint32_t)P.n_hot) {
+      double2* st = P.stripes + v + (size_t)g * 8 * P.n_hot;
+      double2 c[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) c[k] = st[(size_t)k * P.n_hot];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        lo = c[k].x > lo ? c[k].x : lo;
+        hi = c[k].y < hi ? c[k].y : hi;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        st[(size_t)k * P.n_hot] = make_double2(-__builtin_inf(), __builtin_inf());
+    }
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+      const double olo = __shfl_xor(lo, off, kWave);
+      const double ohi = __shfl_xor(hi, off, kWave);
+      lo = olo > lo ? olo : lo;
+      hi = ohi < hi ? ohi : hi;
+    }
+    bool chg = false;
+    if (ok && g == 0) chg = commit_one(P, v, P.bnd[0][v], make_double2(lo, hi), changed, infeasible);
     if (P.marking) {
       const uint64_t bits = __ballot(chg);
-      if (lane == 0) P.chg_bits[v0 / kWave] = bits;
+      if (lane == 0) {
+        uint32_t byte = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) byte |= (uint32_t)((bits >> (8 * k)) & 1u) << k;
+        // variables q0 / 8 .. q0 / 8 + 7: byte q0 / 64 of the little-endian bitmap
+        reinterpret_cast<uint8_t*>(P.chg_bits)[q0 / kWave] = (uint8_t)byte;
+      }
+    }
+  }
+}
+
+// Second part: variables [H, n), a wave taking kCommitUnroll consecutive
+// 64-variable words per step of a grid-stride loop, every pair of the step
+// loaded before any is compared.  In marked rounds the wave also stores
+// each word's changed flags as one word of the round's bitmap; the loop
+// keeps the lanes of a wave together for that.
+constexpr int kCommitUnroll = 2;
+
+__device__ __forceinline__ void commit_range(const Problem& P, uint32_t tid, uint32_t nthreads,
+                                             uint32_t& changed, uint32_t& infeasible) {
+  commit_hot(P, tid, nthreads, changed, infeasible);
+  const uint32_t lane = tid & (kWave - 1);
+  const uint32_t n = (uint32_t)P.n;
+  const uint64_t step = (uint64_t)nthreads * kCommitUnroll;
+  for (uint64_t v0 = hot_end(P) + (uint64_t)(tid - lane) * kCommitUnroll; v0 < n; v0 += step) {
+    double2 a[kCommitUnroll], b[kCommitUnroll];
+#pragma unroll
+    for (int k = 0; k < kCommitUnroll; ++k) {
+      const uint64_t v = v0 + (uint64_t)k * kWave + lane;
+      if (v < n) {
+        a[k] = P.bnd[0][v];
+        b[k] = P.bnd[1][v];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kCommitUnroll; ++k) {
+      const uint64_t w0 = v0 + (uint64_t)k * kWave;
+      const uint64_t v = w0 + lane;
+      bool chg = false;
+      if (v < n) chg = commit_one(P, (uint32_t)v, a[k], b[k], changed, infeasible);
+      if (P.marking && w0 < n) {
+        const uint64_t bits = __ballot(chg);
+        if (lane == 0) P.chg_bits[w0 / kWave] = bits;
+      }
     }
   }
 }

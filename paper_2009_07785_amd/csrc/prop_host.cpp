@@ -386,6 +386,9 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   Ctrl* d_ctrl;
   if ((rc = dev_alloc(p, &d_ctrl, 1))) return rc;
   HIP_TRY(hipMemset(d_ctrl, 0, sizeof(Ctrl)));
+  uint64_t* d_grp;
+  if ((rc = dev_alloc(p, &d_grp, (size_t)kCommitGroups * kGroupWordStride))) return rc;
+  HIP_TRY(hipMemset(d_grp, 0, sizeof(uint64_t) * kCommitGroups * kGroupWordStride));
   if ((rc = dev_alloc(p, &p->d_stage_lb, (size_t)n))) return rc;
   if ((rc = dev_alloc(p, &p->d_stage_ub, (size_t)n))) return rc;
 
@@ -409,6 +412,7 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   P.stripes = stripes;
   P.n_hot = n_hot;
   P.ctrl = d_ctrl;
+  P.commit_grp = d_grp;
   P.eps_int = p->params.eps_int;
   P.cont_rel_tol = p->params.cont_rel_tol;
   P.feas_tol = p->params.feas_tol;

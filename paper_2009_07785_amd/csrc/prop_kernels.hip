@@ -17,6 +17,8 @@ namespace prop {
 // kernels
 // ---------------------------------------------------------------------------
 __global__ void k_init(Problem P) {
+  if (blockIdx.x == 0 && threadIdx.x < kCommitGroups)
+    P.commit_grp[threadIdx.x * kGroupWordStride] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     Ctrl* C = P.ctrl;
     C->commit_word = 0;
@@ -149,7 +151,8 @@ __global__ __launch_bounds__(kBlock) void k_round_long(Problem P) {
   const int r = round_of(P);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int s = blockIdx.x * kWavesPerBlock + wave;
-  if (s < P.n_segs) seg_phase2(P, s, P.bnd[0], P.bnd[1], 1, 0, P.partials, 1, 0, marked_round(P), r);
+  if (s < P.n_segs)
+    seg_phase2<true>(P, s, P.bnd[0], P.bnd[1], 1, 0, P.partials, 1, 0, marked_round(P), r);
 }
 
 // Marked rounds, after the commit of round r: stamps the rows of every
@@ -184,12 +187,21 @@ __global__ __launch_bounds__(kBlock) void k_commit(Problem P) {
   block_sum2(changed, infeasible);
   if (threadIdx.x == 0) {
     const uint64_t add = kCommitBlock | (uint64_t)changed | (infeasible ? kCommitInf : 0ull);
-    const uint64_t old =
-        __hip_atomic_fetch_add(&C->commit_word, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((old >> 48) == gridDim.x - 1u) {
-      const uint64_t tot = old + add;
-      end_of_round(P, r, max_rounds, (uint32_t)tot, (uint32_t)((tot >> 32) & 0xffff));
-      __hip_atomic_store(&C->commit_word, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t grp = blockIdx.x / kCommitGroup;
+    const uint32_t in_grp = min((uint32_t)kCommitGroup, gridDim.x - grp * kCommitGroup);
+    uint64_t* gw = P.commit_grp + (size_t)grp * kGroupWordStride;
+    const uint64_t gold = __hip_atomic_fetch_add(gw, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((gold >> 48) == in_grp - 1u) {
+      // last block of its group: every other block of the group has added
+      const uint64_t gtot = gold + add;
+      __hip_atomic_store(gw, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint64_t old =
+          __hip_atomic_fetch_add(&C->commit_word, gtot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint64_t tot = old + gtot;
+      if ((tot >> 48) == gridDim.x) {
+        end_of_round(P, r, max_rounds, (uint32_t)tot, (uint32_t)((tot >> 32) & 0xffff));
+        __hip_atomic_store(&C->commit_word, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
   }
 }
@@ -244,7 +256,9 @@ hipError_t launch_round(const Problem& P, hipStream_t s, hipEvent_t e0, hipEvent
     hipLaunchKernelGGL(k_round_long, dim3(blocks_for(P.n_segs, kWavesPerBlock, 1 << 30)),
                        dim3(kBlock), 0, s, P);
   // at most 65535 blocks: the packed commit counter keeps 16 bits per field
-  hipLaunchKernelGGL(k_commit, dim3(blocks_for(P.n, kBlock, 1024)), dim3(kBlock), 0, s, P);
+  hipLaunchKernelGGL(k_commit, dim3(blocks_for((int64_t)P.n / 4 + 2 * (int64_t)P.n_hot, kBlock,
+                                                kCommitMaxBlocks)),
+                     dim3(kBlock), 0, s, P);
   if (P.marking) hipLaunchKernelGGL(k_mark, dim3(1024), dim3(kBlock), 0, s, P);
   return hipGetLastError();
 }

@@ -79,6 +79,15 @@ struct SegPartial {
   int32_t pad0, pad1;
 };
 
+// The commit kernel's blocks report their totals in two levels: into one of
+// kCommitGroups group words (kCommitGroup blocks each, one 128-byte line
+// apart), and the last block of a group into Ctrl::commit_word, so that no
+// word sees more than 32 returning atomics per round.
+constexpr int kCommitGroup = 32;
+constexpr int kCommitGroups = 32;
+constexpr int kCommitMaxBlocks = kCommitGroup * kCommitGroups;
+constexpr int kGroupWordStride = 16;  // uint64 words per group word's line
+
 // Device control block of one problem.
 struct Ctrl {
   uint64_t commit_word;    // packed per-round commit totals (see the kernels)
@@ -118,6 +127,7 @@ struct Problem {
   int32_t n_hot;
   int32_t pad_hot;
   Ctrl* ctrl;
+  uint64_t* commit_grp;     // [kCommitGroups * kGroupWordStride] commit group words
   // parameters
   double eps_int, cont_rel_tol, feas_tol;
   // marked rounds (marking != 0): a row is processed in round r only when
