@@ -84,7 +84,59 @@ __global__ __launch_bounds__(kBlock) void k_unpack_batch(Problem P, Batch Bt,
 __device__ __forceinline__ void batch_set_done(const Problem& P, uint32_t my_active) {
   uint32_t dummy = 0;
   block_sum2(my_active, dummy);
-  if (threadIdx.x == 0) P.ctrl->done = my_active == 0 ? 1u : 0u;
+  if (threadIdx.x == 0) {
+    P.ctrl->done = my_active == 0 ? 1u : 0u;
+    P.ctrl->active_nodes = my_active;
+  }
+}
+
+// Slot moves of the batch driver's compaction: for move q, node slot
+// moves[q].x (active) goes to slot moves[q].y (free): its pairs (A and B
+// are equal after a commit) and its per-slot state; the source slot becomes
+// inactive.  Sources and destinations are disjoint.
+__global__ __launch_bounds__(kBlock) void k_move_batch(Problem P, Batch Bt,
+                                                       const int2* __restrict__ moves, int count) {
+  const size_t total = (size_t)count * P.n;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int q = (int)(i / (size_t)P.n);
+    const size_t j = i - (size_t)q * P.n;
+    const int s = moves[q].x, d = moves[q].y;
+    const double2 b = Bt.gA[s / kNodeGroup][j * kNodeGroup + (s % kNodeGroup)];
+    Bt.gA[d / kNodeGroup][j * kNodeGroup + (d % kNodeGroup)] = b;
+    Bt.gB[d / kNodeGroup][j * kNodeGroup + (d % kNodeGroup)] = b;
+  }
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < (size_t)count; q += stride) {
+    const int s = moves[q].x, d = moves[q].y;
+    Bt.status[d] = Bt.status[s];
+    Bt.rounds[d] = Bt.rounds[s];
+    Bt.maxr[d] = Bt.maxr[s];
+    Bt.changed[d] = 0;
+    Bt.infeasible[d] = 0;
+    Bt.invalid[d] = 0;
+    Bt.active[d] = 1;
+    Bt.active[s] = 0;
+  }
+}
+
+// Unpacks slot pairs[q].x into row pairs[q].y of node-major arrays.
+__global__ __launch_bounds__(kBlock) void k_unpack_slots(Problem P, Batch Bt,
+                                                         double* __restrict__ ulb,
+                                                         double* __restrict__ uub,
+                                                         const int2* __restrict__ pairs,
+                                                         int count) {
+  const size_t total = (size_t)count * P.n;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int q = (int)(i / (size_t)P.n);
+    const int v = (int)(i - (size_t)q * P.n);
+    const int k = pairs[q].x;
+    const size_t src = (size_t)P.perm[v] * kNodeGroup + (k % kNodeGroup);
+    const double2 b = Bt.gA[k / kNodeGroup][src];
+    const size_t dst = (size_t)pairs[q].y * P.n + v;
+    ulb[dst] = b.x;
+    uub[dst] = b.y;
+  }
 }
 
 // One block: round-0 decision for nodes [k0, k0 + cnt); with `whole`, the
@@ -374,6 +426,23 @@ hipError_t launch_round_batch(const Problem& P, const Batch& Bt, hipStream_t s) 
                      dim3(blocks_for((int64_t)P.n * kNodeGroup, kBlock, 256), Bt.groups),
                      dim3(kBlock), 0, s, P, Bt);
   hipLaunchKernelGGL(k_end_batch, dim3(1), dim3(kBlock), 0, s, P, Bt);
+  return hipGetLastError();
+}
+
+hipError_t launch_move_batch(const Problem& P, const Batch& Bt, const int2* moves, int count,
+                             hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_move_batch,
+                     dim3(blocks_for((int64_t)count * (P.n > 1 ? P.n : 1), kBlock, 4096)),
+                     dim3(kBlock), 0, s, P, Bt, moves, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_slots(const Problem& P, const Batch& Bt, double* lb, double* ub,
+                               const int2* pairs, int count, hipStream_t s) {
+  if (count <= 0 || P.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unpack_slots, dim3(blocks_for((int64_t)count * P.n, kBlock, 4096)),
+                     dim3(kBlock), 0, s, P, Bt, lb, ub, pairs, count);
   return hipGetLastError();
 }
 

@@ -58,6 +58,8 @@ struct prop_problem {
   std::vector<void*> batch_allocs;
   int32_t* h_bstatus = nullptr;  // pinned copies of per-node status / rounds
   int32_t* h_brounds = nullptr;
+  int2* d_bret = nullptr;        // batch compaction: (slot, node) lists to unpack
+  int2* d_bmove = nullptr;       // and (from slot, to slot) moves, batch capacity each
   // staging for prop_run_batch (host arrays), grown on demand
   double* d_bstage_lb = nullptr;
   double* d_bstage_ub = nullptr;

@@ -616,6 +616,8 @@ int ensure_batch(prop_problem* p, int32_t nodes) {
   if ((rc = alloc((void**)&b.infeasible, nodes * sizeof(uint32_t)))) return rc;
   if ((rc = alloc((void**)&b.invalid, nodes * sizeof(uint32_t)))) return rc;
   if ((rc = alloc((void**)&b.maxr, nodes * sizeof(int32_t)))) return rc;
+  if ((rc = alloc((void**)&p->d_bret, nodes * sizeof(int2)))) return rc;
+  if ((rc = alloc((void**)&p->d_bmove, nodes * sizeof(int2)))) return rc;
   HIP_TRY(hipMemset(b.invalid, 0, nodes * sizeof(uint32_t)));
   HIP_TRY(hipMemset(b.infeasible, 0, nodes * sizeof(uint32_t)));
   if (hipHostMalloc((void**)&p->h_bstatus, nodes * sizeof(int32_t), hipHostMallocDefault) !=
@@ -743,7 +745,7 @@ int prop_create(const prop_csr* A, const double* lhs, const double* rhs, const u
   p->grid = cus * per_cu;
   if (!coop) p->loop_mode = PROP_LOOP_STREAM;
   if (hipHostMalloc((void**)&p->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&p->h_done, 2 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&p->h_done, 4 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
     release(p);
     return fail(PROP_ENOMEM, "pinned host allocation failed");
   }
@@ -824,6 +826,61 @@ int prop_run(prop_problem* p, double* lb, double* ub, int32_t max_rounds, prop_r
   return PROP_OK;
 }
 
+namespace {
+
+// Compaction of a running batch, at a point where all queued rounds are
+// done: every slot whose node has finished is unpacked into the caller's
+// row of that node (its result kept in `res`), and the active nodes of
+// slots at or above A (the number of active nodes) move into the free slots
+// below A, so the next rounds run over ceil(A / 8) groups instead of all.
+// A node's arithmetic does not depend on its slot, so its results do not
+// change.  slot_node[k] is the caller's node in slot k, -1 for none.
+int compact_batch(prop_problem* p, Batch& bt, std::vector<int32_t>& slot_node,
+                  std::vector<prop_result>& res, double* d_lb, double* d_ub, hipStream_t s) {
+  const Problem& P = p->P;
+  const int S = bt.nodes;
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<uint32_t> active(S);
+  std::vector<int32_t> status(S), rounds(S);
+  HIP_TRY(hipMemcpy(active.data(), bt.active, S * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(status.data(), bt.status, S * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(rounds.data(), bt.rounds, S * sizeof(int32_t), hipMemcpyDeviceToHost));
+  std::vector<int2> ret, mv;
+  int A = 0;
+  for (int k = 0; k < S; ++k) {
+    if (slot_node[k] < 0) continue;
+    if (active[k]) {
+      ++A;
+      continue;
+    }
+    res[slot_node[k]] = prop_result{status[k], rounds[k]};
+    ret.push_back(make_int2(k, slot_node[k]));
+    slot_node[k] = -1;
+  }
+  int src = S - 1;
+  for (int h = 0; h < A; ++h) {
+    if (slot_node[h] >= 0) continue;
+    while (slot_node[src] < 0) --src;  // an active slot >= A exists for every hole < A
+    mv.push_back(make_int2(src, h));
+    slot_node[h] = slot_node[src];
+    slot_node[src] = -1;
+    --src;
+  }
+  if (!ret.empty()) {
+    HIP_TRY(hipMemcpy(p->d_bret, ret.data(), ret.size() * sizeof(int2), hipMemcpyHostToDevice));
+    HIP_TRY(launch_unpack_slots(P, bt, d_lb, d_ub, p->d_bret, (int)ret.size(), s));
+  }
+  if (!mv.empty()) {
+    HIP_TRY(hipMemcpy(p->d_bmove, mv.data(), mv.size() * sizeof(int2), hipMemcpyHostToDevice));
+    HIP_TRY(launch_move_batch(P, bt, p->d_bmove, (int)mv.size(), s));
+  }
+  bt.nodes = A;
+  bt.groups = (A + kNodeGroup - 1) / kNodeGroup;
+  return PROP_OK;
+}
+
+}  // namespace
+
 int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* d_ub,
                           int32_t max_rounds, void* stream, prop_result* out) {
   if (!p || !out) return fail(PROP_EINVAL, "NULL argument");
@@ -846,13 +903,18 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
   HIP_TRY(launch_pack_batch(P, bt, d_lb, d_ub, 0, nodes, s));
   HIP_TRY(launch_start_batch(P, bt, max_rounds, 0, nodes, true, s));
   HIP_TRY(hipEventRecord(p->ev[1], s));
-  // rounds in batches; the done flag is read one batch behind (see the
-  // stream driver of single runs)
-  const bool graph = p->loop_mode == PROP_LOOP_GRAPH;
+  // rounds in batches; the done flag and the active-node count are read one
+  // batch behind (see the stream driver of single runs).  When the active
+  // nodes would fit in fewer groups, the batch is compacted.
+  bool graph = p->loop_mode == PROP_LOOP_GRAPH;
   if (graph) {
     rc = ensure_batch_graphs(p, bt);
     if (rc) return rc;
   }
+  std::vector<int32_t> slot_node(nodes);
+  std::iota(slot_node.begin(), slot_node.end(), 0);
+  std::vector<prop_result> res(nodes, prop_result{kInvalidInput, 0});
+  bool compacted = false;
   int slot = 0;
   bool pending[2] = {false, false};
   for (int r = 1; r <= max_rounds;) {
@@ -866,6 +928,8 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
       HIP_TRY(hipMemcpyAsync(&p->h_done[slot], &P.ctrl->done, sizeof(uint32_t),
                              hipMemcpyDeviceToHost, s));
     }
+    HIP_TRY(hipMemcpyAsync(&p->h_done[2 + slot], &P.ctrl->active_nodes, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(p->ev_batch[slot], s));
     pending[slot] = true;
     slot ^= 1;
@@ -873,27 +937,48 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
       HIP_TRY(hipEventSynchronize(p->ev_batch[slot]));
       pending[slot] = false;
       if (p->h_done[slot] == 1) break;
+      const uint32_t act = p->h_done[2 + slot];
+      if (r <= max_rounds && act > 0 &&
+          (act + kNodeGroup - 1) / kNodeGroup < (uint32_t)bt.groups) {
+        rc = compact_batch(p, bt, slot_node, res, d_lb, d_ub, s);
+        if (rc) return rc;
+        compacted = true;
+        graph = false;  // the captured rounds are for the old group count
+        pending[0] = pending[1] = false;
+        if (bt.nodes == 0) break;
+      }
     }
   }
   HIP_TRY(hipEventRecord(p->ev[2], s));
-  HIP_TRY(launch_unpack_batch(P, bt, d_lb, d_ub, 0, nodes, s));
-  HIP_TRY(hipMemcpyAsync(p->h_bstatus, bt.status, nodes * sizeof(int32_t), hipMemcpyDeviceToHost,
-                         s));
-  HIP_TRY(hipMemcpyAsync(p->h_brounds, bt.rounds, nodes * sizeof(int32_t), hipMemcpyDeviceToHost,
-                         s));
+  if (!compacted) {
+    HIP_TRY(launch_unpack_batch(P, bt, d_lb, d_ub, 0, nodes, s));
+  } else if (bt.nodes > 0) {
+    std::vector<int2> fin;
+    for (int k = 0; k < bt.nodes; ++k)
+      if (slot_node[k] >= 0) fin.push_back(make_int2(k, slot_node[k]));
+    // the stream may still run a compaction's unpack of d_bret
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(p->d_bret, fin.data(), fin.size() * sizeof(int2), hipMemcpyHostToDevice));
+    HIP_TRY(launch_unpack_slots(P, bt, d_lb, d_ub, p->d_bret, (int)fin.size(), s));
+  }
+  if (bt.nodes > 0) {
+    HIP_TRY(hipMemcpyAsync(p->h_bstatus, bt.status, bt.nodes * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(p->h_brounds, bt.rounds, bt.nodes * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+  }
   HIP_TRY(hipEventRecord(p->ev[3], s));
   HIP_TRY(hipStreamSynchronize(s));
   hipEventElapsedTime(&p->last_loop_ms, p->ev[1], p->ev[2]);
   hipEventElapsedTime(&p->last_total_ms, p->ev[0], p->ev[3]);
   p->kev_used = 0;
   p->last_kernel_ms = 0.0;
+  for (int k = 0; k < bt.nodes; ++k)
+    if (slot_node[k] >= 0) res[slot_node[k]] = prop_result{p->h_bstatus[k], p->h_brounds[k]};
   for (int32_t k = 0; k < nodes; ++k)
-    if (p->h_bstatus[k] == kInvalidInput)
+    if (res[k].status == kInvalidInput)
       return fail(PROP_EINVAL, "node %d: a bound is NaN, +inf as lower, -inf as upper, or beyond 2^200", k);
-  for (int32_t k = 0; k < nodes; ++k) {
-    out[k].status = p->h_bstatus[k];
-    out[k].rounds = p->h_brounds[k];
-  }
+  for (int32_t k = 0; k < nodes; ++k) out[k] = res[k];
   g_error.clear();
   return PROP_OK;
 }

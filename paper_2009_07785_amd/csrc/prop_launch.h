@@ -30,6 +30,12 @@ hipError_t launch_unpack_batch(const Problem& P, const Batch& Bt, double* lb, do
 hipError_t launch_start_batch(const Problem& P, const Batch& Bt, int max_rounds, int k0, int cnt,
                               bool whole, hipStream_t s);
 hipError_t launch_round_batch(const Problem& P, const Batch& Bt, hipStream_t s);
+// Compaction of a batch: slot moves (moves[q].x -> moves[q].y, device
+// array) and unpacking of listed slots (pairs[q] = (slot, caller's row)).
+hipError_t launch_move_batch(const Problem& P, const Batch& Bt, const int2* moves, int count,
+                             hipStream_t s);
+hipError_t launch_unpack_slots(const Problem& P, const Batch& Bt, double* lb, double* ub,
+                               const int2* pairs, int count, hipStream_t s);
 
 // Serving: one round of every instance listed in step S (device copy; H is
 // the host copy it was uploaded from, for the grid sizes).

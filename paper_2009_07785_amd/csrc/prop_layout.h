@@ -102,7 +102,8 @@ struct Ctrl {
   uint32_t abort;          // barrier wait gave up (device timeout)
   uint32_t mark_all;       // marked rounds: the next round processes every row
   int32_t max_rounds;      // round limit of the current run
-  uint32_t pad[3];
+  uint32_t active_nodes;   // batches: nodes still active after the last round
+  uint32_t pad[2];
 };
 
 // Everything a kernel needs, passed by value.

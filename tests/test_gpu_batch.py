@@ -118,6 +118,25 @@ def test_batch_reuse_and_invalid(torch_cuda, lib):
         assert [(r.status, r.rounds) for r in c] == [(r.status, r.rounds) for r in a]
 
 
+def test_batch_compaction(torch_cuda, lib):
+    """Nodes that finish at different rounds: every third of 40 nodes (five
+    groups) has an empty domain at round 0, so the 26 others fit in four
+    groups and the driver compacts the batch at its first look at the
+    active count, and again as nodes converge.  Every node still gives its
+    own single run's results (and the oracle's), with the stream driver and
+    with the graph driver (which continues with plain launches after a
+    compaction)."""
+    inst = synth.config0(3)
+    lbs, ubs = node_set(inst, 40, 17_000, frac_hi=0.2)
+    ivar = int(np.nonzero(inst.vartype == 1)[0][0])
+    for k in range(0, 40, 3):
+        lbs[k][ivar], ubs[k][ivar] = 5.0, 4.0
+    statuses = check_batch_vs_single(torch_cuda, lib, inst, lbs, ubs, with_oracle=True)
+    assert {oracle.CONVERGED, oracle.INFEASIBLE} <= statuses
+    # a round limit that stops the survivors mid-run, after a compaction
+    check_batch_vs_single(torch_cuda, lib, inst, lbs, ubs, max_rounds=9)
+
+
 def test_batch_host_arrays(torch_cuda, lib):
     """prop_run_batch on host arrays equals prop_run_batch_device, also after
     a larger batch has grown the staging (a smaller call reuses it)."""
