@@ -165,11 +165,15 @@ int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rou
  * place.  out: host array of `nodes` results.  Each node's status, rounds
  * and bounds are bitwise those a separate prop_run_device call on that node
  * returns; nodes that finish early stop consuming work.  Rounds are queued
- * on `stream` in batches as by PROP_LOOP_STREAM.  The first call with more
- * nodes than any earlier call allocates the batch workspace
- * (32 * n * ceil(nodes / 8) * 8 bytes of bounds, plus per-node counters and
- * long-row partials), kept until prop_destroy; later calls allocate
- * nothing.  An invalid bound in any node returns PROP_EINVAL. */
+ * on `stream` in batches as by PROP_LOOP_STREAM (or replayed as by
+ * PROP_LOOP_GRAPH).  When the nodes still running would fit in fewer groups
+ * of 8, the call synchronises `stream`, writes the finished nodes' rows of
+ * d_lb / d_ub, and packs the running nodes into fewer groups; the rest of
+ * the rows are written at the end.  The first call with more nodes than any
+ * earlier call allocates the batch workspace (32 * n * ceil(nodes / 8) * 8
+ * bytes of bounds, plus per-node counters and lists and long-row partials),
+ * kept until prop_destroy; later calls allocate nothing.  An invalid bound
+ * in any node returns PROP_EINVAL. */
 int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* d_ub,
                           int32_t max_rounds, void* stream, prop_result* out);
 
