@@ -286,22 +286,30 @@ __device__ __forceinline__ void end_slots(const Problem& P, const Batch& Bt, Srv
 }
 
 // ---- batch kernels (one problem) ------------------------------------------
+// Waves are numbered group-major: the waves in flight at any time work on
+// one or two groups, whose bound lines (128 bytes per variable, 64 MB for
+// 500,000 variables) then stay in the caches while the matrix streams past,
+// once per group.  Numbered unit-major, every group's lines would be in use
+// at once and each gather would go to HBM.
 __global__ __launch_bounds__(kBlock) void k_round_batch(Problem P, Batch Bt) {
   if (u32_load(&P.ctrl->done)) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-  const int unit = (int)(wid / Bt.groups);
-  const int g = (int)(wid - (int64_t)unit * Bt.groups);
-  round_unit(P, Bt, unit, g);
+  const int64_t units = (int64_t)P.n_segs + P.n_chunks;
+  if (units == 0) return;
+  const int g = (int)(wid / units);
+  if (g >= Bt.groups) return;
+  round_unit(P, Bt, (int)(wid - (int64_t)g * units), g);
 }
 
 __global__ __launch_bounds__(kBlock) void k_round_long_batch(Problem P, Batch Bt) {
   if (u32_load(&P.ctrl->done)) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-  const int s = (int)(wid / Bt.nodes);
-  const int k = (int)(wid - (int64_t)s * Bt.nodes);
-  long_unit(P, Bt, s, k);
+  if (P.n_segs == 0) return;
+  const int k = (int)(wid / P.n_segs);
+  if (k >= Bt.nodes) return;
+  long_unit(P, Bt, (int)(wid - (int64_t)k * P.n_segs), k);
 }
 
 // Commit per (variable, node) of group blockIdx.y, with per-node counts.
