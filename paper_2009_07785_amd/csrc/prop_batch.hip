@@ -356,9 +356,12 @@ __global__ __launch_bounds__(kBlock) void k_srv_round(const SrvInst* __restrict_
   const Problem P = I[E.inst].P;
   if (u32_load(&P.ctrl->done)) return;
   const Batch Bt = step_batch(I, E);
+  // group-major within the instance, as in k_round_batch
   const int64_t local = wid - E.round_base;
-  const int unit = (int)(local / E.groups);
-  round_unit(P, Bt, unit, (int)(local - (int64_t)unit * E.groups));
+  const int64_t units = (int64_t)P.n_segs + P.n_chunks;
+  if (units == 0) return;
+  const int g = (int)(local / units);
+  round_unit(P, Bt, (int)(local - (int64_t)g * units), g);
 }
 
 __global__ __launch_bounds__(kBlock) void k_srv_long(const SrvInst* __restrict__ I,
@@ -371,8 +374,9 @@ __global__ __launch_bounds__(kBlock) void k_srv_long(const SrvInst* __restrict__
   if (u32_load(&P.ctrl->done)) return;
   const Batch Bt = step_batch(I, E);
   const int64_t local = wid - E.long_base;
-  const int s = (int)(local / Bt.nodes);
-  long_unit(P, Bt, s, (int)(local - (int64_t)s * Bt.nodes));
+  if (P.n_segs == 0) return;
+  const int k = (int)(local / P.n_segs);
+  long_unit(P, Bt, (int)(local - (int64_t)k * P.n_segs), k);
 }
 
 __global__ __launch_bounds__(kBlock) void k_srv_commit(const SrvInst* __restrict__ I,
