@@ -133,29 +133,20 @@ __device__ __forceinline__ void accumulate(double a, double l, double u, DD& smi
 // means the candidate cannot count while the slack is >= 0, encoded as the
 // threshold -2^-1074 (slack > -2^-1074 <=> slack >= 0).  An infinite bound
 // to tighten counts every finite candidate: threshold +inf.
+// Straight-line code: every case is computed with the same operations in
+// the same order as its own branch would, and selected at the end, so the
+// wave runs no divergent branches here.
 __device__ __forceinline__ double side_threshold(double a, double l, double u, bool is_int,
                                                  bool upper, double tau) {
-  double w;
-  if (upper) {
-    if (u == __builtin_inf()) return __builtin_inf();
-    if (is_int) {
-      w = u - l;
-    } else {
-      const double s = __builtin_fabs(u) > 1.0 ? __builtin_fabs(u) : 1.0;
-      w = (u - tau * s) - l;
-    }
-  } else {
-    if (l == -__builtin_inf()) return __builtin_inf();
-    if (is_int) {
-      w = u - l;
-    } else {
-      const double s = __builtin_fabs(l) > 1.0 ? __builtin_fabs(l) : 1.0;
-      w = u - (l + tau * s);
-    }
-  }
-  if (!(w > 0.0)) return -0x1p-1074;
-  const double thr = (__builtin_fabs(a) * w) * PROP_SKIP_MARGIN;
-  return thr >= PROP_SKIP_FLOOR ? thr : __builtin_inf();
+  const double bnd = upper ? u : l;  // the bound a candidate would tighten
+  const double s = __builtin_fabs(bnd) > 1.0 ? __builtin_fabs(bnd) : 1.0;
+  const double wc = upper ? (u - tau * s) - l : u - (l + tau * s);
+  const double w = is_int ? u - l : wc;
+  double thr = (__builtin_fabs(a) * w) * PROP_SKIP_MARGIN;
+  thr = thr >= PROP_SKIP_FLOOR ? thr : __builtin_inf();
+  thr = w > 0.0 ? thr : -0x1p-1074;
+  // u = +inf (upper) or l = -inf (lower): every finite candidate counts
+  return is_inf(bnd) ? __builtin_inf() : thr;
 }
 
 __device__ __forceinline__ bool domain_empty(bool is_int, double l, double u, double feas_tol) {
@@ -294,12 +285,11 @@ __device__ __forceinline__ void entry_candidates(const Problem& P, const RowStat
 // map to 2^-100 (no subnormal floats are involved); W <= 0 (skipped iff the
 // slack is >= 0) maps to 0; "never skip" stays +inf.
 __device__ __forceinline__ float skip_code(double thr) {
-  if (thr < 0.0) return 0.0f;
-  if (!(thr < __builtin_inf())) return __builtin_inff();
-  if (thr < 0x1p-100) return 0x1p-100f;
   float f = (float)thr;
-  if ((double)f <= thr) f = __int_as_float(__float_as_int(f) + 1);
-  return f;
+  f = (double)f <= thr ? __int_as_float(__float_as_int(f) + 1) : f;
+  f = thr < 0x1p-100 ? 0x1p-100f : f;
+  f = thr < __builtin_inf() ? f : __builtin_inff();
+  return thr < 0.0 ? 0.0f : f;
 }
 
 // Both skip codes of an entry: the rhs side (through the min activity) and
