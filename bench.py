@@ -181,8 +181,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: this library has no multi-GPU path; "
+              "the value is one GPU's throughput", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
