@@ -135,6 +135,20 @@ def test_batch_compaction(torch_cuda, lib):
     assert {oracle.CONVERGED, oracle.INFEASIBLE} <= statuses
     # a round limit that stops the survivors mid-run, after a compaction
     check_batch_vs_single(torch_cuda, lib, inst, lbs, ubs, max_rounds=9)
+    # an invalid bound in one node of a batch that compacts: the call
+    # reports it, and the problem stays usable
+    bad = lbs.copy()
+    bad[5, 3] = np.nan
+    with lib.Problem.from_instance(inst) as p:
+        with pytest.raises(lib.PropError) as e:
+            run_batch(torch_cuda, p, bad, ubs)
+        assert e.value.code == lib.EINVAL
+        res, blb, bub = run_batch(torch_cuda, p, lbs, ubs)
+        for k in (1, 2, 39):
+            r1, lb1, ub1 = p.run(lbs[k], ubs[k], 100)
+            assert (res[k].status, res[k].rounds) == (r1.status, r1.rounds)
+            if r1.status != oracle.INFEASIBLE:
+                assert np.array_equal(blb[k], lb1) and np.array_equal(bub[k], ub1)
 
 
 def test_batch_host_arrays(torch_cuda, lib):
