@@ -114,8 +114,8 @@ typedef struct {
   int32_t m, n;
   int64_t nnz;             /* nonzero coefficients (explicit zeros dropped) */
   int64_t nnz_stored;      /* stored entries including layout padding */
-  int32_t n_chunks;        /* wave-sized tiles of rows with <= 1024 entries */
-  int32_t n_long_rows;     /* rows with more than 1024 entries */
+  int32_t n_chunks;        /* wave-sized tiles of rows with <= 64 * steps entries */
+  int32_t n_long_rows;     /* rows with more than 64 * steps entries */
   int32_t n_segments;      /* 1024-entry segments of those rows */
   int32_t grid_blocks;     /* blocks of the persistent launch */
   int64_t device_bytes;    /* device memory held by the problem */
@@ -160,7 +160,9 @@ int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rou
                     void* stream, prop_result* out);
 
 /* Propagates `nodes` bound vectors of the same problem together (for
- * example branch-and-bound nodes).  d_lb, d_ub: device arrays of nodes * n
+ * example branch-and-bound nodes: the paper propagates at every node of a
+ * search, Sec. 1, and names propagation after branching as the case that
+ * needs GPU-suited methods, Sec. 5).  d_lb, d_ub: device arrays of nodes * n
  * doubles, node k's bounds at [k * n, (k + 1) * n), caller-owned, updated in
  * place.  out: host array of `nodes` results.  Each node's status, rounds
  * and bounds are bitwise those a separate prop_run_device call on that node
@@ -191,8 +193,8 @@ int prop_run_batch(prop_problem* p, int32_t nodes, double* lb, double* ub, int32
 int prop_set_loop(prop_problem* p, int32_t mode);
 
 /* Marked rounds (enable != 0; off by default), for prop_run and
- * prop_run_device with the stream or host driver (the persistent driver and
- * batches ignore it).  A row is then processed in round r >= 2 only when
+ * prop_run_device with the stream, graph or host driver (the persistent
+ * driver and batches ignore it).  A row is then processed in round r >= 2 only when
  * one of its variables changed in round r - 1: a row whose variables did
  * not change would compute the activities and candidates of the previous
  * round, against the same bounds, and those changed nothing (a candidate
