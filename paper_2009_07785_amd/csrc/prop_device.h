@@ -921,7 +921,15 @@ enum BarrierAction { kActNone = 0, kActStart = 1, kActEndRound = 2 };
 // All threads of all blocks call this.  The action runs on the last
 // arriving block's thread 0 before the others are released.  Returns false
 // when the wait gave up (every block then leaves its loop).
-__device__ __forceinline__ bool grid_barrier(const Problem& P, int action, int r, int max_rounds) {
+//
+// Arrival is counted in two levels, as by the commit kernel: block b adds
+// to group word b mod G (G = min(blocks, kCommitGroups)), and the last
+// block of a group adds the group's total to the control word, so no word
+// sees more than ceil(blocks / G) returning atomics per barrier.  `add` is
+// the block's packed commit total (changed pairs, infeasible flag), summed
+// along: the end-of-round action reads the round's totals from the count.
+__device__ __forceinline__ bool grid_barrier(const Problem& P, int action, int r, int max_rounds,
+                                             uint64_t add = 0) {
   Ctrl* C = P.ctrl;
   __syncthreads();
   __shared__ uint32_t ok_shared;
@@ -929,18 +937,31 @@ __device__ __forceinline__ bool grid_barrier(const Problem& P, int action, int r
     __threadfence();
     uint32_t ok = 1;
     const uint32_t g = __hip_atomic_load(&C->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t prev =
-        __hip_atomic_fetch_add(&C->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == gridDim.x - 1) {
+    const uint32_t ngroups = gridDim.x < (uint32_t)kCommitGroups ? gridDim.x : kCommitGroups;
+    const uint32_t grp = blockIdx.x % ngroups;
+    const uint32_t in_grp = (gridDim.x - 1u - grp) / ngroups + 1u;
+    uint64_t* gw = P.commit_grp + (size_t)grp * kGroupWordStride;
+    const uint64_t mine = kCommitBlock | add;
+    const uint64_t gold = __hip_atomic_fetch_add(gw, mine, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    bool last = false;
+    uint64_t tot = 0;
+    if ((gold >> 48) == in_grp - 1u) {
+      // the group is complete: reset its word (its blocks touch it again
+      // only after this barrier's release) and report the group's total
+      const uint64_t gtot = gold + mine;
+      __hip_atomic_store(gw, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint64_t old =
+          __hip_atomic_fetch_add(&C->commit_word, gtot, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      tot = old + gtot;
+      last = (tot >> 48) == gridDim.x;
+    }
+    if (last) {
       if (action == kActStart) {
         start_status(P, max_rounds);
       } else if (action == kActEndRound) {
-        const uint64_t w =
-            __hip_atomic_load(&C->commit_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        end_of_round(P, r, max_rounds, (uint32_t)w, (uint32_t)((w >> 32) & 0xffff));
-        __hip_atomic_store(&C->commit_word, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        end_of_round(P, r, max_rounds, (uint32_t)tot, (uint32_t)((tot >> 32) & 0xffff));
       }
-      __hip_atomic_store(&C->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&C->commit_word, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&C->bar_gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       uint32_t spins = 0;

@@ -28,7 +28,7 @@ __global__ void k_init(Problem P) {
     C->rounds = 0;
     C->done = 0;
     C->round = 1;
-    C->bar_count = 0;
+    C->bar_spare = 0;
     C->bar_gen = 0;
     C->abort = 0;
     C->mark_all = 1;
@@ -106,11 +106,8 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Problem P, int max_rounds
     uint32_t changed = 0, infeasible = 0;
     commit_range(P, tid, nthreads, changed, infeasible);
     block_sum2(changed, infeasible);
-    if (threadIdx.x == 0 && (changed || infeasible))
-      __hip_atomic_fetch_add(&C->commit_word,
-                             (uint64_t)changed | (infeasible ? kCommitInf : 0ull),
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (!grid_barrier(P, kActEndRound, r, max_rounds)) return;
+    const uint64_t add = (uint64_t)changed | (infeasible ? kCommitInf : 0ull);
+    if (!grid_barrier(P, kActEndRound, r, max_rounds, add)) return;
     if (u32_load(&C->done)) return;
   }
 }

@@ -97,7 +97,7 @@ struct Ctrl {
   int32_t rounds;
   uint32_t done;           // loop finished
   int32_t round;           // next round to run
-  uint32_t bar_count;      // grid barrier arrival counter
+  uint32_t bar_spare;      // unused (arrivals are counted in commit_word)
   uint32_t bar_gen;        // grid barrier generation
   uint32_t abort;          // barrier wait gave up (device timeout)
   uint32_t mark_all;       // marked rounds: the next round processes every row
