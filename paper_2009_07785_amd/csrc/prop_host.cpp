@@ -915,9 +915,32 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
   std::iota(slot_node.begin(), slot_node.end(), 0);
   std::vector<prop_result> res(nodes, prop_result{kInvalidInput, 0});
   bool compacted = false;
+  int r = 1;
+  if (bt.groups > 1 && max_rounds >= 1) {
+    // round 1 on its own: nodes whose input domains or first round make
+    // them infeasible leave at once, and the batch is compacted before the
+    // remaining rounds instead of a batch of rounds later
+    HIP_TRY(launch_round_batch(P, bt, s));
+    HIP_TRY(hipMemcpyAsync(&p->h_done[0], &P.ctrl->done, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           s));
+    HIP_TRY(hipMemcpyAsync(&p->h_done[2], &P.ctrl->active_nodes, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    r = 2;
+    const uint32_t act = p->h_done[2];
+    if (p->h_done[0] == 1) {
+      r = max_rounds + 1;  // every node has finished
+    } else if (act > 0 && (act + kNodeGroup - 1) / kNodeGroup < (uint32_t)bt.groups) {
+      rc = compact_batch(p, bt, slot_node, res, d_lb, d_ub, s);
+      if (rc) return rc;
+      compacted = true;
+      graph = false;
+      if (bt.nodes == 0) r = max_rounds + 1;
+    }
+  }
   int slot = 0;
   bool pending[2] = {false, false};
-  for (int r = 1; r <= max_rounds;) {
+  for (; r <= max_rounds;) {
     const int last = std::min(max_rounds, r + p->batch_rounds - 1);
     if (graph) {
       // one replay: batch_rounds rounds (past the limit they exit at once)
