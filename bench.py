@@ -312,8 +312,11 @@ def main():
         serve = serving(args.serving_scale, args.serving_seconds, args.serving_rate,
                         int(args.serving_budget_gib * (1 << 30)))
 
+    # the CPU baseline leg: the oracle's synchronous rounds on config2 and,
+    # as the paper's own comparison, its sequential Algorithm 1 on config1
     base = cpu_baseline(inst, args.no_cpu_baseline)
-    seq = cpu_seq_compare(args.no_cpu_seq or args.no_cpu_baseline, args.max_rounds)
+    if base is not None:
+        base["sequential_algorithm1"] = cpu_seq_compare(args.no_cpu_seq, args.max_rounds)
 
     out = {
         "metric": METRIC,
@@ -357,7 +360,6 @@ def main():
         "batched": batch,
         "serving": serve,
         "cpu_baseline": base,
-        "cpu_seq": seq,
     }
     print(json.dumps(out), flush=True)
     prob.close()
