@@ -507,9 +507,18 @@ __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkD
     lane_acc_init(L);
     for (int qq = 0; qq < QB; ++qq) {
       const size_t l = (size_t)(rb * QB + qq) * 8 + e;
-      for (int w0 = 0; w0 < W; w0 += 8)
-        node_entries<8>(P, cur, t, on, base + (size_t)w0 * kWave + l, kWave,
-                        W - w0 < 8 ? W - w0 : 8, L);
+      // the chunk's step count W is the same in every lane: short chunks
+      // (most rows have a few entries) take a narrower body, so no wave
+      // issues loads and gathers for steps it does not have
+      if (W <= 2) {
+        node_entries<2>(P, cur, t, on, base + l, kWave, W, L);
+      } else if (W <= 4) {
+        node_entries<4>(P, cur, t, on, base + l, kWave, W, L);
+      } else {
+        for (int w0 = 0; w0 < W; w0 += 8)
+          node_entries<8>(P, cur, t, on, base + (size_t)w0 * kWave + l, kWave,
+                          W - w0 < 8 ? W - w0 : 8, L);
+      }
     }
     slot_reduce(L, klog > 3 ? 3 : klog);
     if (r >= nrows || !on) continue;
