@@ -407,24 +407,24 @@ __device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const do
 // are the block's slots, summed in the single-run order); rows of K >= 16
 // lanes span K / 8 blocks, whose entries each slot sums one after another.
 //
-// Instead of one code per entry, a lane keeps the largest skip code of its
-// entries per side (and whether it holds the entry that owns the side's
-// only infinite contribution): "slack >= largest code" skips every entry of
-// the lane, so only lanes with an entry that may count revisit their
-// entries, with the exact test.
+// Instead of one code per entry, a lane keeps the largest skip threshold of
+// its entries per side (and whether it holds the entry that owns the side's
+// only infinite contribution): "slack > largest threshold" skips every
+// entry of the lane, exactly as the per-entry test would, so only lanes
+// with an entry that may count revisit their entries, with the exact test.
 // ---------------------------------------------------------------------------
 struct LaneAcc {
   DD smin, smax;
   int cmin, cmax;
-  float amin, amax;  // largest finite skip code per side
-  bool omin, omax;   // holds the owner of the side's infinite contribution
+  double tmin, tmax;  // largest skip threshold per side (side_threshold)
+  bool omin, omax;    // holds the owner of the side's infinite contribution
 };
 
 __device__ __forceinline__ void lane_acc_init(LaneAcc& L) {
   L.smin = {0.0, 0.0};
   L.smax = {0.0, 0.0};
   L.cmin = L.cmax = 0;
-  L.amin = L.amax = -__builtin_inff();
+  L.tmin = L.tmax = -__builtin_inf();
   L.omin = L.omax = false;
 }
 
@@ -450,12 +450,16 @@ __device__ __forceinline__ void node_entries(const Problem& P, const double2* __
   for (int k = 0; k < N; ++k) {
     if (k < count && on && av[k] != 0.0) {
       accumulate(av[k], bv[k].x, bv[k].y, L.smin, L.smax, L.cmin, L.cmax);
-      float c1, c2;
-      entry_codes(av[k], bv[k].x, bv[k].y, cv[k], P.cont_rel_tol, c1, c2);
-      if (__builtin_isnan(c1)) L.omin = true;
-      else L.amin = c1 > L.amin ? c1 : L.amin;
-      if (__builtin_isnan(c2)) L.omax = true;
-      else L.amax = c2 > L.amax ? c2 : L.amax;
+      // the lane keeps thresholds, not fp32 codes: only their maximum is
+      // needed.  An owner of an infinite contribution only occurs in rows
+      // with such a contribution, where the maximum is not consulted.
+      const bool is_int = cv[k] < 0, pos = av[k] > 0.0;
+      const double t1 = side_threshold(av[k], bv[k].x, bv[k].y, is_int, pos, P.cont_rel_tol);
+      const double t2 = side_threshold(av[k], bv[k].x, bv[k].y, is_int, !pos, P.cont_rel_tol);
+      L.tmin = t1 > L.tmin ? t1 : L.tmin;
+      L.tmax = t2 > L.tmax ? t2 : L.tmax;
+      L.omin |= is_inf(pos ? bv[k].x : bv[k].y);
+      L.omax |= is_inf(pos ? bv[k].y : bv[k].x);
     }
   }
 }
@@ -482,8 +486,8 @@ __device__ __forceinline__ void slot_reduce(LaneAcc& L, int levels) {
 
 __device__ __forceinline__ bool lane_may_pass(const RowState& R, const LaneAcc& L) {
   bool p = false;
-  if (R.min_side) p |= R.cmin == 0 ? !(R.smn >= (double)L.amin) : L.omin;
-  if (R.max_side) p |= R.cmax == 0 ? !((-R.smx) >= (double)L.amax) : L.omax;
+  if (R.min_side) p |= R.cmin == 0 ? !(R.smn > L.tmin) : L.omin;
+  if (R.max_side) p |= R.cmax == 0 ? !((-R.smx) > L.tmax) : L.omax;
   return p;
 }
 
