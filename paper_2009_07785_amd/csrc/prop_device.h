@@ -531,13 +531,25 @@ __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkD
     if (!lane_may_pass(R, L)) continue;
     for (int qq = 0; qq < QB; ++qq) {
       const size_t l = (size_t)(rb * QB + qq) * 8 + e;
-      for (int w = 0; w < W; ++w) {
-        const size_t idx = base + (size_t)w * kWave + l;
-        const double a = P.vals[idx];
-        if (a == 0.0) continue;
-        const int32_t cw = P.cols[idx];
-        const double2 b = cur[(size_t)(cw & kColMask) * kNodeGroup + t];
-        entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, kNodeGroup, false);
+      // four entries at a time: loads, then gathers, then the exact tests
+      // (two memory round trips per four entries instead of three each)
+      for (int w0 = 0; w0 < W; w0 += 4) {
+        const int cnt = W - w0 < 4 ? W - w0 : 4;
+        double av[4];
+        int32_t cv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const size_t idx = base + (size_t)(w0 + (k < cnt ? k : cnt - 1)) * kWave + l;
+          av[k] = P.vals[idx];
+          cv[k] = P.cols[idx];
+        }
+        double2 bv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bv[k] = cur[(size_t)(cv[k] & kColMask) * kNodeGroup + t];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (k < cnt && av[k] != 0.0)
+            entry_candidates(P, R, av[k], bv[k].x, bv[k].y, cv[k], nxt + t, kNodeGroup, false);
       }
     }
   }
