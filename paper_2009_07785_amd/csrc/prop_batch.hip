@@ -28,6 +28,17 @@ __device__ __forceinline__ uint32_t group_mask(const Batch& Bt, int g) {
   return mask;
 }
 
+// Nodes of group g whose rows all take the exact sums (a tiny bound).
+__device__ __forceinline__ uint32_t group_exact(const Batch& Bt, int g) {
+  uint32_t mask = 0;
+#pragma unroll
+  for (int t = 0; t < kNodeGroup; ++t) {
+    const int k = g * kNodeGroup + t;
+    if (k < Bt.nodes && Bt.tiny[k]) mask |= 1u << t;
+  }
+  return mask;
+}
+
 // Packs nodes [k0, k0 + cnt) from node-major arrays (row q = node k0 + q).
 __global__ __launch_bounds__(kBlock) void k_pack_batch(Problem P, Batch Bt,
                                                        const double* __restrict__ ulb,
@@ -57,6 +68,8 @@ __global__ __launch_bounds__(kBlock) void k_pack_batch(Problem P, Batch Bt,
     const double2 b = make_double2(l, u);
     Bt.gA[k / kNodeGroup][dst] = b;
     Bt.gB[k / kNodeGroup][dst] = b;
+    if (tiny_bound(l) || tiny_bound(u))
+      __hip_atomic_store(&Bt.tiny[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (domain_empty(is_int, l, u, P.feas_tol))
       __hip_atomic_store(&Bt.infeasible[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -111,6 +124,8 @@ __global__ __launch_bounds__(kBlock) void k_move_batch(Problem P, Batch Bt,
     Bt.status[d] = Bt.status[s];
     Bt.rounds[d] = Bt.rounds[s];
     Bt.maxr[d] = Bt.maxr[s];
+    Bt.tiny[d] = Bt.tiny[s];
+    Bt.tiny[s] = 0;
     Bt.changed[d] = 0;
     Bt.infeasible[d] = 0;
     Bt.invalid[d] = 0;
@@ -160,6 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_start_batch(Problem P, Batch Bt, int
     Bt.rounds[k] = 0;
     Bt.maxr[k] = max_rounds;
     Bt.active[k] = a;
+    if (!a) Bt.tiny[k] = 0;
     Bt.changed[k] = 0;
     Bt.infeasible[k] = 0;
     Bt.invalid[k] = 0;
@@ -180,6 +196,7 @@ __device__ __forceinline__ void round_unit(const Problem& P, const Batch& Bt, in
   // with few active nodes, node-parallel lanes would mostly idle: loop over
   // the active nodes with the single-run shape instead
   const bool few = __builtin_popcount(mask) <= kLoopNodes;
+  const uint32_t exact = group_exact(Bt, g);
   if (unit < P.n_segs) {
     if (few)
       seg_phase1(P, unit, Bt.gA[g], kNodeGroup, mask, Bt.partials, Bt.nodes, g * kNodeGroup);
@@ -187,9 +204,9 @@ __device__ __forceinline__ void round_unit(const Problem& P, const Batch& Bt, in
       seg_phase1_nodes(P, unit, Bt.gA[g], mask, Bt.partials, Bt.nodes, g * kNodeGroup);
   } else {
     if (few)
-      chunk_dispatch(P, unit - P.n_segs, Bt.gA[g], Bt.gB[g], kNodeGroup, mask);
+      chunk_dispatch(P, unit - P.n_segs, Bt.gA[g], Bt.gB[g], kNodeGroup, mask, exact);
     else
-      chunk_round_nodes(P, P.chunks[unit - P.n_segs], Bt.gA[g], Bt.gB[g], mask);
+      chunk_round_nodes(P, P.chunks[unit - P.n_segs], Bt.gA[g], Bt.gB[g], mask, exact);
   }
 }
 
@@ -197,7 +214,8 @@ __device__ __forceinline__ void round_unit(const Problem& P, const Batch& Bt, in
 __device__ __forceinline__ void long_unit(const Problem& P, const Batch& Bt, int s, int k) {
   if (s >= P.n_segs || !Bt.active[k]) return;
   const int g = k / kNodeGroup;
-  seg_phase2<true>(P, s, Bt.gA[g], Bt.gB[g], kNodeGroup, k % kNodeGroup, Bt.partials, Bt.nodes, k);
+  seg_phase2<true>(P, s, Bt.gA[g], Bt.gB[g], kNodeGroup, k % kNodeGroup, Bt.partials, Bt.nodes, k,
+                   Bt.tiny[k] != 0);
 }
 
 // Block bx of nbx over group g's (variable, node) pairs: copy changed pairs
@@ -223,6 +241,9 @@ __device__ __forceinline__ void commit_part(const Problem& P, const Batch& Bt, i
       if (a.x != b.x || a.y != b.y) {
         A[e] = b;
         atomicAdd(&ch[t], 1u);
+        if (tiny_bound(b.x) || tiny_bound(b.y))
+          __hip_atomic_store(&Bt.tiny[g * kNodeGroup + t], 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
         if (domain_empty(P.vtype[e / kNodeGroup] != 0, b.x, b.y, P.feas_tol)) inf[t] = 1;
       }
     }
@@ -279,6 +300,7 @@ __device__ __forceinline__ void end_slots(const Problem& P, const Batch& Bt, Srv
     Bt.active[k] = a;
     Bt.changed[k] = 0;
     Bt.infeasible[k] = 0;
+    if (!a) Bt.tiny[k] = 0;
     act += a;
     if (S && !a) report_slot(Bt, S, inst, k);
   }

@@ -8,9 +8,11 @@
 // Bounds live in two arrays of (lb, ub) pairs: A holds the bounds as they
 // stood at the start of the round and is only read during it; B starts
 // equal to A and receives the candidates.  One round:
-//   1. every row's min / max activity from A: finite parts as exact-product
-//      double-double sums (rounded once at the end), plus the counts of
-//      infinite contributions (Definition 1; Sec. 3.4);
+//   1. every row's min / max activity from A: finite parts as the exact sum
+//      of the products rounded once (prop_sum.h: a double-double with an
+//      exact error bound, and a fixed-point sum for the rows that bound
+//      cannot certify), plus the counts of infinite contributions
+//      (Definition 1; Sec. 3.4);
 //   2. per entry the candidates of Step 3 (eqs. bound_candidates_pos / _neg),
 //      rounded inward for integer variables, each one IEEE operation in the
 //      order (beta - activity) / a + bound;
@@ -45,6 +47,7 @@
 #include <hip/hip_runtime.h>
 
 #include "prop_layout.h"
+#include "prop_sum.h"
 
 #pragma clang fp contract(off)
 
@@ -54,40 +57,11 @@ namespace prop {
 #define PROP_SKIP_MARGIN (1.0 + 0x1p-39)
 #define PROP_SKIP_FLOOR 0x1p-900
 
-// ---------------------------------------------------------------------------
-// exact-product double-double accumulation
-// ---------------------------------------------------------------------------
-struct DD {
-  double hi, lo;
-};
-
-// s += a * b: the product is split exactly into p + ep (FMA), p is added to
-// s.hi with an error-free two-sum, and both error terms go to s.lo.
-__device__ __forceinline__ void dd_add_prod(DD& s, double a, double b) {
-  double p = a * b;
-  double ep = __builtin_fma(a, b, -p);
-  double t = s.hi + p;
-  double z = t - s.hi;
-  double e = (s.hi - (t - z)) + (p - z);
-  s.hi = t;
-  s.lo = s.lo + (e + ep);
-}
-
-// s += (yhi, ylo); symmetric in its two operands, so both lanes of a
-// butterfly exchange end with identical bits.
-__device__ __forceinline__ void dd_add(DD& s, double yhi, double ylo) {
-  double t = s.hi + yhi;
-  double z = t - s.hi;
-  double e = (s.hi - (t - z)) + (yhi - z);
-  s.hi = t;
-  s.lo = (s.lo + ylo) + e;
-}
-
-__device__ __forceinline__ double dd_value(const DD& s) { return (s.hi + s.lo) + 0.0; }
-
 // Combines the partial sums of the 2^klog lanes of each row (klog is the
-// same in every lane of the wave, so the branches are uniform).
-__device__ __forceinline__ void group_reduce(DD& smin, DD& smax, int& cmin, int& cmax, int klog) {
+// same in every lane of the wave, so the branches are uniform); err is the
+// lanes' shared error bound of both sums (see prop_sum.h).
+__device__ __forceinline__ void group_reduce(DD& smin, DD& smax, double& err, int& cmin,
+                                             int& cmax, int klog) {
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     if (i >= klog) break;
@@ -96,12 +70,13 @@ __device__ __forceinline__ void group_reduce(DD& smin, DD& smax, int& cmin, int&
     double b = __shfl_xor(smin.lo, off, kWave);
     double c = __shfl_xor(smax.hi, off, kWave);
     double d = __shfl_xor(smax.lo, off, kWave);
-    int e = __shfl_xor(cmin, off, kWave);
-    int f = __shfl_xor(cmax, off, kWave);
-    dd_add(smin, a, b);
-    dd_add(smax, c, d);
-    cmin += e;
-    cmax += f;
+    double f = __shfl_xor(err, off, kWave);
+    int g = __shfl_xor(cmin, off, kWave);
+    int h = __shfl_xor(cmax, off, kWave);
+    dd_add(smin, err, a, b, f);
+    dd_add(smax, err, c, d, 0.0);
+    cmin += g;
+    cmax += h;
   }
 }
 
@@ -109,15 +84,15 @@ __device__ __forceinline__ bool is_inf(double x) { return __builtin_isinf(x); }
 
 // Contribution of one entry to both activities.
 __device__ __forceinline__ void accumulate(double a, double l, double u, DD& smin, DD& smax,
-                                           int& cmin, int& cmax) {
+                                           int& cmin, int& cmax, double& err) {
   const double bmin = a > 0.0 ? l : u;
   const double bmax = a > 0.0 ? u : l;
   const bool imin = is_inf(bmin);
   const bool imax = is_inf(bmax);
   cmin += (a != 0.0 && imin) ? 1 : 0;
   cmax += (a != 0.0 && imax) ? 1 : 0;
-  dd_add_prod(smin, a, imin ? 0.0 : bmin);
-  dd_add_prod(smax, a, imax ? 0.0 : bmax);
+  dd_add_prod(smin, a, imin ? 0.0 : bmin, err);
+  dd_add_prod(smax, a, imax ? 0.0 : bmax, err);
 }
 
 // Skip threshold of one side of an entry: the candidate that side yields
@@ -169,22 +144,105 @@ struct RowState {
   double minfin, maxfin;
   int cmin, cmax;
   bool min_side, max_side;  // the rhs / lhs side can yield candidates
+  bool uncertain;           // a side in use needs the exact path
   double smn;               // rhs - min activity
   double smx;               // lhs - max activity
 };
 
-__device__ __forceinline__ RowState make_row_state(const DD& smin, const DD& smax, int cmin,
-                                                   int cmax, double lhs, double rhs) {
+// Row state from the reduced double-doubles; `force` sends the row to the
+// exact path whatever the certification says (a tiny bound is in play).
+__device__ __forceinline__ RowState make_row_state(const DD& smin, const DD& smax, double err,
+                                                   int cmin, int cmax, double lhs, double rhs,
+                                                   bool force) {
   RowState R;
-  R.minfin = dd_value(smin);
-  R.maxfin = dd_value(smax);
+  const bool okmin = dd_round(smin.hi, smin.lo, err, R.minfin);
+  const bool okmax = dd_round(smax.hi, smax.lo, err, R.maxfin);
   R.cmin = cmin;
   R.cmax = cmax;
   R.min_side = (rhs < __builtin_inf()) && cmin <= 1;
   R.max_side = (lhs > -__builtin_inf()) && cmax <= 1;
+  R.uncertain = force || (R.min_side && !okmin) || (R.max_side && !okmax);
   R.smn = rhs - R.minfin;
   R.smx = lhs - R.maxfin;
   return R;
+}
+
+__device__ __forceinline__ void set_exact(RowState& R, double mn, double mx, double lhs,
+                                          double rhs) {
+  R.minfin = mn;
+  R.maxfin = mx;
+  R.smn = rhs - mn;
+  R.smx = lhs - mx;
+  R.uncertain = false;
+}
+
+// ---------------------------------------------------------------------------
+// exact path (rows the fast sums cannot certify; see prop_sum.h)
+//
+// The lanes holding the row's entries add their exact products into two
+// digit arrays in LDS (min and max activity) with 64-bit integer atomics,
+// and one lane rounds them.  The wave runs it for one row at a time; its
+// other lanes wait.  Rows get here when their double-double sum lies within
+// its error bound of a rounding boundary, so this path is rare.
+// ---------------------------------------------------------------------------
+struct ExactScratch {
+  int64_t w[2][kAccDigits];
+  double out[2];
+};
+
+__device__ __forceinline__ ExactScratch& exact_scratch() {
+  __shared__ ExactScratch sc[kWavesPerBlock];
+  return sc[threadIdx.x >> 6];
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void exact_clear(ExactScratch& X) {
+  const int lane = threadIdx.x & (kWave - 1);
+  if (lane < kAccDigits) {
+    X.w[0][lane] = 0;
+    X.w[1][lane] = 0;
+  }
+  wave_sync();
+}
+
+__device__ __forceinline__ void lds_add_product(int64_t* W, double a, double b) {
+  int d;
+  uint32_t c[5];
+  bool neg;
+  if (!product_digits(a, b, d, c, neg)) return;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+    if (c[i])
+      atomicAdd(reinterpret_cast<unsigned long long*>(&W[d + i]),
+                neg ? (unsigned long long)(-(int64_t)c[i]) : (unsigned long long)c[i]);
+}
+
+// One entry's exact products into both digit arrays (infinite bounds are
+// counted elsewhere and contribute no finite part).
+__device__ __forceinline__ void exact_entry(ExactScratch& X, double a, double l, double u) {
+  if (a == 0.0) return;
+  const double bmin = a > 0.0 ? l : u;
+  const double bmax = a > 0.0 ? u : l;
+  if (!is_inf(bmin)) lds_add_product(X.w[0], a, bmin);
+  if (!is_inf(bmax)) lds_add_product(X.w[1], a, bmax);
+}
+
+// After every lane has added: `leader` rounds both sums; every lane gets them.
+__device__ __forceinline__ void exact_finish(ExactScratch& X, bool leader, double& mn,
+                                             double& mx) {
+  wave_sync();
+  if (leader) {
+    X.out[0] = digits_round(X.w[0]);
+    X.out[1] = digits_round(X.w[1]);
+  }
+  wave_sync();
+  mn = X.out[0];
+  mx = X.out[1];
+  wave_sync();
 }
 
 // Which sides of entry (a, column word cw; start-of-round l, u) need the
@@ -329,15 +387,55 @@ __device__ __forceinline__ bool entry_passes(const RowState& R, float emin, floa
 // line with a plain sparse product.  In a batch, nodes after the first find
 // the chunk's matrix data in cache.
 // ---------------------------------------------------------------------------
+// Exact path for row rr of a chunk (lanes rr * K .. rr * K + K - 1) and
+// node t: the exactly rounded activities replace the row state of those
+// lanes, which then run the candidates of their entries.
+__device__ __forceinline__ void exact_chunk_row(const Problem& P, const ChunkDesc cd, int rr,
+                                                const double2* __restrict__ cur,
+                                                double2* __restrict__ nxt, uint32_t stride,
+                                                uint32_t t, RowState& R, double lhs,
+                                                double rhs) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int klog = cd.meta & 7;
+  const int W = (cd.meta >> 8) & 0xff;
+  const size_t base = (size_t)cd.off64 * kWave + lane;
+  const bool mine = (lane >> klog) == rr;
+  ExactScratch& X = exact_scratch();
+  exact_clear(X);
+  if (mine) {
+    for (int w = 0; w < W; ++w) {
+      const size_t e = base + (size_t)w * kWave;
+      const double a = P.vals[e];
+      if (a == 0.0) continue;
+      const double2 b = cur[(size_t)(P.cols[e] & kColMask) * stride + t];
+      exact_entry(X, a, b.x, b.y);
+    }
+  }
+  double mn, mx;
+  exact_finish(X, lane == (rr << klog), mn, mx);
+  if (!mine) return;
+  set_exact(R, mn, mx, lhs, rhs);
+  if (!(R.min_side || R.max_side)) return;
+  for (int w = 0; w < W; ++w) {
+    const size_t e = base + (size_t)w * kWave;
+    const double a = P.vals[e];
+    if (a == 0.0) continue;
+    const int32_t cw = P.cols[e];
+    const double2 b = cur[(size_t)(cw & kColMask) * stride + t];
+    entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride, stride == 1);
+  }
+}
+
 // With `marked` (single runs in marked rounds), rows not stamped with round
 // r are skipped: none of their variables changed in the previous round, so
 // their activities and candidates are those of that round, which changed
-// nothing.
+// nothing.  Bit t of `exact_mask` sends every row of node t to the exact
+// path (a tiny bound is in play).
 __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd,
                                             const double2* __restrict__ cur,
                                             double2* __restrict__ nxt, uint32_t stride,
-                                            uint32_t node_mask, bool marked = false,
-                                            int r_round = 0) {
+                                            uint32_t node_mask, uint32_t exact_mask,
+                                            bool marked = false, int r_round = 0) {
   const int lane = threadIdx.x & (kWave - 1);
   const int klog = cd.meta & 7;
   const int W = (cd.meta >> 8) & 0xff;
@@ -353,6 +451,7 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
     const uint32_t t = __builtin_ctz(mask);
     float emin[kMaxSteps], emax[kMaxSteps];
     DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
+    double err = 0.0;
     int cmin = 0, cmax = 0;
 #pragma unroll
     for (int w = 0; w < kMaxSteps; ++w) {
@@ -365,34 +464,42 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
         const int32_t cw = stride == 1 ? __builtin_nontemporal_load(P.cols + e) : P.cols[e];
         if (a != 0.0) {
           const double2 b = cur[(size_t)(cw & kColMask) * stride + t];
-          accumulate(a, b.x, b.y, smin, smax, cmin, cmax);
+          accumulate(a, b.x, b.y, smin, smax, cmin, cmax, err);
           entry_codes(a, b.x, b.y, cw, P.cont_rel_tol, emin[w], emax[w]);
         }
       }
     }
-    group_reduce(smin, smax, cmin, cmax, klog);
-    if (!row_ok || !want) continue;
-    const RowState R = make_row_state(smin, smax, cmin, cmax, lhs, rhs);
-    if (!(R.min_side || R.max_side)) continue;
-    // a step no lane needs is skipped by the wave
+    group_reduce(smin, smax, err, cmin, cmax, klog);
+    RowState R = make_row_state(smin, smax, err, cmin, cmax, lhs, rhs, (exact_mask >> t) & 1u);
+    const bool live = row_ok && want;
+    if (live && !R.uncertain && (R.min_side || R.max_side)) {
+      // a step no lane needs is skipped by the wave
 #pragma unroll
-    for (int w = 0; w < kMaxSteps; ++w) {
-      if (w < W && entry_passes(R, emin[w], emax[w])) {
-        const size_t e = base + (size_t)w * kWave;
-        const double a = P.vals[e];
-        const int32_t cw = P.cols[e];
-        const double2 b = cur[(size_t)(cw & kColMask) * stride + t];
-        entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride, stride == 1);
+      for (int w = 0; w < kMaxSteps; ++w) {
+        if (w < W && entry_passes(R, emin[w], emax[w])) {
+          const size_t e = base + (size_t)w * kWave;
+          const double a = P.vals[e];
+          const int32_t cw = P.cols[e];
+          const double2 b = cur[(size_t)(cw & kColMask) * stride + t];
+          entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride, stride == 1);
+        }
       }
+    }
+    // rows the fast sums cannot certify, one at a time with the whole wave
+    // (after the loop above, so the skip codes are no longer held)
+    uint64_t need = __ballot(live && R.uncertain && (lane & ((1 << klog) - 1)) == 0);
+    while (need) {
+      exact_chunk_row(P, cd, __builtin_ctzll(need) >> klog, cur, nxt, stride, t, R, lhs, rhs);
+      need &= need - 1;
     }
   }
 }
 
 __device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const double2* cur,
                                                double2* nxt, uint32_t stride,
-                                               uint32_t node_mask, bool marked = false,
-                                               int r_round = 0) {
-  chunk_round(P, P.chunks[c], cur, nxt, stride, node_mask, marked, r_round);
+                                               uint32_t node_mask, uint32_t exact_mask,
+                                               bool marked = false, int r_round = 0) {
+  chunk_round(P, P.chunks[c], cur, nxt, stride, node_mask, exact_mask, marked, r_round);
 }
 
 // ---------------------------------------------------------------------------
@@ -415,6 +522,7 @@ __device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const do
 // ---------------------------------------------------------------------------
 struct LaneAcc {
   DD smin, smax;
+  double err;         // error bound of both sums (prop_sum.h)
   int cmin, cmax;
   double tmin, tmax;  // largest skip threshold per side (side_threshold)
   bool omin, omax;    // holds the owner of the side's infinite contribution
@@ -423,6 +531,7 @@ struct LaneAcc {
 __device__ __forceinline__ void lane_acc_init(LaneAcc& L) {
   L.smin = {0.0, 0.0};
   L.smax = {0.0, 0.0};
+  L.err = 0.0;
   L.cmin = L.cmax = 0;
   L.tmin = L.tmax = -__builtin_inf();
   L.omin = L.omax = false;
@@ -449,7 +558,7 @@ __device__ __forceinline__ void node_entries(const Problem& P, const double2* __
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     if (k < count && on && av[k] != 0.0) {
-      accumulate(av[k], bv[k].x, bv[k].y, L.smin, L.smax, L.cmin, L.cmax);
+      accumulate(av[k], bv[k].x, bv[k].y, L.smin, L.smax, L.cmin, L.cmax, L.err);
       // the lane keeps thresholds, not fp32 codes: only their maximum is
       // needed.  An owner of an infinite contribution only occurs in rows
       // with such a contribution, where the maximum is not consulted.
@@ -475,12 +584,13 @@ __device__ __forceinline__ void slot_reduce(LaneAcc& L, int levels) {
     double b = __shfl_xor(L.smin.lo, off, kWave);
     double c = __shfl_xor(L.smax.hi, off, kWave);
     double d = __shfl_xor(L.smax.lo, off, kWave);
-    int e = __shfl_xor(L.cmin, off, kWave);
-    int f = __shfl_xor(L.cmax, off, kWave);
-    dd_add(L.smin, a, b);
-    dd_add(L.smax, c, d);
-    L.cmin += e;
-    L.cmax += f;
+    double f = __shfl_xor(L.err, off, kWave);
+    int g = __shfl_xor(L.cmin, off, kWave);
+    int h = __shfl_xor(L.cmax, off, kWave);
+    dd_add(L.smin, L.err, a, b, f);
+    dd_add(L.smax, L.err, c, d, 0.0);
+    L.cmin += g;
+    L.cmax += h;
   }
 }
 
@@ -491,9 +601,58 @@ __device__ __forceinline__ bool lane_may_pass(const RowState& R, const LaneAcc& 
   return p;
 }
 
+// Exact path for one (row, node) of node-parallel lanes: row block rb,
+// node t0, entry slot e0 of the leading lane.  The pair's lanes get the
+// exactly rounded activities and run the candidates of their entries.
+__device__ __forceinline__ void exact_nodes_row(const Problem& P, const ChunkDesc cd, int rb,
+                                                uint32_t t0, int e0,
+                                                const double2* __restrict__ cur,
+                                                double2* __restrict__ nxt, RowState& R,
+                                                double lhs, double rhs) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t t = lane & (kNodeGroup - 1);
+  const int e = lane >> 3;
+  const int klog = cd.meta & 7;
+  const int W = (cd.meta >> 8) & 0xff;
+  const int QB = klog > 3 ? 1 << (klog - 3) : 1;
+  const size_t base = (size_t)cd.off64 * kWave;
+  ExactScratch& X = exact_scratch();
+  exact_clear(X);
+  const bool mine = t == t0 && (klog > 3 || (e >> klog) == (e0 >> klog));
+  if (mine) {
+    for (int qq = 0; qq < QB; ++qq) {
+      const size_t l = (size_t)(rb * QB + qq) * 8 + e;
+      for (int w = 0; w < W; ++w) {
+        const size_t idx = base + (size_t)w * kWave + l;
+        const double a = P.vals[idx];
+        if (a == 0.0) continue;
+        const double2 b = cur[(size_t)(P.cols[idx] & kColMask) * kNodeGroup + t];
+        exact_entry(X, a, b.x, b.y);
+      }
+    }
+  }
+  double mn, mx;
+  exact_finish(X, lane == e0 * 8 + (int)t0, mn, mx);
+  if (!mine) return;
+  set_exact(R, mn, mx, lhs, rhs);
+  if (!(R.min_side || R.max_side)) return;
+  for (int qq = 0; qq < QB; ++qq) {
+    const size_t l = (size_t)(rb * QB + qq) * 8 + e;
+    for (int w = 0; w < W; ++w) {
+      const size_t idx = base + (size_t)w * kWave + l;
+      const double a = P.vals[idx];
+      if (a == 0.0) continue;
+      const int32_t cw = P.cols[idx];
+      const double2 b = cur[(size_t)(cw & kColMask) * kNodeGroup + t];
+      entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, kNodeGroup, false);
+    }
+  }
+}
+
 __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkDesc cd,
                                                   const double2* __restrict__ cur,
-                                                  double2* __restrict__ nxt, uint32_t node_mask) {
+                                                  double2* __restrict__ nxt, uint32_t node_mask,
+                                                  uint32_t exact_mask) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t t = lane & (kNodeGroup - 1);
   const int e = lane >> 3;
@@ -525,32 +684,44 @@ __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkD
       }
     }
     slot_reduce(L, klog > 3 ? 3 : klog);
-    if (r >= nrows || !on) continue;
-    const int row = cd.row0 + r;
-    const RowState R = make_row_state(L.smin, L.smax, L.cmin, L.cmax, P.lhs[row], P.rhs[row]);
-    if (!lane_may_pass(R, L)) continue;
-    for (int qq = 0; qq < QB; ++qq) {
-      const size_t l = (size_t)(rb * QB + qq) * 8 + e;
-      // four entries at a time: loads, then gathers, then the exact tests
-      // (two memory round trips per four entries instead of three each)
-      for (int w0 = 0; w0 < W; w0 += 4) {
-        const int cnt = W - w0 < 4 ? W - w0 : 4;
-        double av[4];
-        int32_t cv[4];
+    const bool live = r < nrows && on;
+    const int row = cd.row0 + (r < nrows ? r : 0);
+    const double lhs = P.lhs[row], rhs = P.rhs[row];
+    RowState R = make_row_state(L.smin, L.smax, L.err, L.cmin, L.cmax, lhs, rhs,
+                                (exact_mask >> t) & 1u);
+    if (live && !R.uncertain && lane_may_pass(R, L)) {
+      for (int qq = 0; qq < QB; ++qq) {
+        const size_t l = (size_t)(rb * QB + qq) * 8 + e;
+        // four entries at a time: loads, then gathers, then the exact tests
+        // (two memory round trips per four entries instead of three each)
+        for (int w0 = 0; w0 < W; w0 += 4) {
+          const int cnt = W - w0 < 4 ? W - w0 : 4;
+          double av[4];
+          int32_t cv[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const size_t idx = base + (size_t)(w0 + (k < cnt ? k : cnt - 1)) * kWave + l;
-          av[k] = P.vals[idx];
-          cv[k] = P.cols[idx];
+          for (int k = 0; k < 4; ++k) {
+            const size_t idx = base + (size_t)(w0 + (k < cnt ? k : cnt - 1)) * kWave + l;
+            av[k] = P.vals[idx];
+            cv[k] = P.cols[idx];
+          }
+          double2 bv[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) bv[k] = cur[(size_t)(cv[k] & kColMask) * kNodeGroup + t];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (k < cnt && av[k] != 0.0)
+              entry_candidates(P, R, av[k], bv[k].x, bv[k].y, cv[k], nxt + t, kNodeGroup, false);
         }
-        double2 bv[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) bv[k] = cur[(size_t)(cv[k] & kColMask) * kNodeGroup + t];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (k < cnt && av[k] != 0.0)
-            entry_candidates(P, R, av[k], bv[k].x, bv[k].y, cv[k], nxt + t, kNodeGroup, false);
       }
+    }
+    // (row, node) pairs the fast sums cannot certify, one at a time with the
+    // whole wave, led by the row's first entry slot
+    const bool lead = klog > 3 ? e == 0 : (e & ((1 << klog) - 1)) == 0;
+    uint64_t need = __ballot(live && lead && R.uncertain);
+    while (need) {
+      const int ll = __builtin_ctzll(need);
+      exact_nodes_row(P, cd, rb, ll & (kNodeGroup - 1), ll >> 3, cur, nxt, R, lhs, rhs);
+      need &= need - 1;
     }
   }
 }
@@ -581,13 +752,14 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
   for (uint32_t mask = node_mask; mask; mask &= mask - 1) {
     const uint32_t t = __builtin_ctz(mask);
     DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
+    double err = 0.0;
     int cmin = 0, cmax = 0;
     double tmin = -0x1p-1074, tmax = -0x1p-1074;  // per-side skip thresholds
 #pragma unroll
     for (int w = 0; w < kMaxSteps; ++w) {
       if (a[w] != 0.0) {
         const double2 b = cur[(size_t)(jj[w] & kColMask) * stride + t];
-        accumulate(a[w], b.x, b.y, smin, smax, cmin, cmax);
+        accumulate(a[w], b.x, b.y, smin, smax, cmin, cmax, err);
         const bool is_int = jj[w] < 0, pos = a[w] > 0.0;
         const double t1 = side_threshold(a[w], b.x, b.y, is_int, pos, P.cont_rel_tol);
         const double t2 = side_threshold(a[w], b.x, b.y, is_int, !pos, P.cont_rel_tol);
@@ -595,7 +767,7 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
         tmax = t2 > tmax ? t2 : tmax;
       }
     }
-    group_reduce(smin, smax, cmin, cmax, 6);
+    group_reduce(smin, smax, err, cmin, cmax, 6);
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
       const double o1 = __shfl_xor(tmin, off, kWave);
@@ -613,7 +785,7 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
       q.tmax = tmax;
       q.min_inf = cmin;
       q.max_inf = cmax;
-      q.pad0 = q.pad1 = 0;
+      q.err = err;
       parts[(size_t)s * pstride + node0 + t] = q;
     }
   }
@@ -652,7 +824,7 @@ __device__ __forceinline__ void seg_phase1_nodes(const Problem& P, int s,
     for (int k = 0; k < 8; ++k) {
       if (k < count && on && av[k] != 0.0) {
         const double2 b = bv[k];
-        accumulate(av[k], b.x, b.y, L.smin, L.smax, L.cmin, L.cmax);
+        accumulate(av[k], b.x, b.y, L.smin, L.smax, L.cmin, L.cmax, L.err);
         const bool is_int = cv[k] < 0, pos = av[k] > 0.0;
         const double t1 = side_threshold(av[k], b.x, b.y, is_int, pos, P.cont_rel_tol);
         const double t2 = side_threshold(av[k], b.x, b.y, is_int, !pos, P.cont_rel_tol);
@@ -679,7 +851,7 @@ __device__ __forceinline__ void seg_phase1_nodes(const Problem& P, int s,
     q.tmax = tmax;
     q.min_inf = L.cmin;
     q.max_inf = L.cmax;
-    q.pad0 = q.pad1 = 0;
+    q.err = L.err;
     parts[(size_t)s * pstride + node0 + t] = q;
   }
 }
@@ -692,26 +864,55 @@ __device__ __forceinline__ void seg_phase1_nodes(const Problem& P, int s,
 // segment's end gather variable 0's pair and are skipped like padding.
 constexpr int kSegBatch = 4;
 
+// Exact path of a long row for node t: the wave sums all of the row's
+// entries (its segments are stored one after another).
+__device__ __forceinline__ void exact_long_row(const Problem& P, const SegDesc sd,
+                                            const double2* __restrict__ cur, uint32_t stride,
+                                            uint32_t t, double& mn, double& mx) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t start = P.segs[sd.first].off;
+  const int64_t len = (int64_t)(sd.nseg - 1) * kSegLen + P.segs[sd.first + sd.nseg - 1].len;
+  ExactScratch& X = exact_scratch();
+  exact_clear(X);
+  for (int64_t p = lane; p < len; p += kWave) {
+    const double a = P.vals[start + p];
+    if (a == 0.0) continue;
+    const double2 b = cur[(size_t)(P.cols[start + p] & kColMask) * stride + t];
+    exact_entry(X, a, b.x, b.y);
+  }
+  exact_finish(X, lane == 0, mn, mx);
+}
+
 template <bool kBatchLoads = false>
 __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
                                            const double2* __restrict__ cur,
                                            double2* __restrict__ nxt, uint32_t stride, uint32_t t,
                                            const SegPartial* parts, uint32_t pstride,
-                                           uint32_t node, bool marked = false, int r_round = 0) {
+                                           uint32_t node, bool force_exact, bool marked = false,
+                                           int r_round = 0) {
   const int lane = threadIdx.x & (kWave - 1);
   const SegDesc sd = P.segs[s];
   if (marked && P.row_mark[sd.row] != r_round) return;
   DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
+  double err = 0.0;
   int cmin = 0, cmax = 0;
   for (int q = lane; q < sd.nseg; q += kWave) {
     const SegPartial pp = parts[(size_t)(sd.first + q) * pstride + node];
-    dd_add(smin, pp.min_hi, pp.min_lo);
-    dd_add(smax, pp.max_hi, pp.max_lo);
+    dd_add(smin, err, pp.min_hi, pp.min_lo, pp.err);
+    dd_add(smax, err, pp.max_hi, pp.max_lo, 0.0);
     cmin += pp.min_inf;
     cmax += pp.max_inf;
   }
-  group_reduce(smin, smax, cmin, cmax, 6);
-  const RowState R = make_row_state(smin, smax, cmin, cmax, P.lhs[sd.row], P.rhs[sd.row]);
+  group_reduce(smin, smax, err, cmin, cmax, 6);
+  const double lhs = P.lhs[sd.row], rhs = P.rhs[sd.row];
+  RowState R = make_row_state(smin, smax, err, cmin, cmax, lhs, rhs, force_exact);
+  if (R.uncertain) {  // the same in every lane after the full-wave reduction
+    // every segment of the row recomputes the exact sums: rare, and no wave
+    // waits on another
+    double mn, mx;
+    exact_long_row(P, sd, cur, stride, t, mn, mx);
+    set_exact(R, mn, mx, lhs, rhs);
+  }
   const SegPartial own = parts[(size_t)s * pstride + node];
   bool need = false;
   if (R.min_side) need |= (R.cmin == 0) ? !(R.smn > own.tmin) : (own.min_inf > 0);
@@ -763,6 +964,8 @@ __device__ __forceinline__ bool commit_one(const Problem& P, uint32_t v, double2
   P.bnd[0][v] = b;
   P.bnd[1][v] = b;
   ++changed;
+  if (tiny_bound(b.x) || tiny_bound(b.y))
+    __hip_atomic_store(&P.ctrl->tiny, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (domain_empty(P.vtype[v] != 0, b.x, b.y, P.feas_tol)) infeasible = 1;
   return true;
 }

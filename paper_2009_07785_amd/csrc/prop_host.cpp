@@ -616,10 +616,12 @@ int ensure_batch(prop_problem* p, int32_t nodes) {
   if ((rc = alloc((void**)&b.infeasible, nodes * sizeof(uint32_t)))) return rc;
   if ((rc = alloc((void**)&b.invalid, nodes * sizeof(uint32_t)))) return rc;
   if ((rc = alloc((void**)&b.maxr, nodes * sizeof(int32_t)))) return rc;
+  if ((rc = alloc((void**)&b.tiny, nodes * sizeof(uint32_t)))) return rc;
   if ((rc = alloc((void**)&p->d_bret, nodes * sizeof(int2)))) return rc;
   if ((rc = alloc((void**)&p->d_bmove, nodes * sizeof(int2)))) return rc;
   HIP_TRY(hipMemset(b.invalid, 0, nodes * sizeof(uint32_t)));
   HIP_TRY(hipMemset(b.infeasible, 0, nodes * sizeof(uint32_t)));
+  HIP_TRY(hipMemset(b.tiny, 0, nodes * sizeof(uint32_t)));
   if (hipHostMalloc((void**)&p->h_bstatus, nodes * sizeof(int32_t), hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc((void**)&p->h_brounds, nodes * sizeof(int32_t), hipHostMallocDefault) !=

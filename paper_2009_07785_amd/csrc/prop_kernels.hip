@@ -28,7 +28,7 @@ __global__ void k_init(Problem P) {
     C->rounds = 0;
     C->done = 0;
     C->round = 1;
-    C->bar_spare = 0;
+    C->tiny = 0;
     C->bar_gen = 0;
     C->abort = 0;
     C->mark_all = 1;
@@ -57,6 +57,8 @@ __global__ __launch_bounds__(kBlock) void k_pack(Problem P, const double* __rest
     const double2 b = make_double2(l, u);
     P.bnd[0][j] = b;
     P.bnd[1][j] = b;
+    if (tiny_bound(l) || tiny_bound(u))
+      __hip_atomic_store(&P.ctrl->tiny, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (domain_empty(is_int, l, u, P.feas_tol))
       __hip_atomic_store(&P.ctrl->infeasible, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -95,12 +97,13 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Problem P, int max_rounds
   if (u32_load(&C->done)) return;
 
   for (int r = 1; r <= max_rounds; ++r) {
-    for (int c = gwave; c < P.n_chunks; c += nwaves) chunk_dispatch(P, c, A, B, 1, 1);
+    const uint32_t exact = u32_load(&C->tiny) ? 1u : 0u;
+    for (int c = gwave; c < P.n_chunks; c += nwaves) chunk_dispatch(P, c, A, B, 1, 1, exact);
     if (P.n_segs) {
       for (int s = gwave; s < P.n_segs; s += nwaves) seg_phase1(P, s, A, 1, 1, P.partials, 1, 0);
       if (!grid_barrier(P, kActNone, r, max_rounds)) return;
       for (int s = gwave; s < P.n_segs; s += nwaves)
-        seg_phase2(P, s, A, B, 1, 0, P.partials, 1, 0);
+        seg_phase2(P, s, A, B, 1, 0, P.partials, 1, 0, exact != 0);
     }
     if (!grid_barrier(P, kActNone, r, max_rounds)) return;
     uint32_t changed = 0, infeasible = 0;
@@ -146,7 +149,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
   const bool marked = marked_round(P);
   if (item < P.n_segs) seg_phase1(P, item, P.bnd[0], 1, 1, P.partials, 1, 0, marked, r);
   else if (item - P.n_segs < P.n_chunks)
-    chunk_dispatch(P, item - P.n_segs, P.bnd[0], P.bnd[1], 1, 1, marked, r);
+    chunk_dispatch(P, item - P.n_segs, P.bnd[0], P.bnd[1], 1, 1,
+                   u32_load(&P.ctrl->tiny) ? 1u : 0u, marked, r);
 }
 
 __global__ __launch_bounds__(kBlock) void k_round_long(Problem P) {
@@ -155,7 +159,8 @@ __global__ __launch_bounds__(kBlock) void k_round_long(Problem P) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int s = blockIdx.x * kWavesPerBlock + wave;
   if (s < P.n_segs)
-    seg_phase2<true>(P, s, P.bnd[0], P.bnd[1], 1, 0, P.partials, 1, 0, marked_round(P), r);
+    seg_phase2<true>(P, s, P.bnd[0], P.bnd[1], 1, 0, P.partials, 1, 0,
+                     u32_load(&P.ctrl->tiny) != 0, marked_round(P), r);
 }
 
 // Marked rounds, after the commit of round r: stamps the rows of every

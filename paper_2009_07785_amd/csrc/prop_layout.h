@@ -76,7 +76,7 @@ struct SegPartial {
   double max_hi, max_lo;   // same for the max activity
   double tmin, tmax;       // largest per-side skip threshold of the segment's entries
   int32_t min_inf, max_inf;
-  int32_t pad0, pad1;
+  double err;              // error bound of both double-doubles (prop_sum.h)
 };
 
 // The commit kernel's blocks report their totals in two levels: into one of
@@ -97,7 +97,7 @@ struct Ctrl {
   int32_t rounds;
   uint32_t done;           // loop finished
   int32_t round;           // next round to run
-  uint32_t bar_spare;      // unused (arrivals are counted in commit_word)
+  uint32_t tiny;           // a bound of this run has 0 < |b| < 2^-906 (exact sums for every row)
   uint32_t bar_gen;        // grid barrier generation
   uint32_t abort;          // barrier wait gave up (device timeout)
   uint32_t mark_all;       // marked rounds: the next round processes every row
@@ -171,6 +171,7 @@ struct Batch {
   uint32_t* invalid;       // [nodes] bound failed validation (cleared by the start kernel)
   int32_t* maxr;           // [nodes] round limit of each node
   uint32_t* live;          // [nodes] serving only (else null): finished, not yet reported
+  uint32_t* tiny;          // [nodes] a bound of the node's run has 0 < |b| < 2^-906
   int32_t nodes;
   int32_t groups;
 };

@@ -559,8 +559,8 @@ int prop_srv_add_instance(prop_server* s, prop_problem* p, int32_t* id) {
   I->cap = s->cfg.max_slots;
   const int32_t cap = I->cap, G8 = cap / kNodeGroup;
   const int32_t segs = p->P.n_segs;
-  // one allocation: 8 per-slot arrays, partials, the two group tables, control
-  const size_t slot_arrays = 8 * (size_t)cap * sizeof(int32_t);
+  // one allocation: 9 per-slot arrays, partials, the two group tables, control
+  const size_t slot_arrays = 9 * (size_t)cap * sizeof(int32_t);
   const size_t part_off = (slot_arrays + 255) & ~(size_t)255;
   const size_t part_bytes = (size_t)(segs > 0 ? segs : 1) * cap * sizeof(SegPartial);
   const size_t table_off = (part_off + part_bytes + 255) & ~(size_t)255;
@@ -594,6 +594,7 @@ int prop_srv_add_instance(prop_server* s, prop_problem* p, int32_t* id) {
   bt.invalid = reinterpret_cast<uint32_t*>(arr + 5 * cap);
   bt.maxr = arr + 6 * cap;
   bt.live = reinterpret_cast<uint32_t*>(arr + 7 * cap);
+  bt.tiny = reinterpret_cast<uint32_t*>(arr + 8 * cap);
   bt.partials = reinterpret_cast<SegPartial*>(base + part_off);
   I->d_table = reinterpret_cast<double2**>(base + table_off);
   bt.gA = I->d_table;

@@ -26,6 +26,7 @@ Workloads (sizes and distributions):
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -424,6 +425,92 @@ def layout_mix(seed: int = 0, copies: int = 3) -> Instance:
     return Instance(f"layout_mix[{seed}]", len(rp) - 1, n, np.array(rp, dtype=np.int64),
                     np.concatenate(cols).astype(np.int32), np.concatenate(vs),
                     np.array(lh), np.array(rh), vartype, lb, ub, x0)
+
+
+def _hard_terms(rng, kind: int):
+    """Coefficients and bound values whose products sum to a value on, or a
+    tiny distance from, the midpoint between two doubles, or cancel to a
+    small remainder: the sums a double-double accumulator cannot round
+    correctly on its own.  Magnitudes stay inside the library's input domain
+    (coefficients in [2^-64, 2^64], bounds up to 2^200)."""
+    two = 2.0
+    if kind == 0:  # 2^53 + 1 + 2^-60 and relatives: the tie hides in the lost bits
+        k = int(rng.integers(0, 60))
+        a = [1.0, 1.0, 1.0]
+        b = [two ** (53 + k), two**k, two ** (k - int(rng.integers(55, 110)))]
+    elif kind == 1:  # exact tie, rounds to even
+        k = int(rng.integers(-30, 30))
+        a = [1.0, 1.0]
+        b = [two ** (53 + k) + 2 * float(rng.integers(0, 4)) * two**k, two**k]
+    elif kind == 2:  # cancellation of large terms around a small remainder
+        big = np.ldexp(rng.uniform(0.5, 1.0), int(rng.integers(100, 190)))
+        small = np.ldexp(rng.uniform(0.5, 1.0), int(rng.integers(-60, 60)))
+        a = [1.0, -1.0, 1.0]
+        b = [big, big, small]
+    else:  # near-midpoint sums of mixed-magnitude pieces
+        e = int(rng.integers(-40, 60))
+        big = np.ldexp(float(rng.integers(2**52, 2**53)), e - 52)
+        half = np.ldexp(1.0, e - 53)
+        off = np.ldexp(1.0, e - 53 - int(rng.integers(5, 100))) * rng.choice([-1.0, 0.0, 1.0])
+        junk = list(np.ldexp(rng.uniform(0.5, 1.0, 3), rng.integers(e - 20, e + 20, 3)))
+        b = [big, half, off] + junk + [-x for x in junk]
+        b = [x for x in b if x != 0.0]
+        a = [1.0] * len(b)
+    # spread each term over a coefficient and a bound: a * b stays exact
+    a = np.array(a, dtype=np.float64)
+    b = np.array(b, dtype=np.float64)
+    sh = rng.integers(-8, 9, size=a.size)
+    a = np.ldexp(a, sh)
+    b = np.ldexp(b, -sh)
+    return a, b
+
+
+def hard_sums(seed: int = 0, count: int = 64,
+              lengths=(3, 7, 20, 60, 130, 300, 900, 2500), tiny: bool = False) -> Instance:
+    """Rows whose min activity is a hard sum (see _hard_terms), one row per
+    case, padded to each of `lengths` entries with variables in [0, 1] (zero
+    contribution to the min activity) so that every lanes-per-row class and
+    the long-row segments see them.  Each term owns a continuous variable:
+    a > 0 gets lower bound b (upper +inf), a < 0 upper bound b (lower -inf),
+    so the min activity is exactly the sum of the terms.  rhs sits a few
+    units above it; every candidate of the row depends on the activity's
+    last bits.  With `tiny`, one term per row uses a bound of magnitude below
+    2^-906 (the products a kernel cannot split exactly with an FMA)."""
+    rng = _rng(BASE_SEED + 800_000 + seed)
+    rows, lhs, rhs, lb, ub = [], [], [], [], []
+    n = 0
+    for c in range(count):
+        a, b = _hard_terms(rng, c % 4)
+        if tiny:
+            a = np.append(a, np.ldexp(rng.uniform(1.0, 2.0), int(rng.integers(-60, 60))))
+            b = np.append(b, np.ldexp(rng.uniform(0.5, 1.0), int(rng.integers(-1074, -907))))
+        L = int(lengths[c % len(lengths)])
+        pad = max(0, L - a.size)
+        row = []
+        for x, y in zip(a, b):
+            row.append((n, float(x)))
+            if x > 0:
+                lb.append(float(y))
+                ub.append(INF)
+            else:
+                lb.append(-INF)
+                ub.append(float(y))
+            n += 1
+        for _ in range(pad):
+            row.append((n, 1.0))
+            lb.append(0.0)
+            ub.append(1.0)
+            n += 1
+        row = [row[q] for q in rng.permutation(len(row))]
+        rows.append(row)
+        # the products are exact by construction, so fsum places rhs just
+        # above the row's exact sum
+        s0 = math.fsum(float(x) * float(y) for x, y in zip(a, b))
+        scale = max(abs(s0), 1.0)
+        lhs.append(-INF)
+        rhs.append(s0 + float(rng.integers(1, 6)) * float(np.spacing(scale)))
+    return from_rows(rows, lhs, rhs, lb, ub, np.zeros(n, np.uint8), n=n,
+                     name=f"hard_sums[{seed}{',tiny' if tiny else ''}]")
 
 
 # --------------------------------------------------------------------------
