@@ -1,6 +1,10 @@
 """Batched nodes on the GPU: every node of a batch must give bitwise the
 status, rounds and bounds of its own single run (and therefore of the
 oracle, checked directly on the smaller cases)."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -177,14 +181,29 @@ def config3(lib):
     return inst, lbs, ubs
 
 
+def _golden_nodes():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "config3_nodes.json")
+    with open(path) as f:
+        return json.load(f)["nodes"]
+
+
+def bounds_sha(lb, ub):
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(lb, dtype="<f8").tobytes())
+    h.update(np.ascontiguousarray(ub, dtype="<f8").tobytes())
+    return h.hexdigest()
+
+
 def test_batch_config3_256_nodes(torch_cuda, lib, config3):
     """The 256 nodes of the 1,000,000 x 500,000 instance in one batch: each
-    node bitwise equal to its own single run.  Against the oracle (a full run
-    per node would take hours on the CPU), rounds are checked one at a time:
-    for sampled nodes, the first round from the node's bounds and the last
-    round before the final state are recomputed by the oracle."""
+    node bitwise equal to its own single run.  Eight nodes against the
+    oracle's full runs (tests/golden/config3_nodes.json: status, rounds and
+    the bounds' SHA-256 after every round): the batch's final state, and
+    every round of the node's single run (max_rounds = r)."""
     torch = torch_cuda
     inst, lbs, ubs = config3
+    gold = _golden_nodes()
     with lib.Problem.from_instance(inst) as p:
         res, blb, bub = run_batch(torch, p, lbs, ubs, 100)
         statuses = set()
@@ -195,17 +214,15 @@ def test_batch_config3_256_nodes(torch_cuda, lib, config3):
             if r1.status != oracle.INFEASIBLE:
                 assert np.array_equal(blb[k], lb1) and np.array_equal(bub[k], ub1), k
         assert {oracle.CONVERGED, oracle.INFEASIBLE} <= statuses
-        conv = [k for k in range(256) if res[k].status == oracle.CONVERGED]
-        for k in conv[:2]:
-            # round 1 from the node's bounds (integer-rounded as on entry)
-            lb0 = np.where(inst.vartype == 1, np.ceil(lbs[k] - 1e-6), lbs[k]) + 0.0
-            ub0 = np.where(inst.vartype == 1, np.floor(ubs[k] + 1e-6), ubs[k]) + 0.0
-            r_one, lb_one, ub_one = p.run(lbs[k], ubs[k], 1)
-            Ln, Un, ch, inf, _ = oracle.round_(inst, lb0, ub0)
-            assert np.array_equal(lb_one, Ln) and np.array_equal(ub_one, Un), k
-            # the last round: from the state one round before, the oracle
-            # reproduces the final bounds and reports no change
-            rp, lbp, ubp = p.run(lbs[k], ubs[k], res[k].rounds - 1)
-            Ln, Un, ch, inf, _ = oracle.round_(inst, lbp, ubp)
-            assert not ch and not inf, k
-            assert np.array_equal(Ln, blb[k]) and np.array_equal(Un, bub[k]), k
+        for key, g in gold.items():
+            k = int(key)
+            R = g["rounds"]
+            assert (res[k].status, res[k].rounds) == (g["status"], R), k
+            if g["status"] != oracle.INFEASIBLE:
+                assert bounds_sha(blb[k], bub[k]) == g["sha"][R], k
+            # every round before the last (infeasible nodes: bounds of the
+            # final round are unspecified)
+            last = R if g["status"] != oracle.INFEASIBLE else R - 1
+            for r in range(1, last + 1):
+                rr, lb_r, ub_r = p.run(lbs[k], ubs[k], r)
+                assert bounds_sha(lb_r, ub_r) == g["sha"][r], f"node {k}: round {r} differs"

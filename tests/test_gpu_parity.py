@@ -7,6 +7,8 @@ the largest deviation for diagnosis).  Runs go through every round-loop
 driver; the graph driver replays its captured rounds many times per run,
 with other drivers' runs in between.
 """
+import hashlib
+import json
 import math
 import os
 import sys
@@ -258,10 +260,26 @@ def test_invalid_bounds_rejected(lib):
 
 
 # ---------------------------------------------------------------------------
-# full-size config 2 (5M x 2M, ~52M nonzeros): round transitions checked one
-# by one against the oracle (a round is a function of the bounds it starts
-# from), plus properties of the final state
+# full-size config 2 (5M x 2M, ~52M nonzeros): every round against the
+# oracle's, through the SHA-256 of the bounds after that round
+# (tests/golden/config2_rounds.json, written by make_round_hashes.py from
+# the oracle alone), plus properties of the final state
 # ---------------------------------------------------------------------------
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def bounds_sha(lb, ub):
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(lb, dtype="<f8").tobytes())
+    h.update(np.ascontiguousarray(ub, dtype="<f8").tobytes())
+    return h.hexdigest()
+
+
+def load_golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
 @pytest.fixture(scope="module")
 def big(lib):
     say("generating config2 (5,000,000 x 2,000,000)")
@@ -272,62 +290,43 @@ def big(lib):
     p.close()
 
 
-def _normalized_root(inst):
-    lb = np.where(inst.vartype == 1, np.ceil(inst.lb - 1e-6), inst.lb) + 0.0
-    ub = np.where(inst.vartype == 1, np.floor(inst.ub + 1e-6), inst.ub) + 0.0
-    return lb, ub
-
-
-def test_config2_round1_lockstep(lib, big):
+def test_config2_every_round(lib, big):
+    """Round r of the GPU run (max_rounds = r) leaves exactly the bounds of
+    the oracle's round r, for every round of the run; the first differing
+    round is named."""
     inst, p = big
-    res, lb1, ub1 = p.run(inst.lb, inst.ub, 1)
-    assert (res.status, res.rounds) == (oracle.MAX_ROUNDS, 1)
-    say("oracle round 1 on config2")
-    L0, U0 = _normalized_root(inst)
-    Ln, Un, ch, inf, _ = oracle.round_(inst, L0, U0)
-    assert ch and not inf
-    assert np.array_equal(lb1, Ln) and np.array_equal(ub1, Un)
-
-
-def test_config2_full_run_lockstep(lib, big):
-    inst, p = big
-    res, lb, ub = p.run(inst.lb, inst.ub, 100)
-    say(f"config2 GPU: status {res.status} rounds {res.rounds}")
-    assert res.status == oracle.CONVERGED
-    assert res.rounds >= 2
-    # the last round must reproduce the final state and report no change
-    r_prev, lbp, ubp = p.run(inst.lb, inst.ub, res.rounds - 1)
-    assert r_prev.status == oracle.MAX_ROUNDS
-    Ln, Un, ch, inf, _ = oracle.round_(inst, lbp, ubp)
-    assert not ch and not inf
-    assert np.array_equal(lbp, lb) and np.array_equal(ubp, ub)
-    assert np.array_equal(Ln, lb) and np.array_equal(Un, ub)
-    # x0 stays inside
+    g = load_golden("config2_rounds.json")
+    R = g["rounds"]
+    assert R >= 2
+    for r in range(1, R + 1):
+        res, lb, ub = p.run(inst.lb, inst.ub, r)
+        want = (g["status"], R) if r == R else (oracle.MAX_ROUNDS, r)
+        assert (res.status, res.rounds) == want, f"round {r}: {res.status}/{res.rounds} vs {want}"
+        assert bounds_sha(lb, ub) == g["sha"][r], f"bounds differ from the oracle's after round {r}"
+    say(f"config2: {R} rounds, every one equal to the oracle's")
+    # x0 stays inside the final bounds
     tol = 1e-6 * np.maximum(1.0, np.abs(inst.x0))
     assert np.all(lb - tol <= inst.x0) and np.all(inst.x0 <= ub + tol)
+    # the full run (all drivers) ends in the same state
+    for loop in LOOPS:
+        p.set_loop(loop)
+        res, lb, ub = p.run(inst.lb, inst.ub, 100)
+        assert (res.status, res.rounds) == (g["status"], R), loop
+        assert bounds_sha(lb, ub) == g["sha"][R], loop
+    p.set_loop("stream")
 
 
 def test_config2_marked_full_run(lib, big):
-    """Marked rounds on the full instance: bitwise the unmarked result."""
+    """Marked rounds on the full instance: the oracle's final state."""
     inst, p = big
-    res0, lb0, ub0 = p.run(inst.lb, inst.ub, 100)
+    g = load_golden("config2_rounds.json")
     p.set_marking(True)
     try:
         res1, lb1, ub1 = p.run(inst.lb, inst.ub, 100)
     finally:
         p.set_marking(False)
-    assert (res1.status, res1.rounds) == (res0.status, res0.rounds)
-    assert np.array_equal(lb1, lb0) and np.array_equal(ub1, ub0)
-
-
-def test_config2_round2_lockstep(lib, big):
-    inst, p = big
-    _, lb1, ub1 = p.run(inst.lb, inst.ub, 1)
-    res, lb2, ub2 = p.run(inst.lb, inst.ub, 2)
-    say("oracle round 2 on config2")
-    Ln, Un, ch, inf, _ = oracle.round_(inst, lb1, ub1)
-    assert np.array_equal(lb2, Ln) and np.array_equal(ub2, Un)
-    assert (res.status == oracle.MAX_ROUNDS) == ch
+    assert (res1.status, res1.rounds) == (g["status"], g["rounds"])
+    assert bounds_sha(lb1, ub1) == g["sha"][g["rounds"]]
 
 
 def test_round_limits_all_drivers(lib):
