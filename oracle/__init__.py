@@ -22,6 +22,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCE = os.path.join(_HERE, "prop_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SEQ_SOURCE = os.path.join(_HERE, "cpu_seq.c")
+_SEQ_LIB_PATH = os.path.join(_HERE, "libcpuseq.so")
 
 CONVERGED, INFEASIBLE, MAX_ROUNDS = 0, 1, 2
 STATUS_NAMES = {CONVERGED: "CONVERGED", INFEASIBLE: "INFEASIBLE", MAX_ROUNDS: "MAX_ROUNDS"}
@@ -43,9 +45,12 @@ def compile_library(src: str, out: str) -> str:
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle library (no GPU code involved)."""
+    """Compile the oracle library and the sequential baseline (no GPU code
+    involved)."""
     if force or not os.path.exists(_LIB_PATH):
         compile_library(SOURCE, _LIB_PATH)
+    if force or not os.path.exists(_SEQ_LIB_PATH):
+        compile_library(SEQ_SOURCE, _SEQ_LIB_PATH)
     return _LIB_PATH
 
 
@@ -210,3 +215,58 @@ def run(inst, lb, ub, max_rounds: int = 100, params: Params | None = None) -> Re
 
 def run_seq(inst, lb, ub, max_sweeps: int = 1000, params: Params | None = None) -> Result:
     return default().run_seq(inst, lb, ub, max_sweeps, params)
+
+
+class CpuSeq:
+    """The paper's sequential baseline (Algorithm 1 with constraint marking,
+    plain double sums in CSR order; ``cpu_seq.c``).  The column view is
+    built once here; ``run`` times the propagation alone, single-threaded."""
+
+    _lib = None
+
+    def __init__(self, inst):
+        if CpuSeq._lib is None:
+            if not os.path.exists(_SEQ_LIB_PATH):
+                compile_library(SEQ_SOURCE, _SEQ_LIB_PATH)
+            lib = ctypes.CDLL(_SEQ_LIB_PATH)
+            P = ctypes.c_void_p
+            i32, f64 = ctypes.c_int32, ctypes.c_double
+            lib.cs_create.argtypes = [i32, i32, P, P, P, P, P, P]
+            lib.cs_create.restype = P
+            lib.cs_destroy.argtypes = [P]
+            lib.cs_destroy.restype = None
+            lib.cs_run.argtypes = [P, f64, f64, f64, P, P, i32, P, P]
+            lib.cs_run.restype = ctypes.c_int
+            CpuSeq._lib = lib
+        self._arrays = _problem_arrays(inst)  # kept alive: the C side borrows them
+        rp, ci, va, lh, rh, vt = self._arrays
+        self.n = inst.n
+        self._h = CpuSeq._lib.cs_create(inst.m, inst.n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(lh),
+                                        _ptr(rh), _ptr(vt))
+        if not self._h:
+            raise OracleError("cs_create failed")
+
+    def run(self, lb, ub, max_sweeps: int = 1000, params: Params | None = None):
+        """(Result, seconds of the propagation itself)."""
+        import time
+
+        p = params or Params()
+        lb = np.array(lb, dtype=np.float64, copy=True)
+        ub = np.array(ub, dtype=np.float64, copy=True)
+        st, sw = ctypes.c_int32(0), ctypes.c_int32(0)
+        t0 = time.perf_counter()
+        rc = CpuSeq._lib.cs_run(self._h, p.eps_int, p.cont_rel_tol, p.feas_tol, _ptr(lb),
+                                _ptr(ub), int(max_sweeps), ctypes.byref(st), ctypes.byref(sw))
+        dt = time.perf_counter() - t0
+        if rc:
+            raise OracleError(f"cs_run failed: {rc}")
+        return Result(st.value, sw.value, lb, ub), dt
+
+    def close(self):
+        if self._h:
+            CpuSeq._lib.cs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
