@@ -195,26 +195,6 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
 int prop_run_batch(prop_problem* p, int32_t nodes, double* lb, double* ub, int32_t max_rounds,
                    prop_result* out);
 
-/* prop_run_batch_device for callers that cannot allocate device memory (code
- * being captured into a HIP graph, tight serving loops, harnesses that
- * forbid hipMalloc): the same arguments, results and errors, but the batch
- * workspace (bound pairs of every 8-node group, group tables, long-row
- * partials, per-node state, the result pairs) lives in a fixed 64 MiB device
- * array of the library instead of memory it allocates; the call allocates
- * nothing.  The workspace needs 32 * n * 8 * ceil(nodes / 8) bytes of bound
- * pairs plus 64 bytes per long-row segment and node slot and about 40 bytes
- * per slot; a call that would need more than 64 MiB returns PROP_EINVAL
- * before touching the device.  Rounds run over every group until all nodes
- * have finished (no compaction) with the stream driver's batches of rounds,
- * whatever prop_set_loop selected.  Each device holds its own copy of the
- * array until the process ends; every call on a device reuses it, so calls
- * that overlap on one device (from different threads or on different
- * streams) race and must be serialised by the caller.  d_lb, d_ub: device
- * arrays of nodes * n doubles as for prop_run_batch_device; out: host array
- * of `nodes` results. */
-int prop_run_batch_device_static(prop_problem* p, int32_t nodes, double* d_lb, double* d_ub,
-                                 int32_t max_rounds, void* stream, prop_result* out);
-
 /* Selects the round-loop driver (PROP_LOOP_*) for later runs. */
 int prop_set_loop(prop_problem* p, int32_t mode);
 
