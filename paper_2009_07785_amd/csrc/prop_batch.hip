@@ -199,12 +199,13 @@ __device__ __forceinline__ void round_unit(const Problem& P, const Batch& Bt, in
   const uint32_t exact = group_exact(Bt, g);
   if (unit < P.n_segs) {
     if (few)
-      seg_phase1(P, unit, Bt.gA[g], kNodeGroup, mask, Bt.partials, Bt.nodes, g * kNodeGroup);
+      seg_phase1<false>(P, unit, Bt.gA[g], kNodeGroup, mask, Bt.partials, Bt.nodes,
+                        g * kNodeGroup);
     else
       seg_phase1_nodes(P, unit, Bt.gA[g], mask, Bt.partials, Bt.nodes, g * kNodeGroup);
   } else {
     if (few)
-      chunk_dispatch(P, unit - P.n_segs, Bt.gA[g], Bt.gB[g], kNodeGroup, mask, exact);
+      chunk_dispatch<false>(P, unit - P.n_segs, Bt.gA[g], Bt.gB[g], kNodeGroup, mask, exact);
     else
       chunk_round_nodes(P, P.chunks[unit - P.n_segs], Bt.gA[g], Bt.gB[g], mask, exact);
   }

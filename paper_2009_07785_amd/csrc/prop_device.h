@@ -58,9 +58,10 @@ namespace prop {
 #define PROP_SKIP_FLOOR 0x1p-900
 
 // Combines the partial sums of the 2^klog lanes of each row (klog is the
-// same in every lane of the wave, so the branches are uniform); err is the
-// lanes' shared error bound of both sums (see prop_sum.h).
-__device__ __forceinline__ void group_reduce(DD& smin, DD& smax, double& err, int& cmin,
+// same in every lane of the wave, so the branches are uniform); emin / emax
+// are the lanes' error bounds of the two sums (see prop_sum.h).
+__device__ __forceinline__ void group_reduce(DD& smin, DD& smax, double& emin, double& emax,
+                                             int& cmin,
                                              int& cmax, int klog) {
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
@@ -70,11 +71,12 @@ __device__ __forceinline__ void group_reduce(DD& smin, DD& smax, double& err, in
     double b = __shfl_xor(smin.lo, off, kWave);
     double c = __shfl_xor(smax.hi, off, kWave);
     double d = __shfl_xor(smax.lo, off, kWave);
-    double f = __shfl_xor(err, off, kWave);
+    double f = __shfl_xor(emin, off, kWave);
+    double f2 = __shfl_xor(emax, off, kWave);
     int g = __shfl_xor(cmin, off, kWave);
     int h = __shfl_xor(cmax, off, kWave);
-    dd_add(smin, err, a, b, f);
-    dd_add(smax, err, c, d, 0.0);
+    dd_add(smin, emin, a, b, f);
+    dd_add(smax, emax, c, d, f2);
     cmin += g;
     cmax += h;
   }
@@ -82,17 +84,18 @@ __device__ __forceinline__ void group_reduce(DD& smin, DD& smax, double& err, in
 
 __device__ __forceinline__ bool is_inf(double x) { return __builtin_isinf(x); }
 
-// Contribution of one entry to both activities.
+// Contribution of one entry to both activities; mmin / mmax are the lane's
+// error bounds of the two sums (dd_add_prod).
 __device__ __forceinline__ void accumulate(double a, double l, double u, DD& smin, DD& smax,
-                                           int& cmin, int& cmax, double& err) {
+                                           int& cmin, int& cmax, double& mmin, double& mmax) {
   const double bmin = a > 0.0 ? l : u;
   const double bmax = a > 0.0 ? u : l;
   const bool imin = is_inf(bmin);
   const bool imax = is_inf(bmax);
   cmin += (a != 0.0 && imin) ? 1 : 0;
   cmax += (a != 0.0 && imax) ? 1 : 0;
-  dd_add_prod(smin, a, imin ? 0.0 : bmin, err);
-  dd_add_prod(smax, a, imax ? 0.0 : bmax, err);
+  dd_add_prod(smin, a, imin ? 0.0 : bmin, mmin);
+  dd_add_prod(smax, a, imax ? 0.0 : bmax, mmax);
 }
 
 // Skip threshold of one side of an entry: the candidate that side yields
@@ -131,6 +134,41 @@ __device__ __forceinline__ bool domain_empty(bool is_int, double l, double u, do
   return (l - u) > feas_tol * s;
 }
 
+// ---------------------------------------------------------------------------
+// compact bound codes (single runs)
+//
+// Beside the (l, u) pairs of the start-of-round bounds, a single run keeps a
+// 2-byte code per variable that the activity pass gathers for integer
+// variables instead of the 16-byte pair: the low byte holds l and the high
+// byte u as signed 8-bit integers, with -127 standing for l = -inf and 127
+// for u = +inf.  A variable whose bounds do not fit (a bound outside
+// [-126, 126] or not an integer, or any continuous variable) has the escape
+// code (low byte -128), and its entries gather the pair.  Every code decodes
+// to the exact doubles of the pair; the pack kernel writes the codes and the
+// commit rewrites the code of every variable it changes.  With 2 bytes per
+// variable instead of 16 the bounds that most entries gather take an eighth
+// of the cache space, and a 64-lane gather touches that many fewer lines.
+// ---------------------------------------------------------------------------
+constexpr uint16_t kCodeEscape = 0x0080;
+
+__device__ __forceinline__ uint16_t bound_code(bool is_int, double l, double u) {
+  const bool lok = l == -__builtin_inf() || (l >= -126.0 && l <= 126.0 && l == __builtin_floor(l));
+  const bool uok = u == __builtin_inf() || (u >= -126.0 && u <= 126.0 && u == __builtin_floor(u));
+  if (!(is_int && lok && uok)) return kCodeEscape;
+  const int lb = l == -__builtin_inf() ? -127 : (int)l;
+  const int ub = u == __builtin_inf() ? 127 : (int)u;
+  return (uint16_t)((uint32_t)(lb & 0xff) | ((uint32_t)(ub & 0xff) << 8));
+}
+
+// Bounds of a code; false for the escape code (the pair must be gathered).
+__device__ __forceinline__ bool decode_code(uint16_t w, double& l, double& u) {
+  const int lb = (int)(int8_t)(w & 0xff);
+  const int ub = (int)(int8_t)(w >> 8);
+  l = lb == -127 ? -__builtin_inf() : (double)lb;
+  u = ub == 127 ? __builtin_inf() : (double)ub;
+  return lb != -128;
+}
+
 // Fire-and-forget FP64 atomics (the result is unused, so no wave waits).
 __device__ __forceinline__ void atomic_max_f64(double* p, double v) {
   (void)__hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -151,12 +189,13 @@ struct RowState {
 
 // Row state from the reduced double-doubles; `force` sends the row to the
 // exact path whatever the certification says (a tiny bound is in play).
-__device__ __forceinline__ RowState make_row_state(const DD& smin, const DD& smax, double err,
+__device__ __forceinline__ RowState make_row_state(const DD& smin, const DD& smax, double emin,
+                                                   double emax,
                                                    int cmin, int cmax, double lhs, double rhs,
                                                    bool force) {
   RowState R;
-  const bool okmin = dd_round(smin.hi, smin.lo, err, R.minfin);
-  const bool okmax = dd_round(smax.hi, smax.lo, err, R.maxfin);
+  const bool okmin = dd_round(smin.hi, smin.lo, emin, R.minfin);
+  const bool okmax = dd_round(smax.hi, smax.lo, emax, R.maxfin);
   R.cmin = cmin;
   R.cmax = cmax;
   R.min_side = (rhs < __builtin_inf()) && cmin <= 1;
@@ -336,39 +375,41 @@ __device__ __forceinline__ void entry_candidates(const Problem& P, const RowStat
   }
 }
 
-// Skip code of one entry side for the chunk filter: a float c with
-// "slack >= c" implying "slack > thr" (thr from side_threshold), so a side
-// skipped by the code is one the exact test skips too.  Finite thresholds
-// round up to the next float strictly above them; thresholds below 2^-100
-// map to 2^-100 (no subnormal floats are involved); W <= 0 (skipped iff the
-// slack is >= 0) maps to 0; "never skip" stays +inf.
-__device__ __forceinline__ float skip_code(double thr) {
-  float f = (float)thr;
-  f = (double)f <= thr ? __int_as_float(__float_as_int(f) + 1) : f;
-  f = thr < 0x1p-100 ? 0x1p-100f : f;
-  f = thr < __builtin_inf() ? f : __builtin_inff();
-  return thr < 0.0 ? 0.0f : f;
+struct LaneAcc {
+  DD smin, smax;
+  double emin, emax;  // error bounds of the two sums (prop_sum.h)
+  int cmin, cmax;
+  double tmin, tmax;  // largest skip threshold per side (side_threshold)
+  bool omin, omax;    // holds the owner of the side's infinite contribution
+};
+
+__device__ __forceinline__ void lane_acc_init(LaneAcc& L) {
+  L.smin = {0.0, 0.0};
+  L.smax = {0.0, 0.0};
+  L.emin = L.emax = 0.0;
+  L.cmin = L.cmax = 0;
+  L.tmin = L.tmax = -__builtin_inf();
+  L.omin = L.omax = false;
 }
 
-// Both skip codes of an entry: the rhs side (through the min activity) and
-// the lhs side (through the max activity).  NaN marks the entry whose bound
-// makes that side's activity infinite: with exactly one infinite
-// contribution only that entry gets a candidate.
-__device__ __forceinline__ void entry_codes(double a, double l, double u, int32_t cw, double tau,
-                                            float& emin, float& emax) {
-  const bool is_int = cw < 0, pos = a > 0.0;
-  const double bmin = pos ? l : u, bmax = pos ? u : l;
-  emin = is_inf(bmin) ? __builtin_nanf("") : skip_code(side_threshold(a, l, u, is_int, pos, tau));
-  emax = is_inf(bmax) ? __builtin_nanf("") : skip_code(side_threshold(a, l, u, is_int, !pos, tau));
+// One entry's thresholds into the lane's per-side maxima (side_threshold);
+// an entry whose bound makes a side's activity infinite owns that side's
+// only infinite contribution when the row has exactly one.
+__device__ __forceinline__ void lane_thresholds(LaneAcc& L, double a, double l, double u,
+                                                bool is_int, double tau) {
+  const bool pos = a > 0.0;
+  const double t1 = side_threshold(a, l, u, is_int, pos, tau);
+  const double t2 = side_threshold(a, l, u, is_int, !pos, tau);
+  L.tmin = t1 > L.tmin ? t1 : L.tmin;
+  L.tmax = t2 > L.tmax ? t2 : L.tmax;
+  L.omin |= is_inf(pos ? l : u);
+  L.omax |= is_inf(pos ? u : l);
 }
 
-// Conservative form of entry_sides from the codes: true for every entry
-// with a side that entry_sides would keep.  Entries without a coefficient
-// carry -inf codes and never pass.
-__device__ __forceinline__ bool entry_passes(const RowState& R, float emin, float emax) {
+__device__ __forceinline__ bool lane_may_pass(const RowState& R, const LaneAcc& L) {
   bool p = false;
-  if (R.min_side) p |= R.cmin == 0 ? !(R.smn >= (double)emin) : __builtin_isnan(emin);
-  if (R.max_side) p |= R.cmax == 0 ? !((-R.smx) >= (double)emax) : __builtin_isnan(emax);
+  if (R.min_side) p |= R.cmin == 0 ? !(R.smn > L.tmin) : L.omin;
+  if (R.max_side) p |= R.cmax == 0 ? !((-R.smx) > L.tmax) : L.omax;
   return p;
 }
 
@@ -378,14 +419,15 @@ __device__ __forceinline__ bool entry_passes(const RowState& R, float emin, floa
 // Bound arrays are addressed as base[var * stride + node]: stride 1 for a
 // single problem, 8 for a batch (8 nodes share each variable's cache line).
 // Per active node (bit t of node_mask) each step loads its coefficient and
-// column word, gathers the bounds, adds the entry to the activities and
-// keeps only the entry's two skip codes; after the row reduction, the
-// entries whose codes do not rule them out reload their data and go through
-// the exact candidate test.  Holding two floats per step instead of the
-// entry's coefficient, column and bounds keeps the wave's register count,
-// and with it the number of resident waves hiding the gather latency, in
-// line with a plain sparse product.  In a batch, nodes after the first find
-// the chunk's matrix data in cache.
+// column word, gathers the bounds (a single run gathers the 2-byte codes of
+// integer variables), adds the entry to the activities and folds its skip
+// thresholds into the lane's per-side maxima; after the row reduction, only
+// lanes whose maxima do not rule out every entry reload their entries and
+// run the exact candidate test.  Keeping two doubles per lane instead of
+// anything per step keeps the wave's register count, and with it the
+// number of resident waves hiding the gather latency, in line with a plain
+// sparse product.  In a batch, nodes after the first find the chunk's
+// matrix data in cache.
 // ---------------------------------------------------------------------------
 // Exact path for row rr of a chunk (lanes rr * K .. rr * K + K - 1) and
 // node t: the exactly rounded activities replace the row state of those
@@ -426,11 +468,89 @@ __device__ __forceinline__ void exact_chunk_row(const Problem& P, const ChunkDes
   }
 }
 
+// Steps of a chunk handled together in the activity pass: their
+// coefficients and column words are loaded first, then their bounds are
+// gathered, then they are added, so a wave waits for two memory round trips
+// per kStepGroup steps instead of three per step (one more for integer
+// variables whose code escapes): groups of 2 measured 416 us per round on
+// the 5,000,000 x 2,000,000 instance, against 431 for 1 and 434 for 4.
+// Padding entries (zero coefficient) hold column 0, a valid variable, so
+// their gathers need no guard; they contribute nothing.
+constexpr int kStepGroup = 2;
+static_assert(kStepGroup == 1 || kStepGroup == 2 || kStepGroup == 4,
+              "lane_steps handles remainders of up to 3 steps");
+
+template <int N, bool kCodes>
+__device__ __forceinline__ void chunk_steps(const Problem& P, const double2* __restrict__ cur,
+                                            const uint16_t* __restrict__ codes, uint32_t stride,
+                                            uint32_t t, size_t e0, LaneAcc& L) {
+  double av[N];
+  int32_t cv[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const size_t e = e0 + (size_t)k * kWave;
+    // a single run reads the matrix once: stream it past the caches
+    av[k] = stride == 1 ? __builtin_nontemporal_load(P.vals + e) : P.vals[e];
+    cv[k] = stride == 1 ? __builtin_nontemporal_load(P.cols + e) : P.cols[e];
+  }
+  double2 bv[N];
+  if (kCodes) {
+    // integer variables: the 2-byte code, the pair only on escape;
+    // continuous variables: the pair
+    bool pair[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      pair[k] = cv[k] >= 0;
+      if (!pair[k]) {
+        const uint16_t w = codes[cv[k] & kColMask];
+        pair[k] = !decode_code(w, bv[k].x, bv[k].y);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+      if (pair[k]) bv[k] = cur[(size_t)(cv[k] & kColMask) * stride + t];
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) bv[k] = cur[(size_t)(cv[k] & kColMask) * stride + t];
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    if (av[k] != 0.0) {
+      accumulate(av[k], bv[k].x, bv[k].y, L.smin, L.smax, L.cmin, L.cmax, L.emin, L.emax);
+      lane_thresholds(L, av[k], bv[k].x, bv[k].y, cv[k] < 0, P.cont_rel_tol);
+    }
+  }
+}
+
+// The activity pass over W steps of one lane, starting at entry e0.
+template <bool kCodes>
+__device__ __forceinline__ void lane_steps(const Problem& P, const double2* __restrict__ cur,
+                                           const uint16_t* __restrict__ codes, uint32_t stride,
+                                           uint32_t t, size_t e0, int W, LaneAcc& L) {
+  int w0 = 0;
+  for (; w0 + kStepGroup <= W; w0 += kStepGroup)
+    chunk_steps<kStepGroup, kCodes>(P, cur, codes, stride, t, e0 + (size_t)w0 * kWave, L);
+  // W is the same in every lane
+  switch (W - w0) {
+    case 3: chunk_steps<3, kCodes>(P, cur, codes, stride, t, e0 + (size_t)w0 * kWave, L); break;
+    case 2: chunk_steps<2, kCodes>(P, cur, codes, stride, t, e0 + (size_t)w0 * kWave, L); break;
+    case 1: chunk_steps<1, kCodes>(P, cur, codes, stride, t, e0 + (size_t)w0 * kWave, L); break;
+    default: break;
+  }
+}
+
 // With `marked` (single runs in marked rounds), rows not stamped with round
 // r are skipped: none of their variables changed in the previous round, so
 // their activities and candidates are those of that round, which changed
 // nothing.  Bit t of `exact_mask` sends every row of node t to the exact
 // path (a tiny bound is in play).
+//
+// Each lane keeps, besides its sums, the largest skip threshold of its
+// entries per side and whether it holds the owner of a side's infinite
+// contribution (LaneAcc): "slack > largest threshold" skips every entry of
+// the lane exactly as the per-entry test would, so only lanes holding an
+// entry that may count revisit their entries, with the exact test.
+template <bool kCodes>
 __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd,
                                             const double2* __restrict__ cur,
                                             double2* __restrict__ nxt, uint32_t stride,
@@ -449,44 +569,35 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
   const double lhs = P.lhs[row], rhs = P.rhs[row];
   for (uint32_t mask = node_mask; mask; mask &= mask - 1) {
     const uint32_t t = __builtin_ctz(mask);
-    float emin[kMaxSteps], emax[kMaxSteps];
-    DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
-    double err = 0.0;
-    int cmin = 0, cmax = 0;
-#pragma unroll
-    for (int w = 0; w < kMaxSteps; ++w) {
-      emin[w] = -__builtin_inff();
-      emax[w] = -__builtin_inff();
-      if (w < W && want) {
-        const size_t e = base + (size_t)w * kWave;
-        // a single run reads the matrix once: stream it past the caches
-        const double a = stride == 1 ? __builtin_nontemporal_load(P.vals + e) : P.vals[e];
-        const int32_t cw = stride == 1 ? __builtin_nontemporal_load(P.cols + e) : P.cols[e];
-        if (a != 0.0) {
-          const double2 b = cur[(size_t)(cw & kColMask) * stride + t];
-          accumulate(a, b.x, b.y, smin, smax, cmin, cmax, err);
-          entry_codes(a, b.x, b.y, cw, P.cont_rel_tol, emin[w], emax[w]);
-        }
-      }
-    }
-    group_reduce(smin, smax, err, cmin, cmax, klog);
-    RowState R = make_row_state(smin, smax, err, cmin, cmax, lhs, rhs, (exact_mask >> t) & 1u);
+    LaneAcc L;
+    lane_acc_init(L);
+    if (want) lane_steps<kCodes>(P, cur, P.codes, stride, t, base, W, L);
+    group_reduce(L.smin, L.smax, L.emin, L.emax, L.cmin, L.cmax, klog);
+    RowState R = make_row_state(L.smin, L.smax, L.emin, L.emax, L.cmin, L.cmax, lhs, rhs,
+                                (exact_mask >> t) & 1u);
     const bool live = row_ok && want;
-    if (live && !R.uncertain && (R.min_side || R.max_side)) {
-      // a step no lane needs is skipped by the wave
+    if (live && !R.uncertain && lane_may_pass(R, L)) {
+      // four entries at a time: loads, then gathers, then the exact tests
+      for (int w0 = 0; w0 < W; w0 += 4) {
+        const int cnt = W - w0 < 4 ? W - w0 : 4;
+        double av[4];
+        int32_t cv[4];
 #pragma unroll
-      for (int w = 0; w < kMaxSteps; ++w) {
-        if (w < W && entry_passes(R, emin[w], emax[w])) {
-          const size_t e = base + (size_t)w * kWave;
-          const double a = P.vals[e];
-          const int32_t cw = P.cols[e];
-          const double2 b = cur[(size_t)(cw & kColMask) * stride + t];
-          entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride, stride == 1);
+        for (int k = 0; k < 4; ++k) {
+          const size_t e = base + (size_t)(w0 + (k < cnt ? k : cnt - 1)) * kWave;
+          av[k] = P.vals[e];
+          cv[k] = P.cols[e];
         }
+        double2 bv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bv[k] = cur[(size_t)(cv[k] & kColMask) * stride + t];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (k < cnt && av[k] != 0.0)
+            entry_candidates(P, R, av[k], bv[k].x, bv[k].y, cv[k], nxt + t, stride, stride == 1);
       }
     }
     // rows the fast sums cannot certify, one at a time with the whole wave
-    // (after the loop above, so the skip codes are no longer held)
     uint64_t need = __ballot(live && R.uncertain && (lane & ((1 << klog) - 1)) == 0);
     while (need) {
       exact_chunk_row(P, cd, __builtin_ctzll(need) >> klog, cur, nxt, stride, t, R, lhs, rhs);
@@ -495,11 +606,14 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
   }
 }
 
+// kCodes: the single run's bounds, with the compact codes of integer
+// variables (P.codes); batches pass their own bound arrays without codes.
+template <bool kCodes>
 __device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const double2* cur,
                                                double2* nxt, uint32_t stride,
                                                uint32_t node_mask, uint32_t exact_mask,
                                                bool marked = false, int r_round = 0) {
-  chunk_round(P, P.chunks[c], cur, nxt, stride, node_mask, exact_mask, marked, r_round);
+  chunk_round<kCodes>(P, P.chunks[c], cur, nxt, stride, node_mask, exact_mask, marked, r_round);
 }
 
 // ---------------------------------------------------------------------------
@@ -520,23 +634,6 @@ __device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const do
 // entry of the lane, exactly as the per-entry test would, so only lanes
 // with an entry that may count revisit their entries, with the exact test.
 // ---------------------------------------------------------------------------
-struct LaneAcc {
-  DD smin, smax;
-  double err;         // error bound of both sums (prop_sum.h)
-  int cmin, cmax;
-  double tmin, tmax;  // largest skip threshold per side (side_threshold)
-  bool omin, omax;    // holds the owner of the side's infinite contribution
-};
-
-__device__ __forceinline__ void lane_acc_init(LaneAcc& L) {
-  L.smin = {0.0, 0.0};
-  L.smax = {0.0, 0.0};
-  L.err = 0.0;
-  L.cmin = L.cmax = 0;
-  L.tmin = L.tmax = -__builtin_inf();
-  L.omin = L.omax = false;
-}
-
 // Entries idx0 + k * dk (k < count, 1 <= count <= N) for node t: loads of
 // the group, then its gathers, then the arithmetic.  Indices past count
 // re-read the last entry and contribute nothing.
@@ -558,17 +655,8 @@ __device__ __forceinline__ void node_entries(const Problem& P, const double2* __
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     if (k < count && on && av[k] != 0.0) {
-      accumulate(av[k], bv[k].x, bv[k].y, L.smin, L.smax, L.cmin, L.cmax, L.err);
-      // the lane keeps thresholds, not fp32 codes: only their maximum is
-      // needed.  An owner of an infinite contribution only occurs in rows
-      // with such a contribution, where the maximum is not consulted.
-      const bool is_int = cv[k] < 0, pos = av[k] > 0.0;
-      const double t1 = side_threshold(av[k], bv[k].x, bv[k].y, is_int, pos, P.cont_rel_tol);
-      const double t2 = side_threshold(av[k], bv[k].x, bv[k].y, is_int, !pos, P.cont_rel_tol);
-      L.tmin = t1 > L.tmin ? t1 : L.tmin;
-      L.tmax = t2 > L.tmax ? t2 : L.tmax;
-      L.omin |= is_inf(pos ? bv[k].x : bv[k].y);
-      L.omax |= is_inf(pos ? bv[k].y : bv[k].x);
+      accumulate(av[k], bv[k].x, bv[k].y, L.smin, L.smax, L.cmin, L.cmax, L.emin, L.emax);
+      lane_thresholds(L, av[k], bv[k].x, bv[k].y, cv[k] < 0, P.cont_rel_tol);
     }
   }
 }
@@ -584,21 +672,15 @@ __device__ __forceinline__ void slot_reduce(LaneAcc& L, int levels) {
     double b = __shfl_xor(L.smin.lo, off, kWave);
     double c = __shfl_xor(L.smax.hi, off, kWave);
     double d = __shfl_xor(L.smax.lo, off, kWave);
-    double f = __shfl_xor(L.err, off, kWave);
+    double f = __shfl_xor(L.emin, off, kWave);
+    double f2 = __shfl_xor(L.emax, off, kWave);
     int g = __shfl_xor(L.cmin, off, kWave);
     int h = __shfl_xor(L.cmax, off, kWave);
-    dd_add(L.smin, L.err, a, b, f);
-    dd_add(L.smax, L.err, c, d, 0.0);
+    dd_add(L.smin, L.emin, a, b, f);
+    dd_add(L.smax, L.emax, c, d, f2);
     L.cmin += g;
     L.cmax += h;
   }
-}
-
-__device__ __forceinline__ bool lane_may_pass(const RowState& R, const LaneAcc& L) {
-  bool p = false;
-  if (R.min_side) p |= R.cmin == 0 ? !(R.smn > L.tmin) : L.omin;
-  if (R.max_side) p |= R.cmax == 0 ? !((-R.smx) > L.tmax) : L.omax;
-  return p;
 }
 
 // Exact path for one (row, node) of node-parallel lanes: row block rb,
@@ -687,7 +769,7 @@ __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkD
     const bool live = r < nrows && on;
     const int row = cd.row0 + (r < nrows ? r : 0);
     const double lhs = P.lhs[row], rhs = P.rhs[row];
-    RowState R = make_row_state(L.smin, L.smax, L.err, L.cmin, L.cmax, lhs, rhs,
+    RowState R = make_row_state(L.smin, L.smax, L.emin, L.emax, L.cmin, L.cmax, lhs, rhs,
                                 (exact_mask >> t) & 1u);
     if (live && !R.uncertain && lane_may_pass(R, L)) {
       for (int qq = 0; qq < QB; ++qq) {
@@ -729,6 +811,7 @@ __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkD
 // ---------------------------------------------------------------------------
 // long rows: partials live at partials[segment * pstride + node]
 // ---------------------------------------------------------------------------
+template <bool kCodes>
 __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
                                            const double2* __restrict__ cur, uint32_t stride,
                                            uint32_t node_mask, SegPartial* parts,
@@ -737,37 +820,17 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
   const int lane = threadIdx.x & (kWave - 1);
   const SegDesc sd = P.segs[s];
   if (marked && P.row_mark[sd.row] != r_round) return;
-  double a[kMaxSteps];
-  int32_t jj[kMaxSteps];
-#pragma unroll
-  for (int w = 0; w < kMaxSteps; ++w) {
-    const int p = w * kWave + lane;
-    a[w] = 0.0;
-    jj[w] = 0;
-    if (p < sd.len) {
-      a[w] = __builtin_nontemporal_load(P.vals + sd.off + p);
-      jj[w] = __builtin_nontemporal_load(P.cols + sd.off + p);
-    }
-  }
+  // the segment's region is padded to whole 64-entry steps (zero
+  // coefficients, column 0), so it is walked like a chunk of one 64-lane row
+  const int W = (sd.len + kWave - 1) / kWave;
+  const size_t base = (size_t)sd.off + lane;
   for (uint32_t mask = node_mask; mask; mask &= mask - 1) {
     const uint32_t t = __builtin_ctz(mask);
-    DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
-    double err = 0.0;
-    int cmin = 0, cmax = 0;
-    double tmin = -0x1p-1074, tmax = -0x1p-1074;  // per-side skip thresholds
-#pragma unroll
-    for (int w = 0; w < kMaxSteps; ++w) {
-      if (a[w] != 0.0) {
-        const double2 b = cur[(size_t)(jj[w] & kColMask) * stride + t];
-        accumulate(a[w], b.x, b.y, smin, smax, cmin, cmax, err);
-        const bool is_int = jj[w] < 0, pos = a[w] > 0.0;
-        const double t1 = side_threshold(a[w], b.x, b.y, is_int, pos, P.cont_rel_tol);
-        const double t2 = side_threshold(a[w], b.x, b.y, is_int, !pos, P.cont_rel_tol);
-        tmin = t1 > tmin ? t1 : tmin;
-        tmax = t2 > tmax ? t2 : tmax;
-      }
-    }
-    group_reduce(smin, smax, err, cmin, cmax, 6);
+    LaneAcc L;
+    lane_acc_init(L);
+    lane_steps<kCodes>(P, cur, P.codes, stride, t, base, W, L);
+    group_reduce(L.smin, L.smax, L.emin, L.emax, L.cmin, L.cmax, 6);
+    double tmin = L.tmin, tmax = L.tmax;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
       const double o1 = __shfl_xor(tmin, off, kWave);
@@ -777,15 +840,16 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
     }
     if (lane == 0) {
       SegPartial q;
-      q.min_hi = smin.hi;
-      q.min_lo = smin.lo;
-      q.max_hi = smax.hi;
-      q.max_lo = smax.lo;
+      q.min_hi = L.smin.hi;
+      q.min_lo = L.smin.lo;
+      q.max_hi = L.smax.hi;
+      q.max_lo = L.smax.lo;
       q.tmin = tmin;
       q.tmax = tmax;
-      q.min_inf = cmin;
-      q.max_inf = cmax;
-      q.err = err;
+      q.min_inf = L.cmin;
+      q.max_inf = L.cmax;
+      q.emin = L.emin;
+      q.emax = L.emax;
       parts[(size_t)s * pstride + node0 + t] = q;
     }
   }
@@ -824,7 +888,7 @@ __device__ __forceinline__ void seg_phase1_nodes(const Problem& P, int s,
     for (int k = 0; k < 8; ++k) {
       if (k < count && on && av[k] != 0.0) {
         const double2 b = bv[k];
-        accumulate(av[k], b.x, b.y, L.smin, L.smax, L.cmin, L.cmax, L.err);
+        accumulate(av[k], b.x, b.y, L.smin, L.smax, L.cmin, L.cmax, L.emin, L.emax);
         const bool is_int = cv[k] < 0, pos = av[k] > 0.0;
         const double t1 = side_threshold(av[k], b.x, b.y, is_int, pos, P.cont_rel_tol);
         const double t2 = side_threshold(av[k], b.x, b.y, is_int, !pos, P.cont_rel_tol);
@@ -851,7 +915,8 @@ __device__ __forceinline__ void seg_phase1_nodes(const Problem& P, int s,
     q.tmax = tmax;
     q.min_inf = L.cmin;
     q.max_inf = L.cmax;
-    q.err = L.err;
+    q.emin = L.emin;
+    q.emax = L.emax;
     parts[(size_t)s * pstride + node0 + t] = q;
   }
 }
@@ -894,18 +959,18 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
   const SegDesc sd = P.segs[s];
   if (marked && P.row_mark[sd.row] != r_round) return;
   DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
-  double err = 0.0;
+  double emin = 0.0, emax = 0.0;
   int cmin = 0, cmax = 0;
   for (int q = lane; q < sd.nseg; q += kWave) {
     const SegPartial pp = parts[(size_t)(sd.first + q) * pstride + node];
-    dd_add(smin, err, pp.min_hi, pp.min_lo, pp.err);
-    dd_add(smax, err, pp.max_hi, pp.max_lo, 0.0);
+    dd_add(smin, emin, pp.min_hi, pp.min_lo, pp.emin);
+    dd_add(smax, emax, pp.max_hi, pp.max_lo, pp.emax);
     cmin += pp.min_inf;
     cmax += pp.max_inf;
   }
-  group_reduce(smin, smax, err, cmin, cmax, 6);
+  group_reduce(smin, smax, emin, emax, cmin, cmax, 6);
   const double lhs = P.lhs[sd.row], rhs = P.rhs[sd.row];
-  RowState R = make_row_state(smin, smax, err, cmin, cmax, lhs, rhs, force_exact);
+  RowState R = make_row_state(smin, smax, emin, emax, cmin, cmax, lhs, rhs, force_exact);
   if (R.uncertain) {  // the same in every lane after the full-wave reduction
     // every segment of the row recomputes the exact sums: rare, and no wave
     // waits on another
@@ -961,12 +1026,14 @@ __device__ __forceinline__ uint32_t u32_load(const uint32_t* p) {
 __device__ __forceinline__ bool commit_one(const Problem& P, uint32_t v, double2 a, double2 b,
                                            uint32_t& changed, uint32_t& infeasible) {
   if (a.x == b.x && a.y == b.y) return false;
+  const bool is_int = P.vtype[v] != 0;
   P.bnd[0][v] = b;
   P.bnd[1][v] = b;
+  P.codes[v] = bound_code(is_int, b.x, b.y);
   ++changed;
   if (tiny_bound(b.x) || tiny_bound(b.y))
     __hip_atomic_store(&P.ctrl->tiny, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (domain_empty(P.vtype[v] != 0, b.x, b.y, P.feas_tol)) infeasible = 1;
+  if (domain_empty(is_int, b.x, b.y, P.feas_tol)) infeasible = 1;
   return true;
 }
 

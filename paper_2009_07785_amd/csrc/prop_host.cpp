@@ -211,6 +211,8 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   double2 *b0, *b1;
   if ((rc = dev_alloc(p, &b0, (size_t)n))) return rc;
   if ((rc = dev_alloc(p, &b1, (size_t)n))) return rc;
+  uint16_t* codes;
+  if ((rc = dev_alloc(p, &codes, (size_t)(n > 0 ? n : 1)))) return rc;
   const int32_t n_hot = L.n_hot;
   double2* stripes;
   if ((rc = dev_alloc(p, &stripes, (size_t)kStripes * (n_hot > 0 ? n_hot : 1)))) return rc;
@@ -240,6 +242,7 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   P.instance_infeasible = p->instance_infeasible ? 1 : 0;
   P.bnd[0] = b0;
   P.bnd[1] = b1;
+  P.codes = codes;
   P.stripes = stripes;
   P.n_hot = n_hot;
   P.ctrl = d_ctrl;

@@ -57,6 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(Problem P, const double* __rest
     const double2 b = make_double2(l, u);
     P.bnd[0][j] = b;
     P.bnd[1][j] = b;
+    P.codes[j] = bound_code(is_int, l, u);
     if (tiny_bound(l) || tiny_bound(u))
       __hip_atomic_store(&P.ctrl->tiny, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (domain_empty(is_int, l, u, P.feas_tol))
@@ -98,9 +99,10 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Problem P, int max_rounds
 
   for (int r = 1; r <= max_rounds; ++r) {
     const uint32_t exact = u32_load(&C->tiny) ? 1u : 0u;
-    for (int c = gwave; c < P.n_chunks; c += nwaves) chunk_dispatch(P, c, A, B, 1, 1, exact);
+    for (int c = gwave; c < P.n_chunks; c += nwaves) chunk_dispatch<true>(P, c, A, B, 1, 1, exact);
     if (P.n_segs) {
-      for (int s = gwave; s < P.n_segs; s += nwaves) seg_phase1(P, s, A, 1, 1, P.partials, 1, 0);
+      for (int s = gwave; s < P.n_segs; s += nwaves)
+        seg_phase1<true>(P, s, A, 1, 1, P.partials, 1, 0);
       if (!grid_barrier(P, kActNone, r, max_rounds)) return;
       for (int s = gwave; s < P.n_segs; s += nwaves)
         seg_phase2(P, s, A, B, 1, 0, P.partials, 1, 0, exact != 0);
@@ -136,10 +138,9 @@ __device__ __forceinline__ bool marked_round(const Problem& P) {
 }
 
 // Six waves per SIMD (at most 84 VGPRs; the kernel fits in 78 without
-// spills): the round is bound by outstanding first-level misses, and the
-// extra wave hides more of their latency than the compiler's freer
-// schedule at 92 VGPRs and five waves (492 vs 506 us per launch on the
-// 5,000,000 x 2,000,000 instance).
+// spills): the round is bound by the gathers of the activity pass, and
+// resident waves hide their latency.  Eight waves (64 VGPRs) spill and run
+// twice as long.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_round(
     Problem P) {
   if (u32_load(&P.ctrl->done)) return;
@@ -147,9 +148,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = blockIdx.x * kWavesPerBlock + wave;
   const bool marked = marked_round(P);
-  if (item < P.n_segs) seg_phase1(P, item, P.bnd[0], 1, 1, P.partials, 1, 0, marked, r);
+  if (item < P.n_segs) seg_phase1<true>(P, item, P.bnd[0], 1, 1, P.partials, 1, 0, marked, r);
   else if (item - P.n_segs < P.n_chunks)
-    chunk_dispatch(P, item - P.n_segs, P.bnd[0], P.bnd[1], 1, 1,
+    chunk_dispatch<true>(P, item - P.n_segs, P.bnd[0], P.bnd[1], 1, 1,
                    u32_load(&P.ctrl->tiny) ? 1u : 0u, marked, r);
 }
 

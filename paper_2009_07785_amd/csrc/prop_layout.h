@@ -56,6 +56,7 @@ struct Problem {
   int32_t instance_infeasible;
   // state: bnd[0] = start-of-round bounds, bnd[1] = candidate target
   double2* bnd[2];
+  uint16_t* codes;          // [n] compact code of bnd[0] per variable (prop_device.h)
   double2* stripes;         // [kStripes][n_hot] candidate targets of hot variables
   int32_t n_hot;
   int32_t pad_hot;

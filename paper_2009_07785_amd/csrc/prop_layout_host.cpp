@@ -39,10 +39,19 @@ bool layout_build(const prop_csr* A, const double* lhs, const double* rhs,
   }
   out->instance_infeasible = infeasible;
 
-  // variables by decreasing degree
+  // Relabelling: the hot variables (degree >= kHotDegree, at most kMaxHot,
+  // the most used first), then the other integer variables, then the other
+  // continuous ones, each part by decreasing degree.  The activity pass
+  // gathers the 2-byte bound codes of integer variables and the 16-byte
+  // pairs of continuous ones, so keeping each class contiguous keeps each
+  // gathered array dense.
   std::vector<int32_t> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
+  int32_t n_hot = 0;
+  while (n_hot < n && n_hot < kMaxHot && deg[order[n_hot]] >= kHotDegree) ++n_hot;
+  std::stable_partition(order.begin() + n_hot, order.end(),
+                        [&](int32_t j) { return vartype[j] != 0; });
   std::vector<int32_t> perm(n);
   for (int32_t q = 0; q < n; ++q) perm[order[q]] = q;
   std::vector<uint8_t> vtype(n);
@@ -201,9 +210,6 @@ bool layout_build(const prop_csr* A, const double* lhs, const double* rhs,
     each_entry([&](int32_t v, int32_t row) { vr[(size_t)fill[v]++] = row; });
   }
 
-  // hot variables: the leading relabelled ones with degree >= kHotDegree
-  int32_t n_hot = 0;
-  while (n_hot < n && n_hot < kMaxHot && deg[order[n_hot]] >= kHotDegree) ++n_hot;
   out->n_hot = n_hot;
   out->n_rows = (int32_t)n_rows_internal;
   out->perm = std::move(perm);

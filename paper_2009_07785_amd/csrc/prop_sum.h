@@ -8,6 +8,7 @@
 // one's rounding error is itself computed exactly with a two-sum, and err
 // collects their magnitudes.  Lanes and partial sums combine with dd_add,
 // which does the same for its own two roundings and adds both operands'
+// err.  Each of the two sums of a row (min and max activity) keeps its own
 // err.  So |S - (hi + lo)| <= sum of the collected errors, S the exact sum
 // of the row's products, and err is that sum computed in floating point
 // (nonnegative terms: at most (k - 1)u relative below the true sum for k
@@ -15,9 +16,11 @@
 // checks whether every real number within that distance of hi + lo rounds
 // to the same double as hi + lo; if so that double is RN(S).  When no
 // addition rounded at all, err is 0 and hi + lo is S itself, which covers
-// exact ties (frequent with +-1 coefficients).  Only when S may lie on the
-// other side of a rounding boundary than hi + lo (as with 2^53 + 1 + 2^-60,
-// where lo loses the 2^-60) does the row need the exact path below.
+// exact ties (frequent with +-1 coefficients and short mantissas; an a
+// priori bound such as 2^-53 |lo| would refuse those ties).  Only when S
+// may lie on the other side of a rounding boundary than hi + lo (as with
+// 2^53 + 1 + 2^-60, where lo loses the 2^-60) does the row need the exact
+// path below.
 //
 // The FMA split is exact when the product's last bit is not below 2^-1074.
 // With coefficients of magnitude in [2^-64, 2^64] that holds for every

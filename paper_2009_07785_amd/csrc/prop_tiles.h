@@ -77,7 +77,7 @@ struct SegPartial {
   double max_hi, max_lo;   // same for the max activity
   double tmin, tmax;       // largest per-side skip threshold of the segment's entries
   int32_t min_inf, max_inf;
-  double err;              // error bound of both double-doubles (prop_sum.h)
+  double emin, emax;       // error bounds of the two double-doubles (prop_sum.h)
 };
 
 }  // namespace prop

@@ -380,6 +380,47 @@ def random_small(seed: int, m: int, n: int, max_len: int = 6, int_frac: float = 
     return Instance(f"small[{seed}]", m, n, row_ptr, col, vals, lhs, rhs, vartype, lb, ub, x0)
 
 
+def code_edges(seed: int = 0, n: int = 4000, m: int = 6000) -> Instance:
+    """Integer variables whose bounds sit on both sides of the small-integer
+    range [-126, 126] (and at its edges, and infinite), continuous ones
+    mixed in, rows of 1-12 entries plus some of 300-2,000 entries, small
+    integer coefficients and sides close to a feasible point, so that
+    propagation moves integer bounds into the range and across its edges."""
+    rng = _rng(BASE_SEED + 800_000 + seed)
+    inf = INF
+    lows = np.array([-inf, -300.0, -128.0, -127.0, -126.0, -125.0, -3.0, 0.0, 1.0, 120.0,
+                     125.0, 126.0, 127.0, 200.0])
+    widths = np.array([0.0, 1.0, 2.0, 5.0, 30.0, 130.0, 253.0, 260.0, 600.0, inf])
+    vartype = (rng.random(n) < 0.85).astype(np.uint8)
+    lb = lows[rng.integers(0, lows.size, n)]
+    free_lo = np.isinf(lb)
+    ub = np.where(free_lo, rng.choice([-126.0, 0.0, 126.0, 127.0, 1000.0, inf], n),
+                  np.where(free_lo, 0.0, lb) + widths[rng.integers(0, widths.size, n)])
+    cont = vartype == 0
+    shift = rng.random(n) * 0.5  # fractional bounds for the continuous variables
+    lb = np.where(cont & ~np.isinf(lb), lb + shift, lb)
+    ub = np.where(cont & ~np.isinf(ub), ub + shift, ub)
+    # a finite point inside every box
+    flo = np.where(np.isinf(lb), np.where(np.isinf(ub), 0.0, ub - 50.0), lb)
+    fhi = np.where(np.isinf(ub), flo + 50.0, ub)
+    x0 = flo + np.floor(rng.random(n) * (fhi - flo + 1))
+    x0 = np.minimum(x0, fhi)
+    x0[cont] = flo[cont] + rng.random(cont.sum()) * (fhi[cont] - flo[cont])
+    lengths = rng.integers(1, 13, size=m)
+    lengths[rng.random(m) < 0.004] = rng.integers(300, 2000, size=1)[0]
+    row_ptr, col = _distinct_columns(rng, lengths, n)
+    mag = rng.integers(1, 6, size=col.size).astype(np.float64)
+    vals = np.where(rng.random(col.size) < 0.5, -mag, mag)
+    s = _row_dot(row_ptr, col, vals, x0)
+    lhs = s - np.floor(rng.random(m) * 12)
+    rhs = s + np.floor(rng.random(m) * 12)
+    one = rng.random(m) < 0.2
+    dl = rng.random(m) < 0.5
+    lhs[one & dl] = -INF
+    rhs[one & ~dl] = INF
+    return Instance(f"code_edges[{seed}]", m, n, row_ptr, col, vals, lhs, rhs, vartype, lb, ub, x0)
+
+
 def layout_mix(seed: int = 0, copies: int = 3) -> Instance:
     """Rows of every length class a wave tile distinguishes (1 .. 1024 entries,
     ragged within each class) plus rows longer than 1024 entries, some of them

@@ -83,7 +83,19 @@ static int check_steps(const prop_csr& A, const std::vector<double>& lhs,
     inv[L.perm[j]] = j;
     CHECK(L.vtype[L.perm[j]] == vt[j]);
   }
-  for (int32_t q = 1; q < n; ++q) CHECK(deg[inv[q - 1]] >= deg[inv[q]]);
+  // hot prefix, then integer variables, then continuous ones, each part by
+  // decreasing degree
+  CHECK(L.n_hot >= 0 && L.n_hot <= n && L.n_hot <= kMaxHot);
+  for (int32_t q = 0; q < L.n_hot; ++q) CHECK(deg[inv[q]] >= kHotDegree);
+  for (int32_t q = L.n_hot; q < n; ++q) {
+    CHECK(deg[inv[q]] < kHotDegree || L.n_hot == kMaxHot);
+    if (q + 1 < n) {
+      if (q + 1 == L.n_hot) continue;
+      const bool same = L.vtype[q] == L.vtype[q + 1];
+      CHECK(same ? deg[inv[q]] >= deg[inv[q + 1]] : (L.vtype[q] != 0 && L.vtype[q + 1] == 0));
+    }
+  }
+  for (int32_t q = 1; q < L.n_hot; ++q) CHECK(deg[inv[q - 1]] >= deg[inv[q]]);
   // rows of every variable
   CHECK((int64_t)L.var_ptr.size() == (int64_t)n + 1 && L.var_ptr[n] == nnz);
   for (int32_t v = 0; v < n; ++v) CHECK(L.var_ptr[v + 1] - L.var_ptr[v] == deg[inv[v]]);

@@ -105,6 +105,20 @@ def test_layout_mix(lib, seed):
     assert ref.status == oracle.CONVERGED
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_code_edges(lib, seed):
+    """Integer bounds on both sides of the compact codes' range [-126, 126],
+    at its edges and infinite, moving into it as the rounds tighten them:
+    codes decode to the pairs' exact values and escaped variables gather
+    their pairs, so the results stay the oracle's bitwise."""
+    inst = synth.code_edges(seed)
+    ref = check_against_oracle(lib, inst)
+    assert ref.status == oracle.CONVERGED and ref.rounds > 5
+    for steps in (4, 16):
+        with lib.Problem.from_instance(inst, steps=steps) as p:
+            assert_same(f"{inst.name}/steps={steps}", p.run(inst.lb, inst.ub, 100), ref)
+
+
 def test_powerlaw_hot_variables(lib):
     """Power-law columns: dozens of variables above the degree at which the
     kernels spread their candidate targets over stripe copies."""
