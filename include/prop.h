@@ -195,6 +195,26 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
 int prop_run_batch(prop_problem* p, int32_t nodes, double* lb, double* ub, int32_t max_rounds,
                    prop_result* out);
 
+/* prop_run_batch_device for callers that cannot allocate device memory:
+ * code being captured into a HIP graph, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and errors, but the batch
+ * workspace lives in a fixed 64 MiB device array of the library instead of
+ * memory the call allocates, and the call allocates nothing.  The
+ * workspace takes 32 * n * 8 * ceil(nodes / 8) bytes of bound pairs, 80
+ * bytes per long-row segment and node, and 40 bytes per node, each region
+ * rounded up to 256 bytes; a call that needs more than 64 MiB returns
+ * PROP_EINVAL before touching the device.  Every group of 8 nodes runs
+ * until all nodes have finished (no compaction), with rounds queued on
+ * `stream` in batches as by PROP_LOOP_STREAM, whatever prop_set_loop
+ * selected; the done flag is read through pinned memory once per batch.
+ * Each device the library runs on holds its own copy of the array until
+ * the process ends, and every call on that device reuses it (the call
+ * clears what must start at zero): calls that overlap on one device, from
+ * several threads or on several streams, race and must be serialised by
+ * the caller. */
+int prop_run_batch_device_static(prop_problem* p, int32_t nodes, double* d_lb, double* d_ub,
+                                 int32_t max_rounds, void* stream, prop_result* out);
+
 /* Selects the round-loop driver (PROP_LOOP_*) for later runs. */
 int prop_set_loop(prop_problem* p, int32_t mode);
 

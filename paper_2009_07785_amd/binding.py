@@ -25,7 +25,7 @@ LOOP_NAMES = {"persistent": LOOP_PERSISTENT, "stream": LOOP_STREAM, "host": LOOP
 
 # every function the header declares
 EXPORTED = ("prop_create", "prop_autotune", "prop_run", "prop_run_device", "prop_run_batch",
-            "prop_run_batch_device",
+            "prop_run_batch_device", "prop_run_batch_device_static",
             "prop_set_loop", "prop_set_marking", "prop_get_info",
             "prop_last_timing", "prop_set_kernel_timing", "prop_last_kernel_timing",
             "prop_destroy", "prop_last_error",
@@ -107,6 +107,8 @@ def _load():
     lib.prop_run_batch.restype = ctypes.c_int
     lib.prop_run_batch_device.argtypes = [P, i32, P, P, i32, P, ctypes.POINTER(_Result)]
     lib.prop_run_batch_device.restype = ctypes.c_int
+    lib.prop_run_batch_device_static.argtypes = [P, i32, P, P, i32, P, ctypes.POINTER(_Result)]
+    lib.prop_run_batch_device_static.restype = ctypes.c_int
     lib.prop_set_loop.argtypes = [P, i32]
     lib.prop_set_loop.restype = ctypes.c_int
     lib.prop_set_marking.argtypes = [P, i32]
@@ -263,9 +265,12 @@ class Problem:
         _check(lib.prop_run_batch(self._h, nodes, _ptr(lbs), _ptr(ubs), int(max_rounds), res))
         return [RunResult(r.status, r.rounds) for r in res], lbs, ubs
 
-    def run_batch_device(self, d_lb, d_ub, max_rounds: int = 100, stream=None):
+    def run_batch_device(self, d_lb, d_ub, max_rounds: int = 100, stream=None,
+                         static: bool = False):
         """Batched nodes: device tensors of shape (nodes, n), float64, updated
-        in place.  Returns one RunResult per node."""
+        in place.  Returns one RunResult per node.  With `static`, the
+        library's fixed workspace array is used and nothing is allocated
+        (prop_run_batch_device_static)."""
         for t in (d_lb, d_ub):
             if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8
                     and t.is_contiguous() and t.dim() == 2 and t.shape[1] == self.n):
@@ -279,9 +284,10 @@ class Problem:
             stream = torch.cuda.current_stream(d_lb.device)
         raw = getattr(stream, "cuda_stream", stream)
         res = (_Result * nodes)()
-        _check(lib.prop_run_batch_device(self._h, nodes, ctypes.c_void_p(d_lb.data_ptr()),
-                                         ctypes.c_void_p(d_ub.data_ptr()), int(max_rounds),
-                                         ctypes.c_void_p(int(raw) if raw else 0), res))
+        fn = lib.prop_run_batch_device_static if static else lib.prop_run_batch_device
+        _check(fn(self._h, nodes, ctypes.c_void_p(d_lb.data_ptr()),
+                  ctypes.c_void_p(d_ub.data_ptr()), int(max_rounds),
+                  ctypes.c_void_p(int(raw) if raw else 0), res))
         return [RunResult(r.status, r.rounds) for r in res]
 
     def set_loop(self, mode):

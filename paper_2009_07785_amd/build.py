@@ -8,8 +8,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libprop.so")
-SOURCES = ["prop_kernels.hip", "prop_batch.hip", "prop_host.cpp", "prop_layout_host.cpp",
-           "prop_serve.cpp"]
+SOURCES = ["prop_kernels.hip", "prop_batch.hip", "prop_static.hip", "prop_host.cpp",
+           "prop_layout_host.cpp", "prop_serve.cpp"]
 ARCH = "gfx950"
 
 
