@@ -85,13 +85,16 @@ def cpu_baseline(inst, skip: bool, min_seconds: float = 10.0, max_rounds: int = 
     }
 
 
-def cpu_seq_compare(skip: bool, max_rounds: int):
-    """The paper's comparison (speed-up over sequential propagation with
-    constraint marking, Algorithm 1, one core), on the 200,000 x 100,000
-    lognormal instance: the oracle's Algorithm 1 timed on one host core
-    against full GPU runs of the synchronous rounds.  The oracle sums
-    activities exactly (fixed point), so it is slower than a production
-    sequential propagator: context, not the paper's ratio."""
+def cpu_seq_compare(skip: bool, max_rounds: int, suite: int = 10):
+    """The paper's comparison: sequential propagation with constraint
+    marking (Algorithm 1) on one host core against full GPU runs of the
+    synchronous rounds, on the 200,000 x 100,000 lognormal instance.  Two
+    sequential codes are timed: the paper's kind (plain double sums in CSR
+    order, cpu_seq.c) and the oracle's Algorithm 1 (exactly rounded sums,
+    several times slower).  Over the first `suite` seeds of that family the
+    synchronous round counts are set against the sequential sweep counts
+    (the paper's rounds study: 4.4 synchronous rounds vs 3.1 sequential
+    on average)."""
     if skip:
         return None
     import numpy as np
@@ -102,10 +105,16 @@ def cpu_seq_compare(skip: bool, max_rounds: int):
     from paper_2009_07785_amd import Problem
 
     inst = synth.cached("config1_1", synth.config1, 1)
-    log("cpu_seq: the oracle's sequential Algorithm 1 on the 200,000 x 100,000 instance")
+    log("cpu_seq: sequential Algorithm 1 on the 200,000 x 100,000 instance")
+    seq = oracle.CpuSeq(inst)
+    t_plain = []
+    for _ in range(3):
+        res_plain, dt = seq.run(inst.lb, inst.ub)
+        t_plain.append(dt)
+    seq.close()
     t0 = time.perf_counter()
-    seq = oracle.run_seq(inst, inst.lb, inst.ub)
-    t_seq = time.perf_counter() - t0
+    res_exact = oracle.run_seq(inst, inst.lb, inst.ub)
+    t_exact = time.perf_counter() - t0
     dev = torch.device("cuda:0")
     from paper_2009_07785_amd import autotune
 
@@ -126,11 +135,32 @@ def cpu_seq_compare(skip: bool, max_rounds: int):
             ts.append(time.perf_counter() - t0)
     prob.close()
     t_gpu = float(np.median(ts))
+    # rounds study over a suite of seeds (feasible ones; every 50th seed of
+    # the family is made infeasible)
+    sync_rounds, seq_sweeps = [], []
+    for k in range(1, suite + 1):
+        ik = synth.cached(f"config1_{k}", synth.config1, k)
+        with Problem.from_instance(ik) as pk:
+            rk = pk.run(ik.lb, ik.ub, max_rounds)[0]
+        cs = oracle.CpuSeq(ik)
+        rs, _ = cs.run(ik.lb, ik.ub)
+        cs.close()
+        if rk.status == 0 and rs.status == 0:
+            sync_rounds.append(rk.rounds)
+            seq_sweeps.append(rs.rounds)
     out = {"workload": f"config1: {inst.m}x{inst.n}, {inst.nnz} nnz, from the root bounds",
-           "cpu_seq_s": t_seq, "cpu_seq_sweeps": seq.rounds, "cores": 1,
-           "kind": "oracle Algorithm 1 (exact sums)",
-           "gpu_run_ms": t_gpu * 1e3, "gpu_rounds": r.rounds, "layout_steps": steps,
-           "speedup_vs_cpu_seq": t_seq / t_gpu}
+           "cores": 1, "gpu_run_ms": t_gpu * 1e3, "gpu_rounds": r.rounds, "layout_steps": steps,
+           "cpu_seq": {"kind": "Algorithm 1 with marking, plain double sums (the paper's kind)",
+                       "seconds": float(np.median(t_plain)), "sweeps": res_plain.rounds,
+                       "speedup_gpu_vs_cpu_seq": float(np.median(t_plain)) / t_gpu},
+           "oracle_seq": {"kind": "the oracle's Algorithm 1, exactly rounded sums",
+                          "seconds": t_exact, "sweeps": res_exact.rounds,
+                          "speedup_gpu_vs_oracle_seq": t_exact / t_gpu},
+           "rounds_study": {"seeds": f"config1 seeds 1..{suite}, converged on both",
+                            "instances": len(sync_rounds),
+                            "synchronous_rounds_mean": float(np.mean(sync_rounds)),
+                            "sequential_sweeps_mean": float(np.mean(seq_sweeps)),
+                            "ratio": float(np.mean(sync_rounds)) / float(np.mean(seq_sweeps))}}
     log(f"cpu_seq: {out}")
     return out
 
@@ -146,6 +176,8 @@ def main():
     ap.add_argument("--no-cpu-seq", action="store_true",
                     help="skip the sequential-propagation comparison on the medium instance")
     ap.add_argument("--no-loop-compare", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 2,000 x 1,000 and 200,000 x 100,000 single-instance lines")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched branch-and-bound node comparison")
     ap.add_argument("--batch-nodes", type=int, default=256)
@@ -305,6 +337,8 @@ def main():
                   "identical_results": same}
         log(f"marked rounds: {marked}")
 
+    small = None if args.no_small else small_configs(args.max_rounds)
+
     batch = None if args.no_batch else batched_nodes(args.batch_nodes, args.max_rounds)
 
     serve = None
@@ -357,12 +391,53 @@ def main():
         },
         "round_loops": loops,
         "marked": marked,
+        "small_configs": small,
         "batched": batch,
         "serving": serve,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)
     prob.close()
+
+
+def small_configs(max_rounds: int, reps: int = 20):
+    """The two smaller single-instance workloads: 2,000 x 1,000 (latency:
+    microseconds per round and per run) and 200,000 x 100,000 (nonzeros per
+    second and fraction of the HBM roofline), full runs from the root bounds
+    with the bounds resident on the device, median of `reps` runs."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2009_07785_amd import Problem
+
+    dev = torch.device("cuda:0")
+    out = {}
+    for key, fn, args in (("config0", synth.config0, ()), ("config1", synth.config1, (1,))):
+        inst = synth.cached(key + "_bench", fn, *args)
+        prob = Problem.from_instance(inst)
+        info = prob.info()
+        prob.set_loop("graph")
+        root_lb = torch.tensor(inst.lb, dtype=torch.float64, device=dev)
+        root_ub = torch.tensor(inst.ub, dtype=torch.float64, device=dev)
+        d_lb, d_ub = torch.empty_like(root_lb), torch.empty_like(root_ub)
+        loop_ms = []
+        for i in range(reps + 2):
+            d_lb.copy_(root_lb)
+            d_ub.copy_(root_ub)
+            r = prob.run_device(d_lb, d_ub, max_rounds)
+            if i >= 2:
+                loop_ms.append(prob.last_timing()[0])
+        prob.close()
+        ms = float(np.median(loop_ms))
+        gbps = info["alg_bytes_round"] * r.rounds / (ms * 1e-3) / 1e9
+        out[key] = {"workload": f"{inst.name}: {inst.m}x{inst.n}, {info['nnz']} nnz, root bounds",
+                    "rounds": r.rounds, "loop": "graph", "layout_steps": info["steps"],
+                    "run_us": ms * 1e3, "us_per_round": ms * 1e3 / r.rounds,
+                    "nnz_per_s": info["nnz"] * r.rounds / (ms * 1e-3),
+                    "alg_GBps": gbps, "frac": gbps / HBM_PEAK_GBS}
+    log(f"small configs: {out}")
+    return out
 
 
 def batched_nodes(count: int, max_rounds: int):

@@ -731,6 +731,10 @@ __device__ __forceinline__ void exact_nodes_row(const Problem& P, const ChunkDes
   }
 }
 
+// Steps of a long chunk that node-parallel lanes load, gather and add as one
+// group: 6 keeps k_round_batch within 128 VGPRs without spills (8 spilled).
+constexpr int kNodeSteps = 6;
+
 __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkDesc cd,
                                                   const double2* __restrict__ cur,
                                                   double2* __restrict__ nxt, uint32_t node_mask,
@@ -760,9 +764,9 @@ __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkD
       } else if (W <= 4) {
         node_entries<4>(P, cur, t, on, base + l, kWave, W, L);
       } else {
-        for (int w0 = 0; w0 < W; w0 += 8)
-          node_entries<8>(P, cur, t, on, base + (size_t)w0 * kWave + l, kWave,
-                          W - w0 < 8 ? W - w0 : 8, L);
+        for (int w0 = 0; w0 < W; w0 += kNodeSteps)
+          node_entries<kNodeSteps>(P, cur, t, on, base + (size_t)w0 * kWave + l, kWave,
+                                   W - w0 < kNodeSteps ? W - w0 : kNodeSteps, L);
       }
     }
     slot_reduce(L, klog > 3 ? 3 : klog);
