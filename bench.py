@@ -178,6 +178,8 @@ def main():
     ap.add_argument("--no-loop-compare", action="store_true")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 2,000 x 1,000 and 200,000 x 100,000 single-instance lines")
+    ap.add_argument("--no-children", action="store_true",
+                    help="skip the branch-and-bound children leg (marked rounds from a parent)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched branch-and-bound node comparison")
     ap.add_argument("--batch-nodes", type=int, default=256)
@@ -340,6 +342,7 @@ def main():
     small = None if args.no_small else small_configs(args.max_rounds)
 
     batch = None if args.no_batch else batched_nodes(args.batch_nodes, args.max_rounds)
+    children = None if args.no_children else children_nodes(args.batch_nodes, args.max_rounds)
 
     serve = None
     if not args.no_serving:
@@ -393,6 +396,7 @@ def main():
         "marked": marked,
         "small_configs": small,
         "batched": batch,
+        "children": children,
         "serving": serve,
         "cpu_baseline": base,
     }
@@ -517,6 +521,85 @@ def batched_nodes(count: int, max_rounds: int):
     return out
 
 
+def children_nodes(count: int, max_rounds: int):
+    """Branch-and-bound children on the 1,000,000 x 500,000 power-law
+    matrix: the root's fixed point is the parent, and children 2i, 2i + 1
+    split the domain of one unfixed integer variable at its middle.  The
+    children run one at a time and batched, each without and with marked
+    rounds seeded from the parent (round 1 then processes only the rows of
+    the branched variable); all four give identical results."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2009_07785_amd import Problem
+
+    dev = torch.device("cuda:0")
+    inst = synth.cached("config3", synth.config3_matrix)
+    prob = Problem.from_instance(inst)
+    d_plb = torch.tensor(inst.lb, dtype=torch.float64, device=dev)
+    d_pub = torch.tensor(inst.ub, dtype=torch.float64, device=dev)
+    root = prob.run_device(d_plb, d_pub, 1000)
+    log(f"children: root {root.status_name} after {root.rounds} rounds")
+    if root.status != 0:
+        prob.close()
+        return {"skipped": f"the root did not converge ({root.status_name})"}
+    plb, pub = d_plb.cpu().numpy(), d_pub.cpu().numpy()
+    lbs, ubs = synth.branch_children(plb, pub, inst.vartype, count, 4100)
+    D_lb = torch.tensor(lbs, dtype=torch.float64, device=dev)
+    D_ub = torch.tensor(ubs, dtype=torch.float64, device=dev)
+    s_lb = torch.empty(inst.n, dtype=torch.float64, device=dev)
+    s_ub = torch.empty_like(s_lb)
+    stream = torch.cuda.current_stream(dev)
+
+    def one_at_a_time():
+        out_lb, out_ub, res = torch.empty_like(D_lb), torch.empty_like(D_ub), []
+        for k in range(count):
+            s_lb.copy_(D_lb[k])
+            s_ub.copy_(D_ub[k])
+            res.append(prob.run_device(s_lb, s_ub, max_rounds, stream))
+            out_lb[k].copy_(s_lb)
+            out_ub[k].copy_(s_ub)
+        return res, out_lb, out_ub
+
+    def batched():
+        b_lb, b_ub = D_lb.clone(), D_ub.clone()
+        return prob.run_batch_device(b_lb, b_ub, max_rounds, stream), b_lb, b_ub
+
+    out, ref = {}, None
+    for key, fn, marked in (("one_at_a_time", one_at_a_time, False),
+                            ("one_at_a_time_marked", one_at_a_time, True),
+                            ("batched", batched, False), ("batched_marked", batched, True)):
+        prob.set_marking(marked)
+        prob.set_parent(d_plb, d_pub) if marked else prob.set_parent(None, None)
+        fn()  # warm-up (workspace, marking data)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, lb, ub = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        got = ([(r.status, r.rounds) for r in res], lb, ub)
+        if ref is None:
+            ref = got
+            same = True
+        else:
+            feas = torch.tensor([st != 1 for st, _ in ref[0]], device=dev)
+            same = got[0] == ref[0] and bool(torch.all(torch.where(
+                feas[:, None], (got[1] == ref[1]) & (got[2] == ref[2]), True)).item())
+        out[key] = {"ms": dt * 1e3, "nodes_per_s": count / dt, "identical_to_first": same}
+    prob.set_marking(False)
+    prob.set_parent(None, None)
+    prob.close()
+    rounds = [r for _, r in ref[0]]
+    out.update({"workload": f"config3 matrix {inst.m}x{inst.n} ({inst.nnz} nnz): {count} "
+                            "children of the root's fixed point, each pair splitting one "
+                            "integer variable's domain",
+                "root_rounds": root.rounds, "children_rounds_mean": float(np.mean(rounds)),
+                "children_rounds_max": int(max(rounds))})
+    log(f"children: {out}")
+    return out
+
+
 def serving(scale: float, seconds: float, rate: float, budget: int, variants: int = 8,
             max_rounds: int = 50):
     """Open-loop serving: Poisson arrivals at `rate` per second for `seconds`,
@@ -612,7 +695,8 @@ def kernel_source_sha() -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for name in ("prop_kernels.hip", "prop_device.h", "prop_layout.h"):
+    for name in ("prop_kernels.hip", "prop_device.h", "prop_layout.h", "prop_sum.h",
+                 "prop_tiles.h"):
         with open(os.path.join(ROOT, "paper_2009_07785_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

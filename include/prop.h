@@ -219,20 +219,44 @@ int prop_run_batch_device_static(prop_problem* p, int32_t nodes, double* d_lb, d
 int prop_set_loop(prop_problem* p, int32_t mode);
 
 /* Marked rounds (enable != 0; off by default), for prop_run and
- * prop_run_device with the stream, graph or host driver (the persistent
- * driver and batches ignore it).  A row is then processed in round r >= 2 only when
- * one of its variables changed in round r - 1: a row whose variables did
- * not change would compute the activities and candidates of the previous
- * round, against the same bounds, and those changed nothing (a candidate
- * that counted would have changed its variable).  Results, status and round
- * counts are bitwise those of unmarked rounds; when more than n / 32
- * variables changed, the next round processes every row.  This is the
- * constraint marking of the paper's sequential Algorithm 1 applied to the
- * synchronous rounds of Algorithm 2.  The first enable uploads the rows of
- * every variable (4 bytes per nonzero, 8 per variable, 12 per piece of 64
- * rows of a variable), a row stamp per row and a changed-variable bitmap;
- * these stay until prop_destroy. */
+ * prop_run_device with the stream, graph or host driver, and for
+ * prop_run_batch / prop_run_batch_device (the persistent driver and
+ * prop_run_batch_device_static ignore it).  A row is then processed in
+ * round r >= 2 only when one of its variables changed in round r - 1 (in a
+ * batch: in any node of the row's group of 8 nodes): a row whose variables
+ * did not change would compute the activities and candidates of the
+ * previous round, against the same bounds, and those changed nothing (a
+ * candidate that counted would have changed its variable).  Results,
+ * status and round counts are bitwise those of unmarked rounds; when more
+ * than n / 32 variables changed, the next round processes every row (in a
+ * batch: every row of that group; also after a compaction).  This is the
+ * constraint marking of the paper's sequential Algorithm 1 (Sec. 2.1)
+ * applied to the synchronous rounds of Algorithm 2.  The first enable
+ * uploads the rows of every variable (4 bytes per nonzero, 8 per variable,
+ * 12 per piece of 64 rows of a variable), a row stamp per row and a
+ * changed-variable bitmap; a marked batch also allocates 4 bytes per row
+ * and n / 8 bytes per group of 8 nodes.  These stay until prop_destroy. */
 int prop_set_marking(prop_problem* p, int32_t enable);
+
+/* Parent fixed point for marked runs (branch-and-bound children; the
+ * paper's outlook, Sec. 5, and the marking of Algorithm 1, Sec. 2.1).
+ * d_lb, d_ub: device arrays of n doubles holding bounds that are a fixed
+ * point of this problem's propagation, such as the bounds a CONVERGED run
+ * returned; the library keeps a copy (integer bounds rounded as at the
+ * start of a run), so the caller's arrays may be reused at once.  While a
+ * parent is set and marked rounds are enabled, round 1 of prop_run,
+ * prop_run_device, prop_run_batch and prop_run_batch_device processes only
+ * the rows holding a variable whose start bounds differ from the parent's
+ * (in a batch: in any node of the row's group): every other row would
+ * compute the candidates of the parent's last round from the same bounds,
+ * and none of those counted.  Results are then bitwise those of an unmarked
+ * run, provided the parent really is a fixed point (the library does not
+ * check it: if it is not, rows that would have tightened a bound in round 1
+ * are skipped).  NULL, NULL clears the parent.  Runs on `stream` and
+ * synchronises it.  A bound that prop_run would reject returns PROP_EINVAL
+ * and clears the parent.  The first call allocates 16 * n bytes (and the
+ * marking data, as prop_set_marking does). */
+int prop_set_parent(prop_problem* p, const double* d_lb, const double* d_ub, void* stream);
 
 /* Fills *out with the problem's sizes. */
 int prop_get_info(const prop_problem* p, prop_info* out);

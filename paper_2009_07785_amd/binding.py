@@ -26,7 +26,7 @@ LOOP_NAMES = {"persistent": LOOP_PERSISTENT, "stream": LOOP_STREAM, "host": LOOP
 # every function the header declares
 EXPORTED = ("prop_create", "prop_autotune", "prop_run", "prop_run_device", "prop_run_batch",
             "prop_run_batch_device", "prop_run_batch_device_static",
-            "prop_set_loop", "prop_set_marking", "prop_get_info",
+            "prop_set_loop", "prop_set_marking", "prop_set_parent", "prop_get_info",
             "prop_last_timing", "prop_set_kernel_timing", "prop_last_kernel_timing",
             "prop_destroy", "prop_last_error",
             "prop_srv_create", "prop_srv_add_instance", "prop_srv_submit", "prop_srv_poll",
@@ -113,6 +113,8 @@ def _load():
     lib.prop_set_loop.restype = ctypes.c_int
     lib.prop_set_marking.argtypes = [P, i32]
     lib.prop_set_marking.restype = ctypes.c_int
+    lib.prop_set_parent.argtypes = [P, P, P, P]
+    lib.prop_set_parent.restype = ctypes.c_int
     lib.prop_get_info.argtypes = [P, ctypes.POINTER(_Info)]
     lib.prop_get_info.restype = ctypes.c_int
     lib.prop_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double),
@@ -299,6 +301,26 @@ class Problem:
         """Marked rounds: skip rows none of whose variables changed in the
         previous round (results unchanged)."""
         _check(lib.prop_set_marking(self._h, 1 if enable else 0))
+
+    def set_parent(self, d_lb=None, d_ub=None, stream=None):
+        """Parent fixed point for marked runs (device tensors of n float64),
+        or None to clear it: round 1 then processes only the rows of
+        variables whose start bounds differ from the parent's."""
+        if d_lb is None and d_ub is None:
+            _check(lib.prop_set_parent(self._h, None, None, None))
+            return
+        for t in (d_lb, d_ub):
+            if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8
+                    and t.is_contiguous() and t.numel() == self.n):
+                raise ValueError("parent bounds must be contiguous float64 device tensors (n,)")
+        if stream is None:
+            import torch
+
+            stream = torch.cuda.current_stream(d_lb.device)
+        raw = getattr(stream, "cuda_stream", stream)
+        _check(lib.prop_set_parent(self._h, ctypes.c_void_p(d_lb.data_ptr()),
+                                   ctypes.c_void_p(d_ub.data_ptr()),
+                                   ctypes.c_void_p(int(raw) if raw else 0)))
 
     def info(self) -> dict:
         inf = _Info()

@@ -119,6 +119,10 @@ __global__ __launch_bounds__(kBlock) void k_move_batch(Problem P, Batch Bt,
     Bt.gA[d / kNodeGroup][j * kNodeGroup + (d % kNodeGroup)] = b;
     Bt.gB[d / kNodeGroup][j * kNodeGroup + (d % kNodeGroup)] = b;
   }
+  // marked batches: a group's stamps do not cover nodes moved into it, so
+  // every group processes every row in the next round
+  if (Bt.row_mark && blockIdx.x == 0)
+    for (int g = threadIdx.x; g < Bt.groups; g += blockDim.x) Bt.gall[g] = 1;
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < (size_t)count; q += stride) {
     const int s = moves[q].x, d = moves[q].y;
     Bt.status[d] = Bt.status[s];
@@ -182,6 +186,15 @@ __global__ __launch_bounds__(kBlock) void k_start_batch(Problem P, Batch Bt, int
     if (Bt.live) Bt.live[k] = 1;
     act += a;
   }
+  if (whole && Bt.row_mark) {
+    // marked batches: round 1 processes every row unless a parent seeds it
+    const int groups = (k0 + cnt + kNodeGroup - 1) / kNodeGroup;
+    for (int g = threadIdx.x; g < groups; g += blockDim.x) {
+      Bt.gall[g] = 1;
+      Bt.gcnt[g] = 0;
+    }
+    if (threadIdx.x == 0) P.ctrl->round = 1;
+  }
   if (whole) batch_set_done(P, act);
   else if (threadIdx.x == 0) P.ctrl->done = 0;
 }
@@ -189,6 +202,19 @@ __global__ __launch_bounds__(kBlock) void k_start_batch(Problem P, Batch Bt, int
 // ---- bodies shared by the batch kernels and the serving kernels ----------
 
 // One wave: work unit `unit` (long-row segment, then chunk) of group g.
+// Marked rounds of a batch: whether group g skips unstamped rows in the
+// current round, and the group's stamps.
+__device__ __forceinline__ bool group_marked(const Problem& P, const Batch& Bt, int g, int& r,
+                                             const int32_t*& marks) {
+  if (!Bt.row_mark || Bt.gall[g]) return false;
+  r = __hip_atomic_load(&P.ctrl->round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  marks = Bt.row_mark + (size_t)g * P.n_rows;
+  return true;
+}
+
+// kMarks: the batch driver's kernels, whose groups may run marked rounds;
+// the serving kernels never do.
+template <bool kMarks>
 __device__ __forceinline__ void round_unit(const Problem& P, const Batch& Bt, int unit, int g) {
   if (unit >= P.n_segs + P.n_chunks) return;
   const uint32_t mask = group_mask(Bt, g);
@@ -197,26 +223,45 @@ __device__ __forceinline__ void round_unit(const Problem& P, const Batch& Bt, in
   // the active nodes with the single-run shape instead
   const bool few = __builtin_popcount(mask) <= kLoopNodes;
   const uint32_t exact = group_exact(Bt, g);
+  int r = 0;
+  const int32_t* marks = nullptr;
+  const bool marked = kMarks && group_marked(P, Bt, g, r, marks);
   if (unit < P.n_segs) {
     if (few)
       seg_phase1<false>(P, unit, Bt.gA[g], kNodeGroup, mask, Bt.partials, Bt.nodes,
-                        g * kNodeGroup);
+                        g * kNodeGroup, marked, r, marks);
     else
-      seg_phase1_nodes(P, unit, Bt.gA[g], mask, Bt.partials, Bt.nodes, g * kNodeGroup);
+      seg_phase1_nodes(P, unit, Bt.gA[g], mask, Bt.partials, Bt.nodes, g * kNodeGroup, marked, r,
+                       marks);
   } else {
     if (few)
-      chunk_dispatch<false>(P, unit - P.n_segs, Bt.gA[g], Bt.gB[g], kNodeGroup, mask, exact);
+      chunk_dispatch<false>(P, unit - P.n_segs, Bt.gA[g], Bt.gB[g], kNodeGroup, mask, exact,
+                            marked, r, marks);
     else
-      chunk_round_nodes(P, P.chunks[unit - P.n_segs], Bt.gA[g], Bt.gB[g], mask, exact);
+      chunk_round_nodes(P, P.chunks[unit - P.n_segs], Bt.gA[g], Bt.gB[g], mask, exact, marked, r,
+                        marks);
   }
 }
 
 // One wave: phase 2 of segment s for node k.
+template <bool kMarks>
 __device__ __forceinline__ void long_unit(const Problem& P, const Batch& Bt, int s, int k) {
   if (s >= P.n_segs || !Bt.active[k]) return;
   const int g = k / kNodeGroup;
+  int r = 0;
+  const int32_t* marks = nullptr;
+  const bool marked = kMarks && group_marked(P, Bt, g, r, marks);
   seg_phase2<true>(P, s, Bt.gA[g], Bt.gB[g], kNodeGroup, k % kNodeGroup, Bt.partials, Bt.nodes, k,
-                   Bt.tiny[k] != 0);
+                   Bt.tiny[k] != 0, marked, r, marks);
+}
+
+// The 8 variable bits of a wave's ballot over 8 variables x 8 nodes (lane
+// v * 8 + t): bit v set when any node t has its bit set.
+__device__ __forceinline__ uint32_t var_bits(uint64_t bits) {
+  uint32_t byte = 0;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) byte |= (uint32_t)(((bits >> (8 * v)) & 0xffull) != 0) << v;
+  return byte;
 }
 
 // Block bx of nbx over group g's (variable, node) pairs: copy changed pairs
@@ -236,16 +281,28 @@ __device__ __forceinline__ void commit_part(const Problem& P, const Batch& Bt, i
     const size_t stride = (size_t)nbx * blockDim.x;
     for (size_t e = (size_t)bx * blockDim.x + threadIdx.x; e < total; e += stride) {
       const uint32_t t = (uint32_t)(e % kNodeGroup);
-      if (!((mask >> t) & 1u)) continue;
-      const double2 a = A[e];
-      const double2 b = B[e];
-      if (a.x != b.x || a.y != b.y) {
-        A[e] = b;
-        atomicAdd(&ch[t], 1u);
-        if (tiny_bound(b.x) || tiny_bound(b.y))
-          __hip_atomic_store(&Bt.tiny[g * kNodeGroup + t], 1u, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-        if (domain_empty(P.vtype[e / kNodeGroup] != 0, b.x, b.y, P.feas_tol)) inf[t] = 1;
+      bool chg = false;
+      if ((mask >> t) & 1u) {
+        const double2 a = A[e];
+        const double2 b = B[e];
+        if (a.x != b.x || a.y != b.y) {
+          chg = true;
+          A[e] = b;
+          atomicAdd(&ch[t], 1u);
+          if (tiny_bound(b.x) || tiny_bound(b.y))
+            __hip_atomic_store(&Bt.tiny[g * kNodeGroup + t], 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+          if (domain_empty(P.vtype[e / kNodeGroup] != 0, b.x, b.y, P.feas_tol)) inf[t] = 1;
+        }
+      }
+      if (Bt.chg) {
+        // marked rounds: the wave's 64 pairs are 8 variables x 8 nodes;
+        // byte e / 64 of the group's bitmap gets one bit per variable
+        // changed in any node (each byte has one writer per round)
+        const uint32_t byte = var_bits(__ballot(chg));
+        if ((threadIdx.x & (kWave - 1)) == 0)
+          reinterpret_cast<uint8_t*>(Bt.chg + (size_t)g * ((P.n + kWave - 1) / kWave))[e / kWave] =
+              (uint8_t)byte;
       }
     }
   }
@@ -326,7 +383,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   if (units == 0) return;
   const int g = (int)(wid / units);
   if (g >= Bt.groups) return;
-  round_unit(P, Bt, (int)(wid - (int64_t)g * units), g);
+  round_unit<true>(P, Bt, (int)(wid - (int64_t)g * units), g);
 }
 
 __global__ __launch_bounds__(kBlock) void k_round_long_batch(Problem P, Batch Bt) {
@@ -336,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_round_long_batch(Problem P, Batch Bt
   if (P.n_segs == 0) return;
   const int k = (int)(wid / P.n_segs);
   if (k >= Bt.nodes) return;
-  long_unit(P, Bt, (int)(wid - (int64_t)k * P.n_segs), k);
+  long_unit<true>(P, Bt, (int)(wid - (int64_t)k * P.n_segs), k);
 }
 
 // Commit per (variable, node) of group blockIdx.y, with per-node counts.
@@ -348,7 +405,77 @@ __global__ __launch_bounds__(kBlock) void k_commit_batch(Problem P, Batch Bt) {
 
 __global__ __launch_bounds__(kBlock) void k_end_batch(Problem P, Batch Bt) {
   if (u32_load(&P.ctrl->done)) return;
+  if (Bt.row_mark && threadIdx.x == 0) P.ctrl->round = P.ctrl->round + 1;
   end_slots(P, Bt, nullptr, 0);
+}
+
+// Marked batches, after the commit of the current round (offset 1) or after
+// the parent seeding (offset 0): for every group with active nodes, stamps
+// the rows of its changed variables with the round they are processed in,
+// one thread per piece of <= kMarkPiece rows of a variable (blockIdx.y is
+// the group).  A group that changed more than n / kMarkAllDiv variables
+// processes every row instead (stamping them would cost more).
+__global__ __launch_bounds__(kBlock) void k_mark_batch(Problem P, Batch Bt, int offset) {
+  if (u32_load(&P.ctrl->done)) return;
+  const int g = blockIdx.y;
+  if (!group_mask(Bt, g)) return;
+  uint32_t count = 0;
+  if (offset == 0) {
+    count = Bt.gcnt[g];
+  } else {
+#pragma unroll
+    for (int t = 0; t < kNodeGroup; ++t) {
+      const int k = g * kNodeGroup + t;
+      if (k < Bt.nodes && Bt.active[k]) count += Bt.changed[k];
+    }
+  }
+  const bool all = count > (uint32_t)(P.n / kMarkAllDiv);
+  if (blockIdx.x == 0 && threadIdx.x == 0) Bt.gall[g] = all ? 1u : 0u;
+  if (all) return;
+  const int next = __hip_atomic_load(&P.ctrl->round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+                   offset;
+  const uint64_t* bits = Bt.chg + (size_t)g * ((P.n + kWave - 1) / kWave);
+  int32_t* marks = Bt.row_mark + (size_t)g * P.n_rows;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P.n_pieces; q += stride) {
+    const int32_t v = P.piece_var[q];
+    if (!((bits[v / kWave] >> (v % kWave)) & 1ull)) continue;
+    const int64_t start = P.piece_off[q];
+    const int64_t stop = P.var_ptr[v + 1] < start + kMarkPiece ? P.var_ptr[v + 1] : start + kMarkPiece;
+    for (int64_t i = start; i < stop; ++i) marks[P.var_rows[i]] = next;
+  }
+}
+
+// Marked batches from a parent fixed point: bit v of group g's bitmap is set
+// when variable v's start bounds differ from the parent's in any active node
+// of the group; gcnt counts those variables.  Round 1 then processes only
+// the rows of those variables (k_mark_batch, offset 0).
+__global__ __launch_bounds__(kBlock) void k_seed_batch(Problem P, Batch Bt) {
+  if (u32_load(&P.ctrl->done)) return;
+  const int g = blockIdx.y;
+  const uint32_t mask = group_mask(Bt, g);
+  if (!mask) return;
+  const double2* A = Bt.gA[g];
+  uint8_t* bytes = reinterpret_cast<uint8_t*>(Bt.chg + (size_t)g * ((P.n + kWave - 1) / kWave));
+  const size_t total = (size_t)P.n * kNodeGroup;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  uint32_t count = 0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const uint32_t t = (uint32_t)(e % kNodeGroup);
+    bool diff = false;
+    if ((mask >> t) & 1u) {
+      const double2 a = A[e];
+      const double2 b = P.parent[e / kNodeGroup];
+      diff = a.x != b.x || a.y != b.y;
+    }
+    const uint32_t byte = var_bits(__ballot(diff));
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+      bytes[e / kWave] = (uint8_t)byte;
+      count += __builtin_popcount(byte);
+    }
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0 && count)
+    __hip_atomic_fetch_add(&Bt.gcnt[g], count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---- serving kernels: every instance of a step in one launch per phase -----
@@ -388,7 +515,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   const int64_t units = (int64_t)P.n_segs + P.n_chunks;
   if (units == 0) return;
   const int g = (int)(local / units);
-  round_unit(P, Bt, (int)(local - (int64_t)g * units), g);
+  round_unit<false>(P, Bt, (int)(local - (int64_t)g * units), g);
 }
 
 __global__ __launch_bounds__(kBlock) void k_srv_long(const SrvInst* __restrict__ I,
@@ -403,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_srv_long(const SrvInst* __restrict__
   const int64_t local = wid - E.long_base;
   if (P.n_segs == 0) return;
   const int k = (int)(local / P.n_segs);
-  long_unit(P, Bt, (int)(local - (int64_t)k * P.n_segs), k);
+  long_unit<false>(P, Bt, (int)(local - (int64_t)k * P.n_segs), k);
 }
 
 __global__ __launch_bounds__(kBlock) void k_srv_commit(const SrvInst* __restrict__ I,
@@ -464,7 +591,19 @@ hipError_t launch_round_batch(const Problem& P, const Batch& Bt, hipStream_t s) 
   hipLaunchKernelGGL(k_commit_batch,
                      dim3(blocks_for((int64_t)P.n * kNodeGroup, kBlock, 256), Bt.groups),
                      dim3(kBlock), 0, s, P, Bt);
+  if (Bt.row_mark)
+    hipLaunchKernelGGL(k_mark_batch, dim3(blocks_for(P.n_pieces, kBlock, 1024), Bt.groups),
+                       dim3(kBlock), 0, s, P, Bt, 1);
   hipLaunchKernelGGL(k_end_batch, dim3(1), dim3(kBlock), 0, s, P, Bt);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_batch(const Problem& P, const Batch& Bt, hipStream_t s) {
+  hipLaunchKernelGGL(k_seed_batch,
+                     dim3(blocks_for((int64_t)P.n * kNodeGroup, kBlock, 256), Bt.groups),
+                     dim3(kBlock), 0, s, P, Bt);
+  hipLaunchKernelGGL(k_mark_batch, dim3(blocks_for(P.n_pieces, kBlock, 1024), Bt.groups),
+                     dim3(kBlock), 0, s, P, Bt, 0);
   return hipGetLastError();
 }
 

@@ -539,11 +539,11 @@ __device__ __forceinline__ void lane_steps(const Problem& P, const double2* __re
   }
 }
 
-// With `marked` (single runs in marked rounds), rows not stamped with round
-// r are skipped: none of their variables changed in the previous round, so
-// their activities and candidates are those of that round, which changed
-// nothing.  Bit t of `exact_mask` sends every row of node t to the exact
-// path (a tiny bound is in play).
+// With `marked` (marked rounds), rows whose stamp in `marks` is not r are
+// skipped: none of their variables changed in the previous round, so their
+// activities and candidates are those of that round, which changed nothing.
+// Bit t of `exact_mask` sends every row of node t to the exact path (a tiny
+// bound is in play).
 //
 // Each lane keeps, besides its sums, the largest skip threshold of its
 // entries per side and whether it holds the owner of a side's infinite
@@ -555,7 +555,8 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
                                             const double2* __restrict__ cur,
                                             double2* __restrict__ nxt, uint32_t stride,
                                             uint32_t node_mask, uint32_t exact_mask,
-                                            bool marked = false, int r_round = 0) {
+                                            bool marked = false, int r_round = 0,
+                                            const int32_t* marks = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
   const int klog = cd.meta & 7;
   const int W = (cd.meta >> 8) & 0xff;
@@ -564,7 +565,7 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
   const size_t base = (size_t)cd.off64 * kWave + lane;
   const bool row_ok = r < nrows;
   const int row = cd.row0 + (row_ok ? r : 0);
-  const bool want = !marked || (row_ok && P.row_mark[row] == r_round);
+  const bool want = !marked || (row_ok && marks[row] == r_round);
   if (marked && __ballot(want) == 0) return;
   const double lhs = P.lhs[row], rhs = P.rhs[row];
   for (uint32_t mask = node_mask; mask; mask &= mask - 1) {
@@ -612,8 +613,10 @@ template <bool kCodes>
 __device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const double2* cur,
                                                double2* nxt, uint32_t stride,
                                                uint32_t node_mask, uint32_t exact_mask,
-                                               bool marked = false, int r_round = 0) {
-  chunk_round<kCodes>(P, P.chunks[c], cur, nxt, stride, node_mask, exact_mask, marked, r_round);
+                                               bool marked = false, int r_round = 0,
+                                               const int32_t* marks = nullptr) {
+  chunk_round<kCodes>(P, P.chunks[c], cur, nxt, stride, node_mask, exact_mask, marked, r_round,
+                      marks);
 }
 
 // ---------------------------------------------------------------------------
@@ -738,7 +741,9 @@ constexpr int kNodeSteps = 6;
 __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkDesc cd,
                                                   const double2* __restrict__ cur,
                                                   double2* __restrict__ nxt, uint32_t node_mask,
-                                                  uint32_t exact_mask) {
+                                                  uint32_t exact_mask, bool marked = false,
+                                                  int r_round = 0,
+                                                  const int32_t* marks = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t t = lane & (kNodeGroup - 1);
   const int e = lane >> 3;
@@ -752,6 +757,8 @@ __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkD
   const size_t base = (size_t)cd.off64 * kWave;
   for (int rb = 0; rb < nblocks; ++rb) {
     const int r = klog > 3 ? rb : rb * per_block + (e >> klog);
+    // marked rounds: a row block none of whose rows is stamped is skipped
+    if (marked && __ballot(r < nrows && marks[cd.row0 + r] == r_round) == 0) continue;
     LaneAcc L;
     lane_acc_init(L);
     for (int qq = 0; qq < QB; ++qq) {
@@ -770,8 +777,8 @@ __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkD
       }
     }
     slot_reduce(L, klog > 3 ? 3 : klog);
-    const bool live = r < nrows && on;
     const int row = cd.row0 + (r < nrows ? r : 0);
+    const bool live = r < nrows && on && (!marked || marks[row] == r_round);
     const double lhs = P.lhs[row], rhs = P.rhs[row];
     RowState R = make_row_state(L.smin, L.smax, L.emin, L.emax, L.cmin, L.cmax, lhs, rhs,
                                 (exact_mask >> t) & 1u);
@@ -820,10 +827,10 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
                                            const double2* __restrict__ cur, uint32_t stride,
                                            uint32_t node_mask, SegPartial* parts,
                                            uint32_t pstride, uint32_t node0, bool marked = false,
-                                           int r_round = 0) {
+                                           int r_round = 0, const int32_t* marks = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
   const SegDesc sd = P.segs[s];
-  if (marked && P.row_mark[sd.row] != r_round) return;
+  if (marked && marks[sd.row] != r_round) return;
   // the segment's region is padded to whole 64-entry steps (zero
   // coefficients, column 0), so it is walked like a chunk of one 64-lane row
   const int W = (sd.len + kWave - 1) / kWave;
@@ -864,12 +871,15 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
 __device__ __forceinline__ void seg_phase1_nodes(const Problem& P, int s,
                                                  const double2* __restrict__ cur,
                                                  uint32_t node_mask, SegPartial* parts,
-                                                 uint32_t pstride, uint32_t node0) {
+                                                 uint32_t pstride, uint32_t node0,
+                                                 bool marked = false, int r_round = 0,
+                                                 const int32_t* marks = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t t = lane & (kNodeGroup - 1);
   const int e = lane >> 3;
   const bool on = (node_mask >> t) & 1u;
   const SegDesc sd = P.segs[s];
+  if (marked && marks[sd.row] != r_round) return;
   const int nblk = (sd.len + 7) / 8;  // the region is padded to whole 64-entry steps
   LaneAcc L;
   lane_acc_init(L);
@@ -958,10 +968,10 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
                                            double2* __restrict__ nxt, uint32_t stride, uint32_t t,
                                            const SegPartial* parts, uint32_t pstride,
                                            uint32_t node, bool force_exact, bool marked = false,
-                                           int r_round = 0) {
+                                           int r_round = 0, const int32_t* marks = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
   const SegDesc sd = P.segs[s];
-  if (marked && P.row_mark[sd.row] != r_round) return;
+  if (marked && marks[sd.row] != r_round) return;
   DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
   double emin = 0.0, emax = 0.0;
   int cmin = 0, cmax = 0;

@@ -68,6 +68,16 @@ struct prop_problem {
   // first prop_set_marking(p, 1)
   bool marking = false;
   bool mark_ready = false;
+  double2* d_parent = nullptr;   // prop_set_parent's copy (P.parent points here when set)
+  // marked batches: per-group row stamps, bitmaps and flags, for
+  // mark_groups groups (grown on demand, kept until destroy)
+  int32_t mark_groups = 0;
+  std::vector<void*> mark_allocs;
+  int32_t* mark_rows = nullptr;  // [mark_groups][n_rows]
+  uint64_t* mark_chg = nullptr;  // [mark_groups][ceil(n / 64) + 1]
+  uint32_t* mark_gall = nullptr; // [mark_groups]
+  uint32_t* mark_gcnt = nullptr; // [mark_groups]
+  int32_t bgraph_marking = -1;
   // graph driver: one captured batch of rounds per done-flag slot
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;

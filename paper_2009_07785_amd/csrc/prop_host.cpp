@@ -111,6 +111,7 @@ void release(prop_problem* p) {
   for (auto& e : p->kev)
     if (e) hipEventDestroy(e);
   for (void* a : p->batch_allocs) hipFree(a);
+  for (void* a : p->mark_allocs) hipFree(a);
   if (p->h_bstatus) hipHostFree(p->h_bstatus);
   if (p->h_brounds) hipHostFree(p->h_brounds);
   if (p->d_bstage_lb) hipFree(p->d_bstage_lb);
@@ -303,7 +304,8 @@ int ensure_graphs(prop_problem* p) {
 // The same for batches of `bt.nodes` nodes (the batch kernels carry the
 // workspace by value: a new workspace or node count recaptures).
 int ensure_batch_graphs(prop_problem* p, const Batch& bt) {
-  if (p->bgexec[0] && p->bgraph_nodes == bt.nodes) return PROP_OK;
+  const int32_t marking = bt.row_mark ? 1 : 0;
+  if (p->bgexec[0] && p->bgraph_nodes == bt.nodes && p->bgraph_marking == marking) return PROP_OK;
   drop_batch_graphs(p);
   if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
   for (int slot = 0; slot < 2; ++slot) {
@@ -325,6 +327,7 @@ int ensure_batch_graphs(prop_problem* p, const Batch& bt) {
     }
   }
   p->bgraph_nodes = bt.nodes;
+  p->bgraph_marking = marking;
   return PROP_OK;
 }
 
@@ -345,6 +348,7 @@ int run_loop(prop_problem* p, int32_t max_rounds, hipStream_t s) {
       // the host, and at most two batches of early-exit launches follow
       // convergence.
       HIP_TRY(launch_start(P, max_rounds, s));
+      if (P.marking && P.parent) HIP_TRY(launch_seed(P, s));
       int slot = 0;
       bool pending[2] = {false, false};
       for (int r = 1; r <= max_rounds;) {
@@ -370,6 +374,7 @@ int run_loop(prop_problem* p, int32_t max_rounds, hipStream_t s) {
       // as the stream driver, with each batch one replay of a captured graph
       // (rounds past the limit find the done flag set and exit at once)
       HIP_TRY(launch_start(P, max_rounds, s));
+      if (P.marking && P.parent) HIP_TRY(launch_seed(P, s));
       const int rc = ensure_graphs(p);
       if (rc) return rc;
       int slot = 0;
@@ -389,6 +394,7 @@ int run_loop(prop_problem* p, int32_t max_rounds, hipStream_t s) {
     }
     default:
       HIP_TRY(launch_start(P, max_rounds, s));
+      if (P.marking && P.parent) HIP_TRY(launch_seed(P, s));
       for (int r = 1; r <= max_rounds; ++r) {
         const int rc = queue_round(p, r, max_rounds, s);
         if (rc) return rc;
@@ -466,6 +472,39 @@ int ensure_batch(prop_problem* p, int32_t nodes) {
   return PROP_OK;
 }
 
+// Marked batches: row stamps, changed-variable bitmaps and flags for
+// `groups` groups, grown on demand (the previous arrays are dropped).
+int ensure_batch_marks(prop_problem* p, int32_t groups) {
+  if (groups <= p->mark_groups) return PROP_OK;
+  drop_batch_graphs(p);
+  for (void* a : p->mark_allocs) hipFree(a);
+  p->mark_allocs.clear();
+  p->mark_groups = 0;
+  auto alloc = [&](void** ptr, size_t bytes) -> int {
+    hipError_t e = hipMalloc(ptr, bytes > 0 ? bytes : 1);
+    if (e != hipSuccess)
+      return fail(PROP_ENOMEM, "batch marking hipMalloc(%zu bytes): %s", bytes,
+                  hipGetErrorString(e));
+    p->mark_allocs.push_back(*ptr);
+    return PROP_OK;
+  };
+  const size_t rows = (size_t)(p->P.n_rows > 0 ? p->P.n_rows : 1);
+  const size_t words = (size_t)(p->n + kWave - 1) / kWave + 1;
+  int rc;
+  void *marks, *chg, *gall, *gcnt;
+  if ((rc = alloc(&marks, (size_t)groups * rows * sizeof(int32_t)))) return rc;
+  if ((rc = alloc(&chg, (size_t)groups * words * sizeof(uint64_t)))) return rc;
+  if ((rc = alloc(&gall, (size_t)groups * sizeof(uint32_t)))) return rc;
+  if ((rc = alloc(&gcnt, (size_t)groups * sizeof(uint32_t)))) return rc;
+  HIP_TRY(hipMemset(marks, 0, (size_t)groups * rows * sizeof(int32_t)));
+  p->mark_groups = groups;
+  p->mark_rows = static_cast<int32_t*>(marks);
+  p->mark_chg = static_cast<uint64_t*>(chg);
+  p->mark_gall = static_cast<uint32_t*>(gall);
+  p->mark_gcnt = static_cast<uint32_t*>(gcnt);
+  return PROP_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -537,6 +576,45 @@ void tune_store(uint64_t sig, int32_t steps) {
 }
 
 }  // namespace
+
+// Uploads what marked rounds need (the rows of every variable in pieces for
+// the mark kernels, the row stamps, the changed-variable bitmap), once.
+int ensure_mark_data(prop_problem* p) {
+  if (!p->mark_ready) {
+    HIP_TRY(hipSetDevice(p->device));
+    Problem& P = p->P;
+    int64_t *vp, *poff;
+    int32_t *vr, *marks, *pvar;
+    uint64_t* bits;
+    int rc;
+    // pieces of <= kMarkPiece rows of one variable, one mark-kernel thread each
+    std::vector<int32_t> h_pvar;
+    std::vector<int64_t> h_poff;
+    for (int32_t v = 0; v < p->n; ++v)
+      for (int64_t q = p->h_var_ptr[v]; q < p->h_var_ptr[(size_t)v + 1]; q += kMarkPiece) {
+        h_pvar.push_back(v);
+        h_poff.push_back(q);
+      }
+    if ((rc = dev_upload(p, &vp, p->h_var_ptr))) return rc;
+    if ((rc = dev_upload(p, &vr, p->h_var_rows))) return rc;
+    if ((rc = dev_upload(p, &pvar, h_pvar))) return rc;
+    if ((rc = dev_upload(p, &poff, h_poff))) return rc;
+    if ((rc = dev_alloc(p, &marks, (size_t)(P.n_rows > 0 ? P.n_rows : 1)))) return rc;
+    HIP_TRY(hipMemset(marks, 0, sizeof(int32_t) * (size_t)(P.n_rows > 0 ? P.n_rows : 1)));
+    if ((rc = dev_alloc(p, &bits, (size_t)(p->n + kWave - 1) / kWave + 1))) return rc;
+    P.var_ptr = vp;
+    P.var_rows = vr;
+    P.row_mark = marks;
+    P.chg_bits = bits;
+    P.piece_var = pvar;
+    P.piece_off = poff;
+    P.n_pieces = (int64_t)h_pvar.size();
+    std::vector<int64_t>().swap(p->h_var_ptr);
+    std::vector<int32_t>().swap(p->h_var_rows);
+    p->mark_ready = true;
+  }
+  return PROP_OK;
+}
 
 extern "C" {
 
@@ -726,18 +804,32 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
   HIP_TRY(hipSetDevice(p->device));
   int rc = ensure_batch(p, nodes);
   if (rc) return rc;
+  const int32_t groups = (nodes + kNodeGroup - 1) / kNodeGroup;
+  if (p->marking) {
+    if ((rc = ensure_mark_data(p))) return rc;
+    if ((rc = ensure_batch_marks(p, groups))) return rc;
+  }
   p->P.marking = 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Problem& P = p->P;
   Batch bt = p->bt;
   bt.nodes = nodes;
-  bt.groups = (nodes + kNodeGroup - 1) / kNodeGroup;
+  bt.groups = groups;
+  if (p->marking) {
+    // marked rounds per group (rows of variables changed in any of the
+    // group's nodes); with a parent, round 1 is marked too
+    bt.row_mark = p->mark_rows;
+    bt.chg = p->mark_chg;
+    bt.gall = p->mark_gall;
+    bt.gcnt = p->mark_gcnt;
+  }
   HIP_TRY(hipEventRecord(p->ev[0], s));
   HIP_TRY(launch_init(P, s));
   HIP_TRY(hipMemsetAsync(bt.invalid, 0, nodes * sizeof(uint32_t), s));
   HIP_TRY(hipMemsetAsync(bt.infeasible, 0, nodes * sizeof(uint32_t), s));
   HIP_TRY(launch_pack_batch(P, bt, d_lb, d_ub, 0, nodes, s));
   HIP_TRY(launch_start_batch(P, bt, max_rounds, 0, nodes, true, s));
+  if (bt.row_mark && P.parent) HIP_TRY(launch_seed_batch(P, bt, s));
   HIP_TRY(hipEventRecord(p->ev[1], s));
   // rounds in batches; the done flag and the active-node count are read one
   // batch behind (see the stream driver of single runs).  When the active
@@ -937,40 +1029,37 @@ int prop_set_loop(prop_problem* p, int32_t mode) {
 
 int prop_set_marking(prop_problem* p, int32_t enable) {
   if (!p) return fail(PROP_EINVAL, "NULL problem");
-  if (enable && !p->mark_ready) {
-    HIP_TRY(hipSetDevice(p->device));
-    Problem& P = p->P;
-    int64_t *vp, *poff;
-    int32_t *vr, *marks, *pvar;
-    uint64_t* bits;
-    int rc;
-    // pieces of <= kMarkPiece rows of one variable, one mark-kernel thread each
-    std::vector<int32_t> h_pvar;
-    std::vector<int64_t> h_poff;
-    for (int32_t v = 0; v < p->n; ++v)
-      for (int64_t q = p->h_var_ptr[v]; q < p->h_var_ptr[(size_t)v + 1]; q += kMarkPiece) {
-        h_pvar.push_back(v);
-        h_poff.push_back(q);
-      }
-    if ((rc = dev_upload(p, &vp, p->h_var_ptr))) return rc;
-    if ((rc = dev_upload(p, &vr, p->h_var_rows))) return rc;
-    if ((rc = dev_upload(p, &pvar, h_pvar))) return rc;
-    if ((rc = dev_upload(p, &poff, h_poff))) return rc;
-    if ((rc = dev_alloc(p, &marks, (size_t)(P.n_rows > 0 ? P.n_rows : 1)))) return rc;
-    HIP_TRY(hipMemset(marks, 0, sizeof(int32_t) * (size_t)(P.n_rows > 0 ? P.n_rows : 1)));
-    if ((rc = dev_alloc(p, &bits, (size_t)(p->n + kWave - 1) / kWave + 1))) return rc;
-    P.var_ptr = vp;
-    P.var_rows = vr;
-    P.row_mark = marks;
-    P.chg_bits = bits;
-    P.piece_var = pvar;
-    P.piece_off = poff;
-    P.n_pieces = (int64_t)h_pvar.size();
-    std::vector<int64_t>().swap(p->h_var_ptr);
-    std::vector<int32_t>().swap(p->h_var_rows);
-    p->mark_ready = true;
+  if (enable) {
+    const int rc = ensure_mark_data(p);
+    if (rc) return rc;
   }
   p->marking = enable != 0;
+  return PROP_OK;
+}
+
+int prop_set_parent(prop_problem* p, const double* d_lb, const double* d_ub, void* stream) {
+  if (!p) return fail(PROP_EINVAL, "NULL problem");
+  if (!d_lb && !d_ub) {
+    p->P.parent = nullptr;
+    return PROP_OK;
+  }
+  if (p->n > 0 && (!d_lb || !d_ub)) return fail(PROP_EINVAL, "one parent bound array is NULL");
+  HIP_TRY(hipSetDevice(p->device));
+  int rc = ensure_mark_data(p);
+  if (rc) return rc;
+  if (!p->d_parent && (rc = dev_alloc(p, &p->d_parent, (size_t)(p->n > 0 ? p->n : 1)))) return rc;
+  p->P.parent = nullptr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  p->h_ctrl->invalid = 0;
+  HIP_TRY(hipMemcpyAsync(&p->P.ctrl->invalid, &p->h_ctrl->invalid, sizeof(uint32_t),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_set_parent(p->P, p->d_parent, d_lb, d_ub, s));
+  HIP_TRY(hipMemcpyAsync(&p->h_ctrl->invalid, &p->P.ctrl->invalid, sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (p->h_ctrl->invalid)
+    return fail(PROP_EINVAL, "parent: a bound is NaN, +inf as lower, -inf as upper, or beyond 2^200");
+  p->P.parent = p->d_parent;
   return PROP_OK;
 }
 

@@ -148,10 +148,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = blockIdx.x * kWavesPerBlock + wave;
   const bool marked = marked_round(P);
-  if (item < P.n_segs) seg_phase1<true>(P, item, P.bnd[0], 1, 1, P.partials, 1, 0, marked, r);
+  if (item < P.n_segs)
+    seg_phase1<true>(P, item, P.bnd[0], 1, 1, P.partials, 1, 0, marked, r, P.row_mark);
   else if (item - P.n_segs < P.n_chunks)
     chunk_dispatch<true>(P, item - P.n_segs, P.bnd[0], P.bnd[1], 1, 1,
-                   u32_load(&P.ctrl->tiny) ? 1u : 0u, marked, r);
+                         u32_load(&P.ctrl->tiny) ? 1u : 0u, marked, r, P.row_mark);
 }
 
 __global__ __launch_bounds__(kBlock) void k_round_long(Problem P) {
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_round_long(Problem P) {
   const int s = blockIdx.x * kWavesPerBlock + wave;
   if (s < P.n_segs)
     seg_phase2<true>(P, s, P.bnd[0], P.bnd[1], 1, 0, P.partials, 1, 0,
-                     u32_load(&P.ctrl->tiny) != 0, marked_round(P), r);
+                     u32_load(&P.ctrl->tiny) != 0, marked_round(P), r, P.row_mark);
 }
 
 // Marked rounds, after the commit of round r: stamps the rows of every
@@ -179,6 +180,54 @@ __global__ __launch_bounds__(kBlock) void k_mark(Problem P) {
     const int64_t start = P.piece_off[q];
     const int64_t stop = P.var_ptr[v + 1] < start + kMarkPiece ? P.var_ptr[v + 1] : start + kMarkPiece;
     for (int64_t i = start; i < stop; ++i) P.row_mark[P.var_rows[i]] = next;
+  }
+}
+
+// Marked runs from a parent fixed point, after the start kernel: bit v of
+// the changed-variable bitmap is set when variable v's start bounds differ
+// from the parent's, and round 1 becomes a marked round; k_mark then stamps
+// the rows of those variables with round 1.  Every other row would compute
+// the candidates the parent's last round computed from the same bounds, and
+// none of those counted (the parent is a fixed point).
+__global__ __launch_bounds__(kBlock) void k_seed(Problem P) {
+  Ctrl* C = P.ctrl;
+  if (u32_load(&C->done)) return;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t words = ((uint32_t)P.n + kWave - 1) / kWave;
+  const uint32_t nw = gridDim.x * kWavesPerBlock;
+  for (uint32_t w = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); w < words; w += nw) {
+    const uint32_t v = w * kWave + lane;
+    bool diff = false;
+    if (v < (uint32_t)P.n) {
+      const double2 a = P.bnd[0][v];
+      const double2 b = P.parent[v];
+      diff = a.x != b.x || a.y != b.y;
+    }
+    const uint64_t bits = __ballot(diff);
+    if (lane == 0) P.chg_bits[w] = bits;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) C->mark_all = 0;
+}
+
+// The parent's bounds, validated and integer-rounded as the pack kernel
+// does, into internal order.
+__global__ __launch_bounds__(kBlock) void k_set_parent(Problem P, double2* __restrict__ parent,
+                                                       const double* __restrict__ ulb,
+                                                       const double* __restrict__ uub) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)P.n; v += stride) {
+    double l = ulb[v], u = uub[v];
+    const bool bad = __builtin_isnan(l) || __builtin_isnan(u) || l == __builtin_inf() ||
+                     u == -__builtin_inf() ||
+                     (!is_inf(l) && __builtin_fabs(l) > PROP_HUGE) ||
+                     (!is_inf(u) && __builtin_fabs(u) > PROP_HUGE);
+    if (bad) __hip_atomic_store(&P.ctrl->invalid, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t j = P.perm[v];
+    if (P.vtype[j] != 0) {
+      l = __builtin_ceil(l - P.eps_int);
+      u = __builtin_floor(u + P.eps_int);
+    }
+    parent[j] = make_double2(l + 0.0, u + 0.0);
   }
 }
 
@@ -248,6 +297,20 @@ hipError_t launch_persistent(const Problem& P, int max_rounds, int grid, hipStre
   void* args[] = {(void*)&p, (void*)&max_rounds};
   return hipLaunchCooperativeKernel((const void*)k_persistent, dim3(grid), dim3(kBlock), args, 0,
                                     s);
+}
+
+hipError_t launch_seed(const Problem& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_seed, dim3(blocks_for(((int64_t)P.n + kWave - 1) / kWave, kWavesPerBlock, 4096)),
+                     dim3(kBlock), 0, s, P);
+  hipLaunchKernelGGL(k_mark, dim3(1024), dim3(kBlock), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_parent(const Problem& P, double2* parent, const double* lb,
+                             const double* ub, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_parent, dim3(blocks_for(P.n, kBlock, 4096)), dim3(kBlock), 0, s, P,
+                     parent, lb, ub);
+  return hipGetLastError();
 }
 
 hipError_t launch_start(const Problem& P, int max_rounds, hipStream_t s) {

@@ -30,6 +30,15 @@ hipError_t launch_unpack_batch(const Problem& P, const Batch& Bt, double* lb, do
 hipError_t launch_start_batch(const Problem& P, const Batch& Bt, int max_rounds, int k0, int cnt,
                               bool whole, hipStream_t s);
 hipError_t launch_round_batch(const Problem& P, const Batch& Bt, hipStream_t s);
+// Marked batches from a parent fixed point: stamps, for round 1, the rows of
+// the variables whose start bounds differ from the parent's (per group).
+hipError_t launch_seed_batch(const Problem& P, const Batch& Bt, hipStream_t s);
+// Marked single runs from a parent fixed point: the same for one bound vector.
+hipError_t launch_seed(const Problem& P, hipStream_t s);
+// Normalises (integer rounding) and relabels a parent fixed point into
+// P.parent; sets the control block's invalid flag for a bad bound.
+hipError_t launch_set_parent(const Problem& P, double2* parent, const double* lb,
+                             const double* ub, hipStream_t s);
 // Compaction of a batch: slot moves (moves[q].x -> moves[q].y, device
 // array) and unpacking of listed slots (pairs[q] = (slot, caller's row)).
 hipError_t launch_move_batch(const Problem& P, const Batch& Bt, const int2* moves, int count,

@@ -75,6 +75,9 @@ struct Problem {
   const int32_t* piece_var; // [n_pieces] variable of each piece of <= kMarkPiece rows
   const int64_t* piece_off; // [n_pieces] first entry of the piece in var_rows
   int64_t n_pieces;
+  // marked runs from a parent: the parent's bounds (a fixed point of this
+  // problem's propagation, integer-rounded, internal order), else null
+  const double2* parent;    // [n]
 };
 
 // Rows of a variable that one thread of the mark kernel stamps; a round
@@ -105,6 +108,12 @@ struct Batch {
   int32_t* maxr;           // [nodes] round limit of each node
   uint32_t* live;          // [nodes] serving only (else null): finished, not yet reported
   uint32_t* tiny;          // [nodes] a bound of the node's run has 0 < |b| < 2^-906
+  // marked rounds of batches (null when off): a group processes a row in
+  // round r only when row_mark[g * n_rows + row] == r, unless gall[g] is set
+  int32_t* row_mark;       // [groups][n_rows]
+  uint64_t* chg;           // [groups][ceil(n / 64)] variables changed in any node of the group
+  uint32_t* gall;          // [groups] the group's next round processes every row
+  uint32_t* gcnt;          // [groups] variables that differ from the parent (seeded runs)
   int32_t nodes;
   int32_t groups;
 };

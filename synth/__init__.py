@@ -17,6 +17,7 @@ from .instances import (  # noqa: F401
     config4_pool,
     config4_requests,
     from_rows,
+    branch_children,
     code_edges,
     hard_sums,
     layout_mix,

@@ -307,6 +307,28 @@ def node_bounds(inst: Instance, seed: int, frac_lo=0.01, frac_hi=0.05, only_int=
     return lb, ub
 
 
+def branch_children(parent_lb, parent_ub, vartype, count: int, seed: int, per_child: int = 1):
+    """Branch-and-bound children of a node whose bounds are (parent_lb,
+    parent_ub): child 2i and 2i + 1 split the domain of the same unfixed
+    integer variables (`per_child` of them) at the middle, the first keeping
+    the lower half, the second the upper half.  Returns (lbs, ubs) of shape
+    (count, n)."""
+    rng = _rng(seed)
+    lbs = np.repeat(np.asarray(parent_lb, dtype=np.float64)[None, :], count, axis=0)
+    ubs = np.repeat(np.asarray(parent_ub, dtype=np.float64)[None, :], count, axis=0)
+    free = np.nonzero((vartype == 1) & (parent_lb < parent_ub) & np.isfinite(parent_lb)
+                      & np.isfinite(parent_ub))[0]
+    if free.size == 0:
+        return lbs, ubs
+    for i in range(0, count, 2):
+        pick = rng.choice(free, size=min(per_child, free.size), replace=False)
+        mid = np.floor((parent_lb[pick] + parent_ub[pick]) / 2.0)
+        ubs[i, pick] = mid
+        if i + 1 < count:
+            lbs[i + 1, pick] = mid + 1.0
+    return lbs, ubs
+
+
 def config3_nodes(inst: Instance, count: int = 256):
     lbs = np.empty((count, inst.n))
     ubs = np.empty((count, inst.n))
