@@ -187,11 +187,18 @@ def main():
                     help="skip the marked-rounds leg (rows without changed variables skipped)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving leg (open-loop requests over 64 resident instances)")
-    ap.add_argument("--serving-scale", type=float, default=0.1,
-                    help="row-count scale of the 64 serving instances (1.0 = ~360M nnz)")
-    ap.add_argument("--serving-seconds", type=float, default=5.0)
+    ap.add_argument("--serving-scale", type=float, default=1.0,
+                    help="row-count scale of the 64 serving instances (1.0 = ~386M nnz)")
+    ap.add_argument("--serving-seconds", type=float, default=60.0)
+    ap.add_argument("--serving-rate-below", type=float, default=400.0,
+                    help="a second, shorter phase at a rate the server sustains (0: none)")
+    ap.add_argument("--serving-seconds-below", type=float, default=20.0)
+    ap.add_argument("--serving-max-slots", type=int, default=256,
+                    help="slots per instance (requests of one instance running at once)")
+    ap.add_argument("--serving-max-pending", type=int, default=1024,
+                    help="requests held before submissions are refused (admission control)")
     ap.add_argument("--serving-rate", type=float, default=2000.0, help="requests per second")
-    ap.add_argument("--serving-budget-gib", type=float, default=16.0)
+    ap.add_argument("--serving-budget-gib", type=float, default=64.0)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_config2.json"),
                     help="HBM traffic per launch measured with rocprofv3 counters (JSON)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -347,7 +354,9 @@ def main():
     serve = None
     if not args.no_serving:
         serve = serving(args.serving_scale, args.serving_seconds, args.serving_rate,
-                        int(args.serving_budget_gib * (1 << 30)))
+                        int(args.serving_budget_gib * (1 << 30)), args.serving_max_pending,
+                        args.serving_rate_below, args.serving_seconds_below,
+                        args.serving_max_slots)
 
     # the CPU baseline leg: the oracle's synchronous rounds on config2 and,
     # as the paper's own comparison, its sequential Algorithm 1 on config1
@@ -600,14 +609,21 @@ def children_nodes(count: int, max_rounds: int):
     return out
 
 
-def serving(scale: float, seconds: float, rate: float, budget: int, variants: int = 8,
-            max_rounds: int = 50):
+def serving(scale: float, seconds: float, rate: float, budget: int, max_pending: int,
+            rate_below: float = 0.0, seconds_below: float = 0.0, max_slots: int = 256,
+            variants: int = 8, max_rounds: int = 50, verify: int = 1000):
     """Open-loop serving: Poisson arrivals at `rate` per second for `seconds`,
     each request a bound vector (0-5% of all variables fixed to a feasible
-    point's values) on one of 64 resident instances drawn uniformly.  Every
-    result is compared bitwise with the same request run alone; latency is
-    the server's (submission to result ready)."""
+    point's values) on one of 64 resident instances drawn uniformly.  A
+    request that finds `max_pending` requests held is refused at submission
+    (admission control: the server sheds load instead of queueing without
+    bound).  A consumer thread collects results as they finish; at least
+    `verify` of them, spread over the run, are compared bitwise with the
+    same request run alone.  Latency is the server's (submission to result
+    ready)."""
+    import queue
     import threading
+    from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
 
@@ -616,78 +632,133 @@ def serving(scale: float, seconds: float, rate: float, budget: int, variants: in
 
     log(f"generating the 64 serving instances (scale {scale})")
     t0 = time.perf_counter()
-    pool = synth.config4_pool(scale=scale)
-    probs = [Problem.from_instance(i) for i in pool]
+    workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                         else os.cpu_count() or 1))
+    pool = synth.config4_pool(scale=scale, workers=workers)
     total_nnz = int(sum(i.nnz for i in pool))
-    log(f"serving pool ready: {total_nnz} nnz in {time.perf_counter() - t0:.1f} s")
+    log(f"generated {total_nnz} nnz in {time.perf_counter() - t0:.1f} s; creating problems")
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(workers) as ex:  # prop_create releases the GIL in ctypes
+        probs = list(ex.map(Problem.from_instance, pool))
+    log(f"serving pool ready in {time.perf_counter() - t0:.1f} s")
     # `variants` distinct requests per instance; arrivals pick one by seed
     bounds = [[synth.request_bounds(inst, 1000 * k + v) for v in range(variants)]
               for k, inst in enumerate(pool)]
     alone = [[probs[k].run(lb, ub, max_rounds) for lb, ub in bounds[k]]
              for k in range(len(pool))]
-    arrivals = synth.config4_requests(pool, rate=rate, duration=seconds)
-    log(f"{len(arrivals)} arrivals over {seconds} s; alone results ready")
-
-    srv = binding.Server(budget, max_slots=256)
+    srv = binding.Server(budget, max_slots=max_slots, max_pending=max_pending)
     for p in probs:
         srv.add_instance(p)
     # warm the server: one request per instance
     for k in range(len(pool)):
         lb, ub = bounds[k][0]
         t = srv.submit(k, lb, ub, max_rounds)
-        srv.wait(t, pool[k].n, timeout_ms=60_000)
-    srv.reset_stats()
+        srv.wait(t, pool[k].n, timeout_ms=120_000, bounds=False)
 
-    tickets = []
-    lag = [0.0]
+    def phase(rate_, seconds_, seed_offset):
+        arrivals = synth.config4_requests(pool, rate=rate_, duration=seconds_,
+                                          seed_offset=seed_offset)
+        log(f"serving: {len(arrivals)} arrivals over {seconds_} s at {rate_:g} req/s")
+        srv.reset_stats()
+        every = max(1, len(arrivals) // (4 * verify))
+        tickets = queue.Queue()
+        counts = {"refused": 0, "verified": 0, "verified_ok": 0, "collected": 0}
+        lock = threading.Lock()
+        lag = [0.0]
+        n_prod = 4  # submissions validate and copy 2n doubles: several threads keep up
+        start = [0.0]
 
-    def producer():
-        start = time.perf_counter()
-        for (ta, k, seed) in arrivals:
-            now = time.perf_counter() - start
-            if ta > now:
-                time.sleep(ta - now)
-            else:
-                lag[0] = max(lag[0], now - ta)
-            v = seed % variants
-            lb, ub = bounds[k][v]
-            tickets.append((srv.submit(k, lb, ub, max_rounds), k, v))
+        def producer(j):
+            for i in range(j, len(arrivals), n_prod):
+                ta, k, seed = arrivals[i]
+                now = time.perf_counter() - start[0]
+                if ta > now:
+                    time.sleep(ta - now)
+                elif now - ta > lag[0]:
+                    lag[0] = now - ta
+                v = seed % variants
+                lb, ub = bounds[k][v]
+                try:
+                    tickets.put((srv.submit(k, lb, ub, max_rounds), k, v, i % every == 0))
+                except binding.PropError as e:
+                    if e.code != binding.EBUSY:
+                        raise
+                    with lock:
+                        counts["refused"] += 1
+            tickets.put(None)
 
-    th = threading.Thread(target=producer)
-    th.start()
-    th.join()
-    ok = 0
-    for t, k, v in tickets:
-        res, lb, ub = srv.wait(t, pool[k].n, timeout_ms=120_000)
-        r1, lb1, ub1 = alone[k][v]
-        same = (res.status, res.rounds) == (r1.status, r1.rounds) and (
-            r1.status == 1 or (np.array_equal(lb, lb1) and np.array_equal(ub, ub1)))
-        ok += bool(same)
-    st = srv.stats()
+        def consumer():
+            done = 0
+            while True:
+                item = tickets.get()
+                if item is None:
+                    done += 1
+                    if done == n_prod:
+                        return
+                    continue
+                t, k, v, check = item
+                res, lb, ub = srv.wait(t, pool[k].n, timeout_ms=300_000, bounds=check)
+                counts["collected"] += 1
+                if check:
+                    r1, lb1, ub1 = alone[k][v]
+                    same = (res.status, res.rounds) == (r1.status, r1.rounds) and (
+                        r1.status == 1 or (np.array_equal(lb, lb1) and np.array_equal(ub, ub1)))
+                    counts["verified"] += 1
+                    counts["verified_ok"] += bool(same)
+
+        th_p = [threading.Thread(target=producer, args=(j,)) for j in range(n_prod)]
+        th_c = threading.Thread(target=consumer)
+        t_start = time.perf_counter()
+        start[0] = t_start
+        th_c.start()
+        for th in th_p:
+            th.start()
+        for th in th_p:
+            th.join()
+        th_c.join()
+        wall = time.perf_counter() - t_start
+        st = srv.stats()
+        out = {
+            "offered": len(arrivals),
+            "offered_per_s": len(arrivals) / seconds_,
+            "seconds": seconds_,
+            "admitted": len(arrivals) - counts["refused"],
+            "refused_busy": counts["refused"],
+            "completed": st["completed"],
+            "req_per_s": st["req_per_s"],
+            "served_per_s_wall": counts["collected"] / wall,
+            "p50_ms": st["p50_ms"],
+            "p99_ms": st["p99_ms"],
+            "mean_ms": st["mean_ms"],
+            "max_ms": st["max_ms"],
+            "verified": counts["verified"],
+            "verified_fraction": counts["verified_ok"] / max(1, counts["verified"]),
+            "submit_lag_max_ms": lag[0] * 1e3,
+            "peak_device_bytes": st["peak_device_bytes"],
+            "round_steps": st["steps"],
+        }
+        log(f"serving at {rate_:g} req/s: {out}")
+        return out
+
+    main = phase(rate, seconds, 0)
+    below = phase(rate_below, seconds_below, 1) if rate_below > 0 else None
     srv.close()
     for p in probs:
         p.close()
     rounds = [r[0].rounds for row in alone for r in row]
     out = {
         "workload": f"config4: 64 instances at row scale {scale} ({total_nnz} nnz resident), "
-                    f"open-loop Poisson {rate:g} req/s for {seconds:g} s, 0-5% of the variables "
-                    f"fixed per request, max_rounds {max_rounds}",
-        "requests": len(tickets),
-        "completed": st["completed"],
-        "req_per_s": st["req_per_s"],
-        "p50_ms": st["p50_ms"],
-        "p99_ms": st["p99_ms"],
-        "mean_ms": st["mean_ms"],
-        "max_ms": st["max_ms"],
-        "verified_fraction": ok / max(1, len(tickets)),
-        "verified_against": "the same request run alone (prop_run), bitwise",
-        "alone_rounds_mean": float(np.mean(rounds)),
-        "submit_lag_max_ms": lag[0] * 1e3,
-        "peak_device_bytes": st["peak_device_bytes"],
+                    f"open-loop Poisson arrivals, 0-5% of the variables fixed per request, "
+                    f"max_rounds {max_rounds}",
+        **main,
+        "max_pending": max_pending,
+        "max_slots": max_slots,
         "budget_bytes": budget,
-        "round_steps": st["steps"],
+        "verified_against": "the same request run alone (prop_run), bitwise, on a sample spread "
+                            "over the run",
+        "alone_rounds_mean": float(np.mean(rounds)),
+        "below_capacity": below,
     }
-    log(f"serving: {out}")
     return out
 
 

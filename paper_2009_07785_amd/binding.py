@@ -432,24 +432,27 @@ class Server:
                                    ctypes.byref(t)))
         return t.value
 
-    def _take(self, fn, ticket, *extra, n):
-        lb = np.empty(n)
-        ub = np.empty(n)
+    def _take(self, fn, ticket, *extra, n, bounds=True):
+        lb = np.empty(n) if bounds else None
+        ub = np.empty(n) if bounds else None
         res = _Result()
-        rc = fn(self._h, ctypes.c_int64(ticket), *extra, ctypes.byref(res), _ptr(lb), _ptr(ub))
+        rc = fn(self._h, ctypes.c_int64(ticket), *extra, ctypes.byref(res),
+                _ptr(lb) if bounds else None, _ptr(ub) if bounds else None)
         if rc < 0:
             raise PropError(rc, last_error())
         if rc == 0:
             return None
         return RunResult(res.status, res.rounds), lb, ub
 
-    def poll(self, ticket: int, n: int):
+    def poll(self, ticket: int, n: int, bounds: bool = True):
         """(RunResult, lb, ub) once finished (releasing the ticket), else None.
-        n is the instance's variable count."""
-        return self._take(lib.prop_srv_poll, ticket, n=n)
+        n is the instance's variable count; with bounds=False the bounds are
+        not copied (lb, ub are None)."""
+        return self._take(lib.prop_srv_poll, ticket, n=n, bounds=bounds)
 
-    def wait(self, ticket: int, n: int, timeout_ms: int = -1):
-        return self._take(lib.prop_srv_wait, ticket, ctypes.c_int32(int(timeout_ms)), n=n)
+    def wait(self, ticket: int, n: int, timeout_ms: int = -1, bounds: bool = True):
+        return self._take(lib.prop_srv_wait, ticket, ctypes.c_int32(int(timeout_ms)), n=n,
+                          bounds=bounds)
 
     def stats(self) -> dict:
         st = _SrvStats()

@@ -648,6 +648,9 @@ int prop_srv_submit(prop_server* s, int32_t id, const double* lb, const double* 
                   "one slot group of instance %d (%lld bytes) does not fit the budget beside "
                   "the server's fixed state (%lld bytes)",
                   id, (long long)group_bytes(n), (long long)s->fixed_bytes);
+    // refuse before validating and copying the bounds (checked again below)
+    if (s->held >= s->cfg.max_pending)
+      return fail(PROP_EBUSY, "%lld requests held", (long long)s->held);
   }
   if (n > 0 && (!lb || !ub)) return fail(PROP_EINVAL, "bound arrays are NULL");
   for (int32_t j = 0; j < n; ++j)

@@ -337,18 +337,34 @@ def config3_nodes(inst: Instance, count: int = 256):
     return lbs, ubs
 
 
-def config4_pool(count: int = 64, m_lo: float = 1e4, m_hi: float = 2e6, scale: float = 1.0):
-    """The serving pool; `scale` shrinks every instance (tests use < 1)."""
+def _config4_instance(args):
+    k, mk = args
+    mk = max(int(mk), 10)
+    nk = max(mk // 2, 5)
+    sub = _rng(BASE_SEED + 4000 + k)
+    return _lognormal_instance(sub, mk, nk, f"config4[{k}]", dense_len=min(5000, nk))
+
+
+def config4_pool(count: int = 64, m_lo: float = 1e4, m_hi: float = 2e6, scale: float = 1.0,
+                 workers: int = 1):
+    """The serving pool; `scale` shrinks every instance (tests use < 1).
+    Every instance has its own seed, so `workers` processes may generate
+    them side by side with the same result."""
     rng = _rng(BASE_SEED + 4)
     ms = np.rint(np.exp(rng.uniform(np.log(m_lo), np.log(m_hi), size=count)) * scale)
-    pool = []
-    for k, mk in enumerate(ms.astype(np.int64)):
-        mk = max(int(mk), 10)
-        nk = max(mk // 2, 5)
-        sub = _rng(BASE_SEED + 4000 + k)
-        pool.append(_lognormal_instance(sub, mk, nk, f"config4[{k}]",
-                                        dense_len=min(5000, nk)))
-    return pool
+    jobs = list(enumerate(ms.astype(np.int64)))
+    if workers <= 1:
+        return [_config4_instance(j) for j in jobs]
+    import multiprocessing as mp
+
+    # largest first, so that the big instances do not finish last
+    order = sorted(range(count), key=lambda k: -int(ms[k]))
+    with mp.get_context("fork").Pool(workers) as pool:
+        made = pool.map(_config4_instance, [jobs[k] for k in order], chunksize=1)
+    out = [None] * count
+    for k, inst in zip(order, made):
+        out[k] = inst
+    return out
 
 
 def config4_requests(pool, rate: float = 2000.0, duration: float = 60.0, seed_offset: int = 0):
