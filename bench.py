@@ -178,6 +178,8 @@ def main():
     ap.add_argument("--no-loop-compare", action="store_true")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 2,000 x 1,000 and 200,000 x 100,000 single-instance lines")
+    ap.add_argument("--no-layouts", action="store_true",
+                    help="skip the nnz-split layout comparison")
     ap.add_argument("--no-children", action="store_true",
                     help="skip the branch-and-bound children leg (marked rounds from a parent)")
     ap.add_argument("--no-batch", action="store_true",
@@ -347,6 +349,7 @@ def main():
         log(f"marked rounds: {marked}")
 
     small = None if args.no_small else small_configs(args.max_rounds)
+    layouts = None if args.no_layouts else layout_compare(args.max_rounds, inst)
 
     batch = None if args.no_batch else batched_nodes(args.batch_nodes, args.max_rounds)
     children = None if args.no_children else children_nodes(args.batch_nodes, args.max_rounds)
@@ -404,6 +407,7 @@ def main():
         "round_loops": loops,
         "marked": marked,
         "small_configs": small,
+        "layouts": layouts,
         "batched": batch,
         "children": children,
         "serving": serve,
@@ -450,6 +454,54 @@ def small_configs(max_rounds: int, reps: int = 20):
                     "nnz_per_s": info["nnz"] * r.rounds / (ms * 1e-3),
                     "alg_GBps": gbps, "frac": gbps / HBM_PEAK_GBS}
     log(f"small configs: {out}")
+    return out
+
+
+def layout_compare(max_rounds: int, inst2, reps: int = 6):
+    """The nnz-split layout (merge-path style: rows in input order packed
+    into 512-entry waves, 8 consecutive entries per lane, rows spanning
+    lanes joined by a segmented scan) against the default length-class
+    chunks, on the 5,000,000 x 2,000,000 and 200,000 x 100,000 instances:
+    round-kernel time per launch and full-run time, identical results
+    required."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2009_07785_amd import Problem
+
+    dev = torch.device("cuda:0")
+    out = {}
+    for key in ("config2", "config1"):
+        inst = inst2 if key == "config2" else synth.cached("config1_bench", synth.config1, 1)
+        res = {}
+        for name, kw in (("chunks", {}), ("nnz_split", {"layout": 1})):
+            p = Problem.from_instance(inst, **kw)
+            p.set_loop("stream")
+            p.set_kernel_timing(True)
+            rl = torch.tensor(inst.lb, dtype=torch.float64, device=dev)
+            ru = torch.tensor(inst.ub, dtype=torch.float64, device=dev)
+            dl, du = torch.empty_like(rl), torch.empty_like(ru)
+            lm, km, kn = [], [], []
+            for i in range(reps + 1):
+                dl.copy_(rl)
+                du.copy_(ru)
+                r = p.run_device(dl, du, max_rounds)
+                if i:
+                    lm.append(p.last_timing()[0])
+                    a, b = p.last_kernel_timing()
+                    km.append(a)
+                    kn.append(b)
+            res[name] = {"loop_ms": float(np.median(lm)),
+                         "round_kernel_us": 1e3 * float(np.sum(km)) / max(1, int(np.sum(kn))),
+                         "stored_entries": p.info()["nnz_stored"],
+                         "result": (r.status, r.rounds, dl.cpu().numpy().tobytes(),
+                                    du.cpu().numpy().tobytes())}
+            p.close()
+        same = res["chunks"].pop("result") == res["nnz_split"].pop("result")
+        out[key] = {**res, "identical_results": same,
+                    "nnz_split_over_chunks": res["nnz_split"]["loop_ms"] / res["chunks"]["loop_ms"]}
+    log(f"layouts: {out}")
     return out
 
 

@@ -101,7 +101,14 @@ typedef struct {
                           prop_autotune recorded for a matrix of this shape, else by
                           size: 4 up to 100,000 stored entries, 8 up to 5,000,000,
                           16 above */
-  int32_t reserved;    /* must be 0 */
+  int32_t layout;      /* 0: rows in length classes, K lanes per row, in wave-sized
+                          chunks (default); 1: nnz split (merge-path style): rows in
+                          input order packed into waves of 512 entries, 8 consecutive
+                          entries per lane, rows spanning lanes joined by a segmented
+                          scan, rows longer than 512 entries in segments (steps is
+                          then ignored).  Layout 1 serves single runs only (batches
+                          and serving return PROP_EINVAL) and processes every row in
+                          marked rounds (same results). */
 } prop_params;
 
 typedef struct {
@@ -121,7 +128,7 @@ typedef struct {
   int64_t device_bytes;    /* device memory held by the problem */
   int64_t alg_bytes_round; /* algorithmic bytes per round: 12 nnz + 20 m + 33 n + 4 */
   int32_t steps;           /* entries per lane of a short row in the layout (4, 8, 16) */
-  int32_t reserved;
+  int32_t layout;          /* prop_params.layout of the problem */
 } prop_info;
 
 /* Builds a problem on the current HIP device.  The inputs are copied; the

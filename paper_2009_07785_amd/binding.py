@@ -48,7 +48,7 @@ class _Csr(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("eps_int", ctypes.c_double), ("cont_rel_tol", ctypes.c_double),
                 ("feas_tol", ctypes.c_double), ("steps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("layout", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -61,7 +61,7 @@ class _Info(ctypes.Structure):
                 ("n_long_rows", ctypes.c_int32), ("n_segments", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("alg_bytes_round", ctypes.c_int64), ("steps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("layout", ctypes.c_int32)]
 
 
 class _SrvConfig(ctypes.Structure):
@@ -179,9 +179,10 @@ class Problem:
     """A constraint system resident on the current HIP device."""
 
     def __init__(self, m, n, row_ptr, col_idx, vals, lhs, rhs, vartype, eps_int=1e-6,
-                 cont_rel_tol=1e-6, feas_tol=1e-6, steps=0):
+                 cont_rel_tol=1e-6, feas_tol=1e-6, steps=0, layout=0):
         """steps: layout entries per lane (4, 8, 16); 0 = the autotuned value
-        for this matrix shape, else 16."""
+        for this matrix shape, else by size.  layout: 0 length-class chunks,
+        1 nnz split (single runs only)."""
         self._h = None
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
         ci = np.ascontiguousarray(col_idx, dtype=np.int32)
@@ -194,7 +195,7 @@ class Problem:
         if ci.shape != va.shape or ci.shape[0] != int(rp[-1]):
             raise ValueError("col_idx / vals do not match row_ptr")
         csr = _Csr(int(m), int(n), int(rp[-1]), _ptr(rp).value, _ptr(ci).value, _ptr(va).value)
-        prm = _Params(float(eps_int), float(cont_rel_tol), float(feas_tol), int(steps), 0)
+        prm = _Params(float(eps_int), float(cont_rel_tol), float(feas_tol), int(steps), int(layout))
         h = ctypes.c_void_p()
         _check(lib.prop_create(ctypes.byref(csr), _ptr(lh), _ptr(rh), _ptr(vt), ctypes.byref(prm),
                                ctypes.byref(h)))

@@ -480,23 +480,16 @@ constexpr int kStepGroup = 2;
 static_assert(kStepGroup == 1 || kStepGroup == 2 || kStepGroup == 4,
               "lane_steps handles remainders of up to 3 steps");
 
+// Start-of-round bounds of N entries (column words cv): with kCodes, an
+// integer variable's 2-byte code (its pair only on escape) and a continuous
+// variable's pair; otherwise the pairs.  All first gathers are issued before
+// any escape gather.
 template <int N, bool kCodes>
-__device__ __forceinline__ void chunk_steps(const Problem& P, const double2* __restrict__ cur,
-                                            const uint16_t* __restrict__ codes, uint32_t stride,
-                                            uint32_t t, size_t e0, LaneAcc& L) {
-  double av[N];
-  int32_t cv[N];
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const size_t e = e0 + (size_t)k * kWave;
-    // a single run reads the matrix once: stream it past the caches
-    av[k] = stride == 1 ? __builtin_nontemporal_load(P.vals + e) : P.vals[e];
-    cv[k] = stride == 1 ? __builtin_nontemporal_load(P.cols + e) : P.cols[e];
-  }
-  double2 bv[N];
+__device__ __forceinline__ void gather_bounds(const double2* __restrict__ cur,
+                                              const uint16_t* __restrict__ codes,
+                                              const int32_t* cv, uint32_t stride, uint32_t t,
+                                              double2* bv) {
   if (kCodes) {
-    // integer variables: the 2-byte code, the pair only on escape;
-    // continuous variables: the pair
     bool pair[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -513,6 +506,23 @@ __device__ __forceinline__ void chunk_steps(const Problem& P, const double2* __r
 #pragma unroll
     for (int k = 0; k < N; ++k) bv[k] = cur[(size_t)(cv[k] & kColMask) * stride + t];
   }
+}
+
+template <int N, bool kCodes>
+__device__ __forceinline__ void chunk_steps(const Problem& P, const double2* __restrict__ cur,
+                                            const uint16_t* __restrict__ codes, uint32_t stride,
+                                            uint32_t t, size_t e0, LaneAcc& L) {
+  double av[N];
+  int32_t cv[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const size_t e = e0 + (size_t)k * kWave;
+    // a single run reads the matrix once: stream it past the caches
+    av[k] = stride == 1 ? __builtin_nontemporal_load(P.vals + e) : P.vals[e];
+    cv[k] = stride == 1 ? __builtin_nontemporal_load(P.cols + e) : P.cols[e];
+  }
+  double2 bv[N];
+  gather_bounds<N, kCodes>(cur, codes, cv, stride, t, bv);
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     if (av[k] != 0.0) {
@@ -617,6 +627,261 @@ __device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const do
                                                const int32_t* marks = nullptr) {
   chunk_round<kCodes>(P, P.chunks[c], cur, nxt, stride, node_mask, exact_mask, marked, r_round,
                       marks);
+}
+
+// ---------------------------------------------------------------------------
+// nnz-split waves (single runs; layout in prop_tiles.h)
+//
+// Lane l walks its 8 consecutive entries, which may hold the end of a row
+// begun in earlier lanes (the head piece), whole rows, and the start of a
+// row that may go on in later lanes (the open piece).  Whole rows are
+// finished as they end.  An inclusive segmented scan over the lanes adds
+// the open pieces of a row (a segment starts at the lane where the row
+// starts), so the lane where a row ends holds all of it but its own head
+// piece; each row's state (slacks, counts, sides) is computed by the lane
+// where it ends and handed to the lanes holding its other pieces.  Every
+// piece then runs the exact candidate test when the lane's per-piece
+// thresholds do not rule it out.  A row the fast sums cannot certify sends
+// the whole wave to the exact fixed-point sums, row by row.
+// ---------------------------------------------------------------------------
+struct Sums {
+  DD smin, smax;
+  double emin, emax;
+  int cmin, cmax;
+};
+
+__device__ __forceinline__ Sums sums_of(const LaneAcc& L) {
+  return Sums{L.smin, L.smax, L.emin, L.emax, L.cmin, L.cmax};
+}
+
+// x = y + x, y the earlier part of the row
+__device__ __forceinline__ void sums_prepend(Sums& x, const Sums& y) {
+  dd_add(x.smin, x.emin, y.smin.hi, y.smin.lo, y.emin);
+  dd_add(x.smax, x.emax, y.smax.hi, y.smax.lo, y.emax);
+  x.cmin += y.cmin;
+  x.cmax += y.cmax;
+}
+
+__device__ __forceinline__ Sums sums_shfl_up(const Sums& x, int d) {
+  Sums y;
+  y.smin.hi = __shfl_up(x.smin.hi, d, kWave);
+  y.smin.lo = __shfl_up(x.smin.lo, d, kWave);
+  y.smax.hi = __shfl_up(x.smax.hi, d, kWave);
+  y.smax.lo = __shfl_up(x.smax.lo, d, kWave);
+  y.emin = __shfl_up(x.emin, d, kWave);
+  y.emax = __shfl_up(x.emax, d, kWave);
+  y.cmin = __shfl_up(x.cmin, d, kWave);
+  y.cmax = __shfl_up(x.cmax, d, kWave);
+  return y;
+}
+
+__device__ __forceinline__ RowState sums_state(const Sums& x, double lhs, double rhs, bool force) {
+  return make_row_state(x.smin, x.smax, x.emin, x.emax, x.cmin, x.cmax, lhs, rhs, force);
+}
+
+// Row state in three words for a shuffle: the counts matter only as 0, 1 or
+// more (a side with two infinite contributions yields no candidates).
+__device__ __forceinline__ int state_bits(const RowState& R) {
+  const int c0 = R.cmin < 2 ? R.cmin : 2, c1 = R.cmax < 2 ? R.cmax : 2;
+  return c0 | (c1 << 2) | ((int)R.min_side << 4) | ((int)R.max_side << 5) |
+         ((int)R.uncertain << 6);
+}
+
+__device__ __forceinline__ RowState state_from(double smn, double smx, int bits) {
+  RowState R{};
+  R.smn = smn;
+  R.smx = smx;
+  R.cmin = bits & 3;
+  R.cmax = (bits >> 2) & 3;
+  R.min_side = (bits >> 4) & 1;
+  R.max_side = (bits >> 5) & 1;
+  R.uncertain = (bits >> 6) & 1;
+  return R;
+}
+
+// The exact candidate test over the lane's entries k0 .. k1 - 1 (one row).
+__device__ __forceinline__ void nz_piece_candidates(const Problem& P, const RowState& R,
+                                                    size_t base, int k0, int k1,
+                                                    const double2* __restrict__ cur,
+                                                    double2* __restrict__ nxt) {
+  for (int k = k0; k < k1; ++k) {
+    const size_t e = base + (size_t)k * kWave;
+    const double a = P.vals[e];
+    if (a == 0.0) continue;
+    const int32_t cw = P.cols[e];
+    const double2 b = cur[cw & kColMask];
+    entry_candidates(P, R, a, b.x, b.y, cw, nxt, 1, true);
+  }
+}
+
+// A row that lies in one lane, entries k0 .. k1 - 1, has ended: its state,
+// and its candidates when the thresholds allow.  Returns true when the
+// fast sums cannot certify it.
+__device__ __forceinline__ bool nz_finish_row(const Problem& P, const LaneAcc& L, int row,
+                                              size_t base, int k0, int k1,
+                                              const double2* __restrict__ cur,
+                                              double2* __restrict__ nxt, bool force) {
+  const RowState R = sums_state(sums_of(L), P.lhs[row], P.rhs[row], force);
+  if (R.uncertain) return true;
+  if (lane_may_pass(R, L)) nz_piece_candidates(P, R, base, k0, k1, cur, nxt);
+  return false;
+}
+
+// Exact path of an nnz-split wave: every row in turn, the lanes holding its
+// entries adding their exact products into LDS digits.
+__device__ void nz_wave_exact(const Problem& P, const ChunkDesc cd, size_t base, uint32_t flags,
+                              int first_row, const double2* __restrict__ cur,
+                              double2* __restrict__ nxt) {
+  const int lane = threadIdx.x & (kWave - 1);
+  ExactScratch& X = exact_scratch();
+  for (int r = 0; r < cd.pad; ++r) {
+    exact_clear(X);
+    int row = first_row, cmin = 0, cmax = 0;
+    for (int k = 0; k < kNzSteps; ++k) {
+      if (k > 0 && ((flags >> k) & 1u)) ++row;
+      if (row != r) continue;
+      const size_t e = base + (size_t)k * kWave;
+      const double a = P.vals[e];
+      if (a == 0.0) continue;
+      const double2 b = cur[P.cols[e] & kColMask];
+      exact_entry(X, a, b.x, b.y);
+      cmin += is_inf(a > 0.0 ? b.x : b.y) ? 1 : 0;
+      cmax += is_inf(a > 0.0 ? b.y : b.x) ? 1 : 0;
+    }
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      cmin += __shfl_xor(cmin, off, kWave);
+      cmax += __shfl_xor(cmax, off, kWave);
+    }
+    double mn, mx;
+    exact_finish(X, lane == 0, mn, mx);
+    const double lhs = P.lhs[cd.row0 + r], rhs = P.rhs[cd.row0 + r];
+    RowState R{};
+    R.cmin = cmin;
+    R.cmax = cmax;
+    R.min_side = (rhs < __builtin_inf()) && cmin <= 1;
+    R.max_side = (lhs > -__builtin_inf()) && cmax <= 1;
+    set_exact(R, mn, mx, lhs, rhs);
+    if (!(R.min_side || R.max_side)) continue;
+    row = first_row;
+    for (int k = 0; k < kNzSteps; ++k) {
+      if (k > 0 && ((flags >> k) & 1u)) ++row;
+      if (row != r) continue;
+      const size_t e = base + (size_t)k * kWave;
+      const double a = P.vals[e];
+      if (a == 0.0) continue;
+      const int32_t cw = P.cols[e];
+      const double2 b = cur[cw & kColMask];
+      entry_candidates(P, R, a, b.x, b.y, cw, nxt, 1, true);
+    }
+  }
+}
+
+__device__ __forceinline__ void nz_wave_round(const Problem& P, int w,
+                                              const double2* __restrict__ cur,
+                                              double2* __restrict__ nxt, bool force_exact) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const ChunkDesc cd = P.chunks[w];
+  const size_t base = (size_t)cd.off64 * kWave + lane;
+  const uint32_t flags = P.wave_flags[(size_t)w * kWave + lane];
+  // rows started in earlier lanes (exclusive scan of the flag counts)
+  const int own = __builtin_popcount(flags);
+  int pre = own;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int y = __shfl_up(pre, d, kWave);
+    if (lane >= d) pre += y;
+  }
+  pre -= own;
+  const bool starts = flags != 0;
+  const bool head_open = !(flags & 1u);  // the first entry continues an earlier row
+  const int first_row = (flags & 1u) ? pre : pre - 1;
+  int row = first_row, kstart = 0, head_end = 0;
+  LaneAcc acc, head;
+  lane_acc_init(acc);
+  lane_acc_init(head);
+  bool redo = force_exact;
+  // activity pass, two steps' loads before their gathers
+#pragma unroll
+  for (int k0 = 0; k0 < kNzSteps; k0 += 2) {
+    double av[2];
+    int32_t cv[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const size_t e = base + (size_t)(k0 + k) * kWave;
+      av[k] = __builtin_nontemporal_load(P.vals + e);
+      cv[k] = __builtin_nontemporal_load(P.cols + e);
+    }
+    double2 bv[2];
+    gather_bounds<2, true>(cur, P.codes, cv, 1, 0, bv);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int kk = k0 + k;
+      if (kk > 0 && ((flags >> kk) & 1u)) {
+        // the piece kstart .. kk - 1 ends: the head piece, or a whole row
+        if (kstart == 0 && head_open) {
+          head = acc;
+          head_end = kk;
+        } else {
+          redo |= nz_finish_row(P, acc, cd.row0 + row, base, kstart, kk, cur, nxt, force_exact);
+        }
+        lane_acc_init(acc);
+        ++row;
+        kstart = kk;
+      }
+      if (av[k] != 0.0) {
+        accumulate(av[k], bv[k].x, bv[k].y, acc.smin, acc.smax, acc.cmin, acc.cmax, acc.emin,
+                   acc.emax);
+        lane_thresholds(acc, av[k], bv[k].x, bv[k].y, cv[k] < 0, P.cont_rel_tol);
+      }
+    }
+  }
+  // open pieces joined over the lanes: a segment starts where its row starts
+  Sums x = sums_of(acc);
+  bool f = starts;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const Sums y = sums_shfl_up(x, d);
+    const bool fy = __shfl_up((int)f, d, kWave) != 0;
+    if (lane >= d && !f) {
+      sums_prepend(x, y);
+      f = fy;
+    }
+  }
+  // rows ending here: the open row when the next lane starts a new row (or
+  // this is the last lane), and the head row (its earlier pieces are the
+  // previous lane's scan)
+  const uint32_t next_flags = __shfl_down(flags, 1, kWave);
+  const bool ends = lane == kWave - 1 || (next_flags & 1u);
+  const Sums carry = sums_shfl_up(x, 1);
+  RowState rt{}, rh{};
+  if (ends) rt = sums_state(x, P.lhs[cd.row0 + row], P.rhs[cd.row0 + row], force_exact);
+  const bool has_head = starts && head_open;
+  if (has_head) {
+    Sums h = sums_of(head);
+    sums_prepend(h, carry);
+    rh = sums_state(h, P.lhs[cd.row0 + pre - 1], P.rhs[cd.row0 + pre - 1], force_exact);
+  }
+  // the open row's state from the lane where it ends: the first lane from
+  // here on where it ends (`ends`), or the first later lane that starts a
+  // row (the open row is that lane's head row)
+  const uint64_t m_end = __ballot(ends), m_start = __ballot(starts);
+  const uint64_t ge = ~0ull << lane;
+  const uint64_t gt = lane == kWave - 1 ? 0ull : ~0ull << (lane + 1);
+  const int j = __builtin_ctzll((m_end & ge) | (m_start & gt));
+  const double h_smn = __shfl(rh.smn, j, kWave), h_smx = __shfl(rh.smx, j, kWave);
+  const int h_bits = __shfl(state_bits(rh), j, kWave);
+  const double t_smn = __shfl(rt.smn, j, kWave), t_smx = __shfl(rt.smx, j, kWave);
+  const int t_bits = __shfl(state_bits(rt), j, kWave);
+  const bool via_head = j > lane && ((m_start >> j) & 1ull);
+  const RowState ro = via_head ? state_from(h_smn, h_smx, h_bits) : state_from(t_smn, t_smx, t_bits);
+  if (has_head) {
+    if (rh.uncertain) redo = true;
+    else if (lane_may_pass(rh, head)) nz_piece_candidates(P, rh, base, 0, head_end, cur, nxt);
+  }
+  if (ro.uncertain) redo = true;
+  else if (lane_may_pass(ro, acc)) nz_piece_candidates(P, ro, base, kstart, kNzSteps, cur, nxt);
+  if (__ballot(redo)) nz_wave_exact(P, cd, base, flags, first_row, cur, nxt);
 }
 
 // ---------------------------------------------------------------------------

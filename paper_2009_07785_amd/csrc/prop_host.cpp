@@ -161,7 +161,7 @@ int validate(const prop_csr* A, const double* lhs, const double* rhs, const uint
       return fail(PROP_EINVAL, "cont_rel_tol must be finite and >= 0");
     if (prm->steps != 0 && prm->steps != 4 && prm->steps != 8 && prm->steps != 16)
       return fail(PROP_EINVAL, "params.steps must be 0, 4, 8 or 16");
-    if (prm->reserved != 0) return fail(PROP_EINVAL, "params.reserved must be 0");
+    if (prm->layout != 0 && prm->layout != 1) return fail(PROP_EINVAL, "params.layout must be 0 or 1");
     if (!(prm->feas_tol >= 0.0 && std::isfinite(prm->feas_tol)))
       return fail(PROP_EINVAL, "feas_tol must be finite and >= 0");
   }
@@ -174,7 +174,8 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   const int32_t n = A->n;
   HostLayout L;
   std::string err;
-  if (!layout_build(A, lhs, rhs, vartype, p->steps, &L, &err)) return fail(PROP_EINVAL, "%s", err.c_str());
+  if (!layout_build(A, lhs, rhs, vartype, p->steps, &L, &err, p->params.layout))
+    return fail(PROP_EINVAL, "%s", err.c_str());
   p->nnz = L.nnz;
   p->nnz_stored = L.stored;
   p->instance_infeasible = L.instance_infeasible;
@@ -207,6 +208,8 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   if ((rc = dev_upload(p, &d_rhs, h_rhs))) return rc;
   if ((rc = dev_upload(p, &d_vtype, vtype))) return rc;
   if ((rc = dev_upload(p, &d_perm, perm))) return rc;
+  uint8_t* d_wflags = nullptr;
+  if (p->params.layout == 1 && (rc = dev_upload(p, &d_wflags, L.wave_flags))) return rc;
   SegPartial* d_part;
   if ((rc = dev_alloc(p, &d_part, h_segs.size()))) return rc;
   double2 *b0, *b1;
@@ -241,6 +244,8 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   P.n_segs = (int32_t)h_segs.size();
   P.n = n;
   P.instance_infeasible = p->instance_infeasible ? 1 : 0;
+  P.nnz_split = p->params.layout == 1 ? 1 : 0;
+  P.wave_flags = d_wflags;
   P.bnd[0] = b0;
   P.bnd[1] = b1;
   P.codes = codes;
@@ -652,7 +657,7 @@ int prop_create(const prop_csr* A, const double* lhs, const double* rhs, const u
   int coop = 0, cus = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, p->device) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
-      persistent_occupancy(&per_cu) != hipSuccess || cus <= 0 || per_cu <= 0) {
+      persistent_occupancy(&per_cu, p->params.layout == 1) != hipSuccess || cus <= 0 || per_cu <= 0) {
     release(p);
     return fail(PROP_EDEVICE, "device attribute / occupancy query failed");
   }
@@ -801,6 +806,7 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
   if (nodes < 1) return fail(PROP_EINVAL, "nodes < 1");
   if (max_rounds < 0) return fail(PROP_EINVAL, "max_rounds < 0");
   if (p->n > 0 && (!d_lb || !d_ub)) return fail(PROP_EINVAL, "bound arrays are NULL");
+  if (p->P.nnz_split) return fail(PROP_EINVAL, "the nnz-split layout runs single bound vectors only");
   HIP_TRY(hipSetDevice(p->device));
   int rc = ensure_batch(p, nodes);
   if (rc) return rc;
@@ -1076,7 +1082,7 @@ int prop_get_info(const prop_problem* p, prop_info* out) {
   out->device_bytes = p->device_bytes;
   out->alg_bytes_round = 12 * p->nnz + 20 * (int64_t)p->m + 33 * (int64_t)p->n + 4;
   out->steps = p->steps;
-  out->reserved = 0;
+  out->layout = p->params.layout;
   return PROP_OK;
 }
 

@@ -84,6 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_unpack(Problem P, double* __restrict
 }
 
 // ---- persistent driver: every round inside one cooperative launch -------
+template <bool kNz>
 __global__ __launch_bounds__(kBlock) void k_persistent(Problem P, int max_rounds) {
   Ctrl* C = P.ctrl;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -99,7 +100,10 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Problem P, int max_rounds
 
   for (int r = 1; r <= max_rounds; ++r) {
     const uint32_t exact = u32_load(&C->tiny) ? 1u : 0u;
-    for (int c = gwave; c < P.n_chunks; c += nwaves) chunk_dispatch<true>(P, c, A, B, 1, 1, exact);
+    for (int c = gwave; c < P.n_chunks; c += nwaves) {
+      if (kNz) nz_wave_round(P, c, A, B, exact != 0);
+      else chunk_dispatch<true>(P, c, A, B, 1, 1, exact);
+    }
     if (P.n_segs) {
       for (int s = gwave; s < P.n_segs; s += nwaves)
         seg_phase1<true>(P, s, A, 1, 1, P.partials, 1, 0);
@@ -153,6 +157,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
   else if (item - P.n_segs < P.n_chunks)
     chunk_dispatch<true>(P, item - P.n_segs, P.bnd[0], P.bnd[1], 1, 1,
                          u32_load(&P.ctrl->tiny) ? 1u : 0u, marked, r, P.row_mark);
+}
+
+// The same round for the nnz-split layout (a kernel of its own, so that
+// neither layout's registers limit the other's occupancy).  Its waves
+// process every row, marked or not (processing a row is always exact).
+__global__ __launch_bounds__(kBlock) void k_round_nz(Problem P) {
+  if (u32_load(&P.ctrl->done)) return;
+  const int r = round_of(P);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int item = blockIdx.x * kWavesPerBlock + wave;
+  if (item < P.n_segs)
+    seg_phase1<true>(P, item, P.bnd[0], 1, 1, P.partials, 1, 0, marked_round(P), r, P.row_mark);
+  else if (item - P.n_segs < P.n_chunks)
+    nz_wave_round(P, item - P.n_segs, P.bnd[0], P.bnd[1], u32_load(&P.ctrl->tiny) != 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_round_long(Problem P) {
@@ -288,15 +306,18 @@ hipError_t launch_unpack(const Problem& P, double* lb, double* ub, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t persistent_occupancy(int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent, kBlock, 0);
+hipError_t persistent_occupancy(int* blocks_per_cu, bool nnz_split) {
+  return nnz_split ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
+                                                                  k_persistent<true>, kBlock, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
+                                                                  k_persistent<false>, kBlock, 0);
 }
 
 hipError_t launch_persistent(const Problem& P, int max_rounds, int grid, hipStream_t s) {
   Problem p = P;
   void* args[] = {(void*)&p, (void*)&max_rounds};
-  return hipLaunchCooperativeKernel((const void*)k_persistent, dim3(grid), dim3(kBlock), args, 0,
-                                    s);
+  const void* fn = P.nnz_split ? (const void*)k_persistent<true> : (const void*)k_persistent<false>;
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlock), args, 0, s);
 }
 
 hipError_t launch_seed(const Problem& P, hipStream_t s) {
@@ -321,8 +342,12 @@ hipError_t launch_start(const Problem& P, int max_rounds, hipStream_t s) {
 hipError_t launch_round(const Problem& P, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const int items = P.n_chunks + P.n_segs;
   if (e0) hipEventRecord(e0, s);
-  hipLaunchKernelGGL(k_round, dim3(blocks_for(items, kWavesPerBlock, 1 << 30)), dim3(kBlock), 0,
-                     s, P);
+  if (P.nnz_split)
+    hipLaunchKernelGGL(k_round_nz, dim3(blocks_for(items, kWavesPerBlock, 1 << 30)), dim3(kBlock),
+                       0, s, P);
+  else
+    hipLaunchKernelGGL(k_round, dim3(blocks_for(items, kWavesPerBlock, 1 << 30)), dim3(kBlock), 0,
+                       s, P);
   if (e1) hipEventRecord(e1, s);
   if (P.n_segs)
     hipLaunchKernelGGL(k_round_long, dim3(blocks_for(P.n_segs, kWavesPerBlock, 1 << 30)),

@@ -10,7 +10,7 @@ namespace prop {
 hipError_t launch_init(const Problem& P, hipStream_t s);
 hipError_t launch_pack(const Problem& P, const double* lb, const double* ub, hipStream_t s);
 hipError_t launch_unpack(const Problem& P, double* lb, double* ub, hipStream_t s);
-hipError_t persistent_occupancy(int* blocks_per_cu);
+hipError_t persistent_occupancy(int* blocks_per_cu, bool nnz_split);
 hipError_t launch_persistent(const Problem& P, int max_rounds, int grid, hipStream_t s);
 hipError_t launch_start(const Problem& P, int max_rounds, hipStream_t s);
 // Queues one round: the matrix kernel (bracketed by e0 / e1 when they are

@@ -50,10 +50,13 @@ struct Problem {
   const double* rhs;
   const uint8_t* vtype;     // internal variable order
   const int32_t* perm;      // perm[user var] = internal var
-  int32_t n_chunks;
+  int32_t n_chunks;         // chunks, or nnz-split waves (nnz_split != 0)
   int32_t n_segs;
   int32_t n;
   int32_t instance_infeasible;
+  int32_t nnz_split;        // the layout is nnz-split (prop_tiles.h)
+  int32_t pad_nz;
+  const uint8_t* wave_flags; // nnz-split: [n_chunks][64] row starts per lane
   // state: bnd[0] = start-of-round bounds, bnd[1] = candidate target
   double2* bnd[2];
   uint16_t* codes;          // [n] compact code of bnd[0] per variable (prop_device.h)

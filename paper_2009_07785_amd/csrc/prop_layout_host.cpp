@@ -18,7 +18,8 @@ int ceil_log2(int64_t x) {
 }  // namespace
 
 bool layout_build(const prop_csr* A, const double* lhs, const double* rhs,
-                  const uint8_t* vartype, int steps, HostLayout* out, std::string* err) {
+                  const uint8_t* vartype, int steps, HostLayout* out, std::string* err,
+                  int kind) {
   const int32_t m = A->m, n = A->n;
   // nonzero entries per row and per column
   std::vector<int64_t> len(m, 0);
@@ -60,15 +61,22 @@ bool layout_build(const prop_csr* A, const double* lhs, const double* rhs,
     return (int32_t)((uint32_t)perm[j] | (vartype[j] ? 0x80000000u : 0u));
   };
 
-  // rows by lanes-per-row class; long rows apart
+  // rows by lanes-per-row class; long rows apart (nnz-split waves: rows
+  // longer than a wave's entries)
+  const int64_t long_above = kind == 1 ? (int64_t)kNzEntries : (int64_t)kWave * steps;
   std::vector<std::vector<int32_t>> cls(7);
   std::vector<int32_t> longs;
+  std::vector<int32_t> shorts;  // nnz-split: short rows in input order
   for (int32_t i = 0; i < m; ++i) {
     if (len[i] == 0) continue;
     // rows of at most 64 lanes x `steps` entries go to chunks, longer ones
     // to 1024-entry segments
-    if (len[i] > (int64_t)kWave * steps) {
+    if (len[i] > long_above) {
       longs.push_back(i);
+      continue;
+    }
+    if (kind == 1) {
+      shorts.push_back(i);
       continue;
     }
     const int64_t lanes = (len[i] + steps - 1) / steps;
@@ -102,15 +110,76 @@ bool layout_build(const prop_csr* A, const double* lhs, const double* rhs,
   out->stored = stored;
   out->chunk_entries = chunk_entries;
 
+  // nnz-split waves: consecutive short rows, in input order, packed into
+  // waves of at most kNzEntries entries and kNzMaxRows rows
+  int64_t chunk_entries_all = chunk_entries;
+  struct NzWave {
+    size_t first, count;  // range of `shorts`
+  };
+  std::vector<NzWave> nzw;
+  if (kind == 1) {
+    size_t q = 0;
+    while (q < shorts.size()) {
+      NzWave w{q, 0};
+      int64_t fill = 0;
+      while (q < shorts.size() && w.count < (size_t)kNzMaxRows &&
+             fill + len[shorts[q]] <= (int64_t)kNzEntries) {
+        fill += len[shorts[q]];
+        ++w.count;
+        ++q;
+      }
+      nzw.push_back(w);
+    }
+    stored = (int64_t)nzw.size() * kNzEntries;
+    for (int32_t i : longs) stored += (len[i] + kWave - 1) / kWave * kWave;
+    if ((int64_t)nzw.size() * kNzEntries / kWave > INT32_MAX)
+      { *err = "matrix too large for the layout"; return false; }
+    out->stored = stored;
+    out->chunk_entries = chunk_entries_all = (int64_t)nzw.size() * kNzEntries;
+  }
+
   std::vector<double> h_vals(stored, 0.0);
   std::vector<int32_t> h_cols(stored, 0);
   std::vector<ChunkDesc> h_chunks;
-  h_chunks.reserve(chunks.size());
+  h_chunks.reserve(kind == 1 ? nzw.size() : chunks.size());
+  std::vector<uint8_t> h_wflags;
   std::vector<double> h_lhs, h_rhs;
   h_lhs.reserve(m);
   h_rhs.reserve(m);
   int64_t off = 0;
   int32_t next_row = 0;
+  // nnz-split: entry q of a wave (CSR order within the wave) belongs to lane
+  // q / kNzSteps, step q % kNzSteps, stored at step * 64 + lane; bit k of a
+  // lane's flag byte marks the first entry of a row
+  for (const NzWave& w : nzw) {
+    ChunkDesc d;
+    d.off64 = (int32_t)(off / kWave);
+    d.row0 = next_row;
+    d.meta = 0;
+    d.pad = (int32_t)w.count;  // rows of the wave
+    h_chunks.push_back(d);
+    const size_t f0 = h_wflags.size();
+    h_wflags.resize(f0 + kWave, 0);
+    int64_t q = 0;
+    for (size_t t = 0; t < w.count; ++t) {
+      const int32_t i = shorts[w.first + t];
+      h_lhs.push_back(lhs[i] + 0.0);
+      h_rhs.push_back(rhs[i] + 0.0);
+      bool first = true;
+      for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k) {
+        if (A->vals[k] == 0.0) continue;
+        const int64_t ln = q / kNzSteps, st = q % kNzSteps;
+        const int64_t idx = off + st * kWave + ln;
+        h_vals[idx] = A->vals[k];
+        h_cols[idx] = col_word(A->col_idx[k]);
+        if (first) h_wflags[f0 + (size_t)ln] |= (uint8_t)(1u << st);
+        first = false;
+        ++q;
+      }
+    }
+    next_row += (int32_t)w.count;
+    off += kNzEntries;
+  }
   for (auto& c : chunks) {
     const auto& rows = cls[c.klog];
     const int K = 1 << c.klog;
@@ -169,14 +238,30 @@ bool layout_build(const prop_csr* A, const double* lhs, const double* rhs,
   // every index a kernel forms must stay inside the arrays built above
   const int64_t n_rows_internal = next_row;
   for (const ChunkDesc& d : h_chunks) {
+    if (kind == 1) {
+      if (d.pad < 1 || d.pad > kNzMaxRows ||
+          (int64_t)d.off64 * kWave + kNzEntries > chunk_entries_all || d.row0 < 0 ||
+          d.row0 + d.pad > n_rows_internal)
+        { *err = "internal layout check failed (nnz-split wave)"; return false; }
+      continue;
+    }
     const int W = (d.meta >> 8) & 0xff, nr = (d.meta >> 16) & 0xff, kl = d.meta & 7;
     if (W < 1 || W > steps || nr < 1 || nr > (kWave >> kl) ||
         (int64_t)d.off64 * kWave + (int64_t)W * kWave > chunk_entries || d.row0 < 0 ||
         d.row0 + nr > n_rows_internal)
       { *err = "internal layout check failed (chunk)"; return false; }
   }
+  if (kind == 1) {
+    // a wave's first entry starts a row, and its flags name its rows
+    for (size_t c = 0; c < h_chunks.size(); ++c) {
+      int starts = 0;
+      for (int l = 0; l < kWave; ++l) starts += __builtin_popcount(h_wflags[c * kWave + l]);
+      if (!(h_wflags[c * kWave] & 1u) || starts != h_chunks[c].pad)
+        { *err = "internal layout check failed (nnz-split flags)"; return false; }
+    }
+  }
   for (const SegDesc& d : h_segs) {
-    if (d.len < 1 || d.len > kSegLen || d.off < chunk_entries || d.off + d.len > stored ||
+    if (d.len < 1 || d.len > kSegLen || d.off < chunk_entries_all || d.off + d.len > stored ||
         d.first < 0 || d.first + d.nseg > (int32_t)h_segs.size() || d.row < 0 ||
         d.row >= n_rows_internal)
       { *err = "internal layout check failed (segment)"; return false; }
@@ -193,7 +278,19 @@ bool layout_build(const prop_csr* A, const double* lhs, const double* rhs,
     std::vector<int32_t>& vr = out->var_rows;
     vp.assign((size_t)n + 1, 0);
     auto each_entry = [&](auto&& fn) {
+      for (size_t c = 0; kind == 1 && c < h_chunks.size(); ++c) {
+        const ChunkDesc& d = h_chunks[c];
+        const int64_t b = (int64_t)d.off64 * kWave;
+        int32_t local = -1;
+        for (int64_t q = 0; q < kNzEntries; ++q) {
+          const int64_t ln = q / kNzSteps, st = q % kNzSteps;
+          if ((h_wflags[c * kWave + (size_t)ln] >> st) & 1u) ++local;
+          const int64_t idx = b + st * kWave + ln;
+          if (h_vals[idx] != 0.0) fn(h_cols[idx] & kColMask, d.row0 + local);
+        }
+      }
       for (const ChunkDesc& d : h_chunks) {
+        if (kind == 1) break;
         const int W = (d.meta >> 8) & 0xff, kl = d.meta & 7;
         const int64_t b = (int64_t)d.off64 * kWave;
         for (int64_t q = 0; q < (int64_t)W * kWave; ++q)
@@ -217,6 +314,7 @@ bool layout_build(const prop_csr* A, const double* lhs, const double* rhs,
   out->vals = std::move(h_vals);
   out->cols = std::move(h_cols);
   out->chunks = std::move(h_chunks);
+  out->wave_flags = std::move(h_wflags);
   out->segs = std::move(h_segs);
   out->lhs = std::move(h_lhs);
   out->rhs = std::move(h_rhs);

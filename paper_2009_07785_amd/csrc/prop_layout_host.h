@@ -24,7 +24,8 @@ struct HostLayout {
   std::vector<uint8_t> vtype;      // per internal var
   std::vector<double> vals;        // [stored]
   std::vector<int32_t> cols;       // [stored] column words
-  std::vector<ChunkDesc> chunks;
+  std::vector<ChunkDesc> chunks;   // chunks, or the waves of the nnz-split layout
+  std::vector<uint8_t> wave_flags; // nnz-split: [chunks][64] row starts per lane (bit = step)
   std::vector<SegDesc> segs;
   std::vector<double> lhs, rhs;    // internal row order (chunk rows, then long rows)
   int32_t n_rows = 0;              // internal rows
@@ -37,7 +38,10 @@ struct HostLayout {
 // Builds the layout of a validated matrix with `steps` entries per lane of a
 // short row (4, 8 or 16).  Returns false with a message when an internal
 // consistency check fails or the matrix does not fit the layout.
+// kind 1 builds the nnz-split layout instead (prop_tiles.h; `steps` then
+// only matters for the chunk consistency checks).
 bool layout_build(const prop_csr* A, const double* lhs, const double* rhs,
-                  const uint8_t* vartype, int steps, HostLayout* out, std::string* err);
+                  const uint8_t* vartype, int steps, HostLayout* out, std::string* err,
+                  int kind = 0);
 
 }  // namespace prop

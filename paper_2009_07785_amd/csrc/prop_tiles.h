@@ -53,6 +53,19 @@ constexpr int kInfeasible = 1;
 constexpr int kMaxRounds = 2;
 constexpr int kInvalidInput = -1;  // batch node status: an input bound failed validation
 
+// The nnz-split layout (merge-path style load balancing; an alternative to
+// the length-class chunks, chosen at create).  Rows in input order are
+// packed into waves of at most kNzEntries entries and kNzMaxRows rows, with
+// no sorting by length; rows longer than kNzEntries go to segments.  Lane l
+// of a wave owns the wave's entries l * kNzSteps .. l * kNzSteps + 7 in CSR
+// order, stored step-major (entry k of lane l at k * 64 + l) so that every
+// step is one contiguous load; a flag byte per lane marks the entries that
+// start a row.  Rows may span lanes: a segmented scan over the lanes joins
+// their pieces.
+constexpr int kNzSteps = 8;
+constexpr int kNzEntries = kWave * kNzSteps;
+constexpr int kNzMaxRows = 256;
+
 // One chunk of short/medium rows.
 struct ChunkDesc {
   int32_t off64;   // data offset in units of 64 entries

@@ -140,6 +140,65 @@ static int check_steps(const prop_csr& A, const std::vector<double>& lhs,
   return 0;
 }
 
+// The nnz-split layout: each internal short row, read back from its wave
+// through the flag bytes (entry q of a wave at step q % 8, lane q / 8), holds
+// exactly the input row's nonzeros in order, with its sides, rows in input
+// order; long rows go to segments as in the chunk layout.
+static int check_nnz_split(const prop_csr& A, const std::vector<double>& lhs,
+                           const std::vector<double>& rhs, const std::vector<uint8_t>& vt) {
+  const int32_t m = A.m, n = A.n;
+  HostLayout L;
+  std::string err;
+  CHECK(layout_build(&A, lhs.data(), rhs.data(), vt.data(), 16, &L, &err, 1));
+  CHECK((int64_t)L.wave_flags.size() == (int64_t)L.chunks.size() * kWave);
+  CHECK(L.chunk_entries == (int64_t)L.chunks.size() * kNzEntries);
+  std::vector<int32_t> inv(n > 0 ? n : 1, -1);
+  for (int32_t j = 0; j < n; ++j) inv[L.perm[j]] = j;
+  // the short rows in input order
+  std::vector<int32_t> shorts;
+  for (int32_t i = 0; i < m; ++i) {
+    int64_t len = 0;
+    for (int64_t k = A.row_ptr[i]; k < A.row_ptr[i + 1]; ++k) len += A.vals[k] != 0.0;
+    if (len > 0 && len <= kNzEntries) shorts.push_back(i);
+  }
+  size_t next = 0;
+  for (size_t c = 0; c < L.chunks.size(); ++c) {
+    const ChunkDesc& d = L.chunks[c];
+    CHECK(d.pad >= 1 && d.pad <= kNzMaxRows && d.row0 == (int32_t)next);
+    std::vector<std::vector<std::pair<int32_t, double>>> rows((size_t)d.pad);
+    int32_t local = -1;
+    for (int64_t q = 0; q < kNzEntries; ++q) {
+      const int64_t ln = q / kNzSteps, st = q % kNzSteps;
+      if ((L.wave_flags[c * kWave + (size_t)ln] >> st) & 1u) ++local;
+      CHECK(local >= 0 && local < d.pad);
+      const int64_t idx = (int64_t)d.off64 * kWave + st * kWave + ln;
+      CHECK(idx >= 0 && idx < L.chunk_entries);
+      if (L.vals[idx] == 0.0) continue;
+      const int32_t v = L.cols[idx] & kColMask;
+      CHECK(v >= 0 && v < n);
+      CHECK(((L.cols[idx] < 0) ? 1 : 0) == L.vtype[v]);
+      rows[(size_t)local].push_back({inv[v], L.vals[idx]});
+    }
+    CHECK(local == d.pad - 1);
+    for (int32_t r = 0; r < d.pad; ++r, ++next) {
+      CHECK(next < shorts.size());
+      const int32_t i = shorts[next];
+      std::vector<std::pair<int32_t, double>> want;
+      for (int64_t k = A.row_ptr[i]; k < A.row_ptr[i + 1]; ++k)
+        if (A.vals[k] != 0.0) want.push_back({A.col_idx[k], A.vals[k]});
+      CHECK(rows[(size_t)r] == want);
+      CHECK(L.lhs[(size_t)(d.row0 + r)] == lhs[i] + 0.0 && L.rhs[(size_t)(d.row0 + r)] == rhs[i] + 0.0);
+    }
+  }
+  CHECK(next == shorts.size());
+  for (const SegDesc& sd : L.segs)
+    CHECK(sd.len >= 1 && sd.len <= kSegLen && sd.off >= L.chunk_entries && sd.off + sd.len <= L.stored);
+  // rows of every variable: each entry's row counted once
+  CHECK((int64_t)L.var_ptr.size() == (int64_t)n + 1);
+  for (int32_t r : L.var_rows) CHECK(r >= 0 && r < L.n_rows);
+  return 0;
+}
+
 int main(int argc, char** argv) {
   if (argc != 2) return 2;
   const std::string dir = argv[1];
@@ -163,6 +222,10 @@ int main(int argc, char** argv) {
       fprintf(stderr, "steps = %d\n", steps);
       return rc;
     }
+  }
+  if (check_nnz_split(A, lhs, rhs, vt)) {
+    fprintf(stderr, "nnz-split layout\n");
+    return 1;
   }
   printf("layout ok: %d x %d, %lld nonzeros\n", A.m, A.n, (long long)A.nnz);
   return 0;

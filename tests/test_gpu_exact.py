@@ -13,6 +13,8 @@ import synth
 pytestmark = pytest.mark.gpu
 
 LOOPS = ("stream", "persistent", "host", "graph")
+# every chunk layout, and the nnz-split waves
+LAYOUTS = (dict(steps=4), dict(steps=8), dict(steps=16), dict(layout=1))
 
 
 @pytest.fixture(scope="module")
@@ -52,12 +54,12 @@ def test_counterexample_row(lib):
                            [two53, 1.0, 2.0**-60], [np.inf] * 3, [0, 0, 0], n=3)
     ref = oracle.run(inst, inst.lb, inst.ub, 100)
     assert np.array_equal(ref.ub, [two53 + 2, 3.0, 2.0])
-    for steps in (4, 8, 16):
-        with lib.Problem.from_instance(inst, steps=steps) as p:
+    for kw in LAYOUTS:
+        with lib.Problem.from_instance(inst, **kw) as p:
             for loop in LOOPS:
                 p.set_loop(loop)
                 res, lb, ub = p.run(inst.lb, inst.ub, 100)
-                same(f"steps={steps} {loop}", res, lb, ub, ref)
+                same(f"{kw} {loop}", res, lb, ub, ref)
 
 
 @pytest.mark.parametrize("seed,tiny", [(0, False), (1, False), (2, True)])
@@ -67,13 +69,13 @@ def test_hard_sums_all_layouts(lib, seed, tiny):
     say(f"  {inst.name}: oracle {oracle.STATUS_NAMES[ref.status]} after {ref.rounds} rounds, "
         f"{int(np.sum(ref.ub != inst.ub))} upper bounds tightened")
     assert ref.status == oracle.CONVERGED
-    for steps in (4, 8, 16):
-        with lib.Problem.from_instance(inst, steps=steps) as p:
+    for kw in LAYOUTS:
+        with lib.Problem.from_instance(inst, **kw) as p:
             for loop in LOOPS:
                 p.set_loop(loop)
-                say(f"  {inst.name} steps={steps} loop={loop}")
+                say(f"  {inst.name} {kw} loop={loop}")
                 res, lb, ub = p.run(inst.lb, inst.ub, 100)
-                same(f"{inst.name} steps={steps} {loop}", res, lb, ub, ref)
+                same(f"{inst.name} {kw} {loop}", res, lb, ub, ref)
 
 
 @pytest.mark.parametrize("nodes", [1, 2, 3, 8, 11])

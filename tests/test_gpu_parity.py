@@ -119,6 +119,39 @@ def test_code_edges(lib, seed):
             assert_same(f"{inst.name}/steps={steps}", p.run(inst.lb, inst.ub, 100), ref)
 
 
+def test_nnz_split_layout(lib):
+    """The nnz-split layout (rows in input order packed into 512-entry waves,
+    8 consecutive entries per lane, rows spanning lanes joined by a
+    segmented scan, longer rows in segments) gives the oracle's results
+    bitwise on every driver."""
+    insts = [synth.config0(), synth.layout_mix(0), synth.layout_mix(1), synth.code_edges(0),
+             synth.config1(1), synth.config3_matrix(50_000, 25_000), pins.cascade_instance(99)]
+    insts += [synth.random_small(s, m=int(3 + s % 9), n=int(3 + s % 7), box=6,
+                                 int_frac=[1.0, 0.5, 0.0][s % 3], inf_frac=0.2 * (s % 2))
+              for s in range(12)]
+    for c in pins.load_closed_forms():
+        insts.append((pins.case_instance(c), c["max_rounds"], pins.case_params(c)))
+    for item in insts:
+        inst, max_rounds, params = item if isinstance(item, tuple) else (item, 100, None)
+        ref = oracle.run(inst, inst.lb, inst.ub, max_rounds, params)
+        kw = {} if params is None else dict(eps_int=params.eps_int,
+                                            cont_rel_tol=params.cont_rel_tol,
+                                            feas_tol=params.feas_tol)
+        with lib.Problem.from_instance(inst, layout=1, **kw) as p:
+            assert p.info()["layout"] == 1
+            for loop in LOOPS:
+                p.set_loop(loop)
+                assert_same(f"{inst.name}/nnz-split/{loop}", p.run(inst.lb, inst.ub, max_rounds),
+                            ref)
+            p.set_marking(True)
+            p.set_loop("stream")
+            assert_same(f"{inst.name}/nnz-split/marked", p.run(inst.lb, inst.ub, max_rounds), ref)
+    # batches and serving refuse the layout
+    with lib.Problem.from_instance(synth.config0(), layout=1) as p:
+        with pytest.raises(lib.PropError):
+            p.run_batch(np.stack([synth.config0().lb] * 2), np.stack([synth.config0().ub] * 2), 10)
+
+
 def test_powerlaw_hot_variables(lib):
     """Power-law columns: dozens of variables above the degree at which the
     kernels spread their candidate targets over stripe copies."""
@@ -341,6 +374,21 @@ def test_config2_marked_full_run(lib, big):
         p.set_marking(False)
     assert (res1.status, res1.rounds) == (g["status"], g["rounds"])
     assert bounds_sha(lb1, ub1) == g["sha"][g["rounds"]]
+
+
+def test_config2_nnz_split(lib, big):
+    """The nnz-split layout on the full instance: every 4th round and the
+    final state equal to the oracle's stored hashes."""
+    inst, _ = big
+    g = load_golden("config2_rounds.json")
+    R = g["rounds"]
+    with lib.Problem.from_instance(inst, layout=1) as p:
+        for r in list(range(1, R, 4)) + [R]:
+            res, lb, ub = p.run(inst.lb, inst.ub, r)
+            want = (g["status"], R) if r == R else (oracle.MAX_ROUNDS, r)
+            assert (res.status, res.rounds) == want, f"round {r}"
+            assert bounds_sha(lb, ub) == g["sha"][r], f"nnz-split: bounds differ after round {r}"
+    say(f"config2 nnz-split: rounds 1, 5, ..., {R} equal to the oracle's")
 
 
 def test_round_limits_all_drivers(lib):

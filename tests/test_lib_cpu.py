@@ -64,7 +64,7 @@ def test_valid_input_reaches_device_stage():
     (dict(params=(1e-6, -1.0, 1e-6)), "negative cont_rel_tol"),
     (dict(params=(1e-6, 1e-6, np.nan)), "NaN feas_tol"),
     (dict(params=(1e-6, 1e-6, 1e-6, 5)), "layout steps 5"),
-    (dict(params=(1e-6, 1e-6, 1e-6, 0, 1)), "reserved field set"),
+    (dict(params=(1e-6, 1e-6, 1e-6, 0, 2)), "layout 2"),
 ])
 def test_invalid_input_rejected(over, why):
     assert _rc(**over) == b.EINVAL, why
