@@ -111,6 +111,13 @@ class Oracle:
         lib.orc_run.restype = ctypes.c_int
         lib.orc_run_seq.argtypes = [i32, i32, P, P, P, P, P, P, f64, f64, f64, P, P, i32, P, P]
         lib.orc_run_seq.restype = ctypes.c_int
+        lib.orc_run_store.argtypes = [i32, i32, P, P, P, P, P, P, f64, f64, f64, i32, P, P, i32,
+                                      P, P, P]
+        lib.orc_run_store.restype = ctypes.c_int
+        lib.orc_store_down.argtypes = [f64]
+        lib.orc_store_down.restype = f64
+        lib.orc_store_up.argtypes = [f64]
+        lib.orc_store_up.restype = f64
         self.lib = lib
         self.path = lib_path
 
@@ -152,21 +159,39 @@ class Oracle:
             raise OracleError(f"orc_round failed: {rc}")
         return Ln, Un, bool(ch.value), bool(inf.value), int(fl.value)
 
-    def run(self, inst, lb, ub, max_rounds: int = 100, params: Params | None = None) -> Result:
-        """Full synchronous propagation: status, rounds and the bounds."""
+    def run(self, inst, lb, ub, max_rounds: int = 100, params: Params | None = None,
+            store: int = 64) -> Result:
+        """Full synchronous propagation: status, rounds and the bounds.
+        ``store=32`` keeps the bounds in single precision, rounded outward
+        (reading R10 of ``prop_oracle.c``)."""
         p = params or Params()
         rp, ci, va, lh, rh, vt = _problem_arrays(inst)
         lb = np.array(lb, dtype=np.float64, copy=True)
         ub = np.array(ub, dtype=np.float64, copy=True)
         st, rd = ctypes.c_int32(0), ctypes.c_int32(0)
         fl = ctypes.c_int64(0)
-        rc = self.lib.orc_run(inst.m, inst.n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(lh), _ptr(rh),
-                              _ptr(vt), p.eps_int, p.cont_rel_tol, p.feas_tol, _ptr(lb),
-                              _ptr(ub), int(max_rounds), ctypes.byref(st), ctypes.byref(rd),
-                              ctypes.byref(fl))
+        if store == 64:
+            rc = self.lib.orc_run(inst.m, inst.n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(lh),
+                                  _ptr(rh), _ptr(vt), p.eps_int, p.cont_rel_tol, p.feas_tol,
+                                  _ptr(lb), _ptr(ub), int(max_rounds), ctypes.byref(st),
+                                  ctypes.byref(rd), ctypes.byref(fl))
+        else:
+            rc = self.lib.orc_run_store(inst.m, inst.n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(lh),
+                                        _ptr(rh), _ptr(vt), p.eps_int, p.cont_rel_tol,
+                                        p.feas_tol, int(store), _ptr(lb), _ptr(ub),
+                                        int(max_rounds), ctypes.byref(st), ctypes.byref(rd),
+                                        ctypes.byref(fl))
         if rc:
             raise OracleError(f"orc_run failed: {rc}")
         return Result(st.value, rd.value, lb, ub, int(fl.value))
+
+    def store_down(self, x: float) -> float:
+        """Largest member of the single-precision store's grid not above x."""
+        return float(self.lib.orc_store_down(float(x)))
+
+    def store_up(self, x: float) -> float:
+        """Smallest member of the single-precision store's grid not below x."""
+        return float(self.lib.orc_store_up(float(x)))
 
     def run_seq(self, inst, lb, ub, max_sweeps: int = 1000,
                 params: Params | None = None) -> Result:
@@ -209,8 +234,9 @@ def round_(inst, L, U, params: Params | None = None):
     return default().round_(inst, L, U, params)
 
 
-def run(inst, lb, ub, max_rounds: int = 100, params: Params | None = None) -> Result:
-    return default().run(inst, lb, ub, max_rounds, params)
+def run(inst, lb, ub, max_rounds: int = 100, params: Params | None = None,
+        store: int = 64) -> Result:
+    return default().run(inst, lb, ub, max_rounds, params, store)
 
 
 def run_seq(inst, lb, ub, max_sweeps: int = 1000, params: Params | None = None) -> Result:

@@ -50,10 +50,22 @@
  *       decided at the end of every round, infeasibility first;
  *   R9  before round 1 the integer bounds are rounded as in R4, and the run
  *       stops with status INFEASIBLE after 0 rounds when an input domain is
- *       empty (R7), some row has lhs > rhs, or an empty row excludes 0.
+ *       empty (R7), some row has lhs > rhs, or an empty row excludes 0;
+ *   R10 single-precision bound store (orc_run_store with 32; Sec. 4.5 runs
+ *       the whole method in single precision and reports results that are
+ *       no longer correct): all arithmetic stays as in R1-R9, but every
+ *       bound is kept as a member of F = {0, -inf, +inf} together with the
+ *       normal single-precision numbers, rounded outward: a lower bound to
+ *       the largest member of F not above it, an upper bound to the
+ *       smallest member not below it.  This applies to the input bounds
+ *       after R9's integer rounding and to every bound a round commits,
+ *       before the round decides whether anything changed.  Outward
+ *       rounding only loosens bounds, so a point the FP64 store keeps is
+ *       kept (integers up to 2^24 are members of F and stay exact).
  *
  * Build:  gcc -O2 -ffp-contract=off -fno-fast-math -fPIC -shared
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -219,6 +231,7 @@ typedef struct {
 
 typedef struct {
   double eps_int, cont_rel_tol, feas_tol;
+  int store32; /* R10 */
 } orc_params;
 
 static int valid_value(double x) { return isfinite(x) && fabs(x) <= orc_huge(); }
@@ -268,6 +281,25 @@ static int orc_validate_bounds(const orc_problem* P, const double* lb, const dou
   }
   return 0;
 }
+
+/* Reading R10: the largest member of F not above x (x not NaN). */
+static double store_down(double x) {
+  if (isinf(x) || x == 0.0) return x + 0.0;
+  if (x > FLT_MAX) return FLT_MAX;
+  if (x < -FLT_MAX) return -INFINITY;
+  if (x > 0.0 && x < FLT_MIN) return 0.0;
+  if (x < 0.0 && x > -FLT_MIN) return -FLT_MIN;
+  float f = (float)x; /* nearest: at most one step of the grid away */
+  if ((double)f > x) f = nextafterf(f, -INFINITY);
+  return (double)f;
+}
+
+/* Reading R10: the smallest member of F not below x. */
+static double store_up(double x) { return -store_down(-x) + 0.0; }
+
+/* Exported for the oracle's own pins. */
+double orc_store_down(double x) { return store_down(x); }
+double orc_store_up(double x) { return store_up(x); }
 
 /* Reading R7. */
 static int domain_empty(int is_int, double l, double u, double feas_tol) {
@@ -445,6 +477,10 @@ static int round_impl(const orc_problem* P, const orc_params* prm, const double*
   }
   int ch = 0, inf = 0;
   for (int32_t j = 0; j < P->n; j++) {
+    if (prm->store32) {
+      Ln[j] = store_down(Ln[j]);
+      Un[j] = store_up(Un[j]);
+    }
     if (Ln[j] != L[j] || Un[j] != U[j]) ch = 1;
     if (domain_empty(P->vartype[j] == 1, Ln[j], Un[j], prm->feas_tol)) inf = 1;
   }
@@ -457,6 +493,7 @@ static void fill_params(orc_params* prm, double eps_int, double cont_rel_tol, do
   prm->eps_int = eps_int;
   prm->cont_rel_tol = cont_rel_tol;
   prm->feas_tol = feas_tol;
+  prm->store32 = 0;
 }
 
 /* One round from (L, U) to (Ln, Un); no entry normalisation. */
@@ -493,17 +530,23 @@ static void normalize_bounds(const orc_problem* P, const orc_params* prm, double
     }
     lb[j] = lb[j] + 0.0;
     ub[j] = ub[j] + 0.0;
+    if (prm->store32) {
+      lb[j] = store_down(lb[j]);
+      ub[j] = store_up(ub[j]);
+    }
   }
 }
 
 /* Full run: lb/ub in, tightened lb/ub out (unspecified when INFEASIBLE). */
-int orc_run(int32_t m, int32_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
-            const double* lhs, const double* rhs, const uint8_t* vartype, double eps_int,
-            double cont_rel_tol, double feas_tol, double* lb, double* ub, int32_t max_rounds,
-            int32_t* status, int32_t* rounds, int64_t* flags) {
+static int run_impl(int32_t m, int32_t n, const int64_t* row_ptr, const int32_t* col,
+                    const double* val, const double* lhs, const double* rhs,
+                    const uint8_t* vartype, double eps_int, double cont_rel_tol, double feas_tol,
+                    int store32, double* lb, double* ub, int32_t max_rounds, int32_t* status,
+                    int32_t* rounds, int64_t* flags) {
   orc_problem P = {m, n, row_ptr, col, val, lhs, rhs, vartype};
   orc_params prm;
   fill_params(&prm, eps_int, cont_rel_tol, feas_tol);
+  prm.store32 = store32;
   if (max_rounds < 0) return ORC_EINVAL;
   int rc = orc_validate_problem(&P);
   if (rc) return rc;
@@ -559,6 +602,26 @@ int orc_run(int32_t m, int32_t n, const int64_t* row_ptr, const int32_t* col, co
   free(Un);
   free(A);
   return 0;
+}
+
+int orc_run(int32_t m, int32_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+            const double* lhs, const double* rhs, const uint8_t* vartype, double eps_int,
+            double cont_rel_tol, double feas_tol, double* lb, double* ub, int32_t max_rounds,
+            int32_t* status, int32_t* rounds, int64_t* flags) {
+  return run_impl(m, n, row_ptr, col, val, lhs, rhs, vartype, eps_int, cont_rel_tol, feas_tol, 0,
+                  lb, ub, max_rounds, status, rounds, flags);
+}
+
+/* The same run with the bound store of R10: store_bits 64 (doubles, as
+   orc_run) or 32 (single precision, rounded outward). */
+int orc_run_store(int32_t m, int32_t n, const int64_t* row_ptr, const int32_t* col,
+                  const double* val, const double* lhs, const double* rhs,
+                  const uint8_t* vartype, double eps_int, double cont_rel_tol, double feas_tol,
+                  int32_t store_bits, double* lb, double* ub, int32_t max_rounds,
+                  int32_t* status, int32_t* rounds, int64_t* flags) {
+  if (store_bits != 32 && store_bits != 64) return ORC_EINVAL;
+  return run_impl(m, n, row_ptr, col, val, lhs, rhs, vartype, eps_int, cont_rel_tol, feas_tol,
+                  store_bits == 32, lb, ub, max_rounds, status, rounds, flags);
 }
 
 /* ------------------------------------------------------------------ */

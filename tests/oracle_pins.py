@@ -146,7 +146,7 @@ def check_activities_spmv(orc):
 def check_closed_forms(orc):
     for c in load_closed_forms():
         inst = case_instance(c)
-        r = orc.run(inst, inst.lb, inst.ub, c["max_rounds"], case_params(c))
+        r = orc.run(inst, inst.lb, inst.ub, c["max_rounds"], case_params(c), c.get("store", 64))
         e = c["expect"]
         assert (r.status, r.rounds) == (e["status"], e["rounds"]), (c["name"], r.status, r.rounds)
         if "lb" in e:
@@ -393,6 +393,135 @@ def check_validation(orc):
     assert bad(vt=[2, 1])
 
 
+# ---------------------------------------------------------------------------
+# single-precision bound store, rounded outward (reading R10)
+# ---------------------------------------------------------------------------
+F32_MIN = float(np.finfo(np.float32).tiny)  # smallest normal single
+F32_MAX = float(np.finfo(np.float32).max)
+
+
+def _in_store_grid(x):
+    """x is 0, an infinity, or a normal single-precision number."""
+    if x == 0.0 or math.isinf(x):
+        return True
+    if not F32_MIN <= abs(x) <= F32_MAX:
+        return False
+    return float(np.float32(x)) == x
+
+
+def _grid_next(f, up):
+    """The neighbour of grid member f in the given direction (the grid skips
+    the subnormal singles)."""
+    if up:
+        if f == -math.inf:
+            return -F32_MAX
+        if f == -F32_MIN:
+            return 0.0
+        if f == 0.0:
+            return F32_MIN
+        if f == F32_MAX:
+            return math.inf
+        return float(np.nextafter(np.float32(f), np.float32(np.inf)))
+    return -_grid_next(-f, True)
+
+
+def _store_probe_values(seed=5, count=6000):
+    rng = np.random.default_rng(seed)
+    vals = [0.0, -0.0, math.inf, -math.inf, F32_MIN, -F32_MIN, F32_MAX, -F32_MAX,
+            F32_MIN / 2, -F32_MIN / 2, 5e-324, -5e-324, F32_MAX * (1 + 2.0**-30), 1e39, -1e39,
+            0.1, 0.9, 1.9999999, 1.0 + 2.0**-30, 16777217.0, -16777217.0, 2.0**200, -2.0**200]
+    # random doubles over the whole exponent range a bound may take
+    e = rng.integers(-160, 161, size=count)
+    m = 1.0 + rng.random(count)
+    sgn = np.where(rng.random(count) < 0.5, -1.0, 1.0)
+    vals += list(sgn * np.ldexp(m, e))
+    # singles, and the doubles next to them and halfway between two of them
+    f = np.float32(np.ldexp(m[:1500], np.clip(e[:1500], -120, 120)) * sgn[:1500])
+    for x in f.astype(np.float64):
+        vals += [x, np.nextafter(x, np.inf), np.nextafter(x, -np.inf)]
+        y = float(np.nextafter(np.float32(x), np.float32(np.inf)))
+        vals.append((x + y) / 2)
+    # integers near 2^24, where the singles stop being every integer
+    vals += [float(2**24 + k) for k in range(-3, 6)]
+    return [float(v) for v in vals]
+
+
+def check_store_grid(orc):
+    """The store's roundings, by their definition: down(x) is a grid member
+    not above x whose upper neighbour is above x, up(x) the mirror image;
+    grid members map to themselves."""
+    for x in _store_probe_values():
+        d, u = orc.store_down(x), orc.store_up(x)
+        assert _in_store_grid(d) and _in_store_grid(u), (x, d, u)
+        assert d <= x <= u, (x, d, u)
+        if not math.isinf(x):
+            assert _grid_next(d, True) > x, (x, d)
+            assert _grid_next(u, False) < x, (x, u)
+        if _in_store_grid(x):
+            assert d == x == u, (x, d, u)
+        assert not (d == 0.0 and math.copysign(1.0, d) < 0), x
+
+
+def check_store_integer_identity(orc, count=40):
+    """Integer bounds below 2^24 are grid members: on pure-integer systems the
+    single-precision store gives the FP64 store's results bitwise."""
+    for s in range(count):
+        inst = synth.random_small(700 + s, m=int(3 + s % 6), n=int(3 + s % 5), box=8, slack=4.0)
+        a = orc.run(inst, inst.lb, inst.ub, 200)
+        b = orc.run(inst, inst.lb, inst.ub, 200, store=32)
+        assert (a.status, a.rounds) == (b.status, b.rounds), s
+        if a.status != oracle_mod.INFEASIBLE:
+            assert np.array_equal(a.lb, b.lb) and np.array_equal(a.ub, b.ub), s
+
+
+def check_store_sound(orc, count=40):
+    """Outward rounding only loosens: on one continuous row over a box the
+    stored bounds contain the exact projection (linear programming) and stay
+    within a few single-precision steps of it; feasible integer points stay
+    inside; every stored bound is a grid member."""
+    from scipy.optimize import linprog
+
+    for s in range(count):
+        rng = np.random.default_rng(3000 + s)
+        n = int(rng.integers(2, 6))
+        a = rng.integers(1, 6, size=n) * np.where(rng.random(n) < 0.5, -1, 1).astype(float)
+        lo = rng.integers(-5, 1, size=n).astype(float) + 0.1 * rng.integers(0, 10, size=n)
+        hi = lo + rng.integers(1, 8, size=n) + 0.3
+        x0 = lo + rng.random(n) * (hi - lo)
+        s0 = float(a @ x0)
+        lhs = s0 - 0.7 * float(rng.integers(0, 3))
+        rhs = s0 + 0.7 * float(rng.integers(0, 3))
+        inst = synth.from_rows([[(j, a[j]) for j in range(n)]], [lhs], [rhs], lo, hi,
+                               np.zeros(n), n=n)
+        r = orc.run(inst, lo, hi, 100, oracle_mod.Params(cont_rel_tol=0.0), store=32)
+        assert r.status == oracle_mod.CONVERGED, s
+        assert all(_in_store_grid(v) for v in np.concatenate([r.lb, r.ub])), s
+        kw = dict(A_ub=np.array([a, -a]), b_ub=np.array([rhs, -lhs]), bounds=list(zip(lo, hi)),
+                  method="highs")
+        for j in range(n):
+            c = np.zeros(n)
+            c[j] = 1.0
+            lo_j = linprog(c, **kw).fun
+            hi_j = -linprog(-c, **kw).fun
+            tol = 1e-9 * max(1.0, abs(lo_j), abs(hi_j))
+            assert r.lb[j] <= lo_j + tol and r.ub[j] >= hi_j - tol, (s, j)
+            assert r.lb[j] >= lo_j - 1e-4 and r.ub[j] <= hi_j + 1e-4, (s, j, r.lb[j], lo_j)
+    for s in range(count):
+        inst = synth.random_small(900 + s, m=int(3 + s % 5), n=int(3 + s % 4), box=4, slack=3.0)
+        pts = _feasible_points(inst)
+        r = orc.run(inst, inst.lb, inst.ub, 100, store=32)
+        if r.status == oracle_mod.INFEASIBLE:
+            assert pts.shape[0] == 0, s
+        elif pts.shape[0]:
+            assert np.all(pts >= r.lb) and np.all(pts <= r.ub), s
+    for inst in (synth.config0(), synth.config0(1)):
+        r = orc.run(inst, inst.lb, inst.ub, 100, store=32)
+        assert r.status == oracle_mod.CONVERGED
+        tol = 1e-6 * np.maximum(1.0, np.abs(inst.x0))
+        assert np.all(r.lb - tol <= inst.x0) and np.all(inst.x0 <= r.ub + tol)
+        assert all(_in_store_grid(v) for v in np.concatenate([r.lb, r.ub]))
+
+
 ALL_CHECKS = [
     check_exact_dot_special,
     check_exact_dot_random,
@@ -408,4 +537,7 @@ ALL_CHECKS = [
     check_permutation_invariance,
     check_sequential_limit_point,
     check_validation,
+    check_store_grid,
+    check_store_integer_identity,
+    check_store_sound,
 ]

@@ -29,6 +29,8 @@ def test_closed_forms():
     for c in pins.load_closed_forms():
         if c["name"].startswith("exact_sum"):
             continue  # plain sums round differently on purpose
+        if c.get("store", 64) != 64:
+            continue  # the sequential baseline keeps its bounds in FP64
         inst = pins.case_instance(c)
         e = c["expect"]
         cs = oracle.CpuSeq(inst)

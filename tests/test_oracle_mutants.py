@@ -48,6 +48,18 @@ MUTANTS = [
     ("last_row_skipped", "  for (int32_t i = 0; i < P->m; i++) {\n    double minfin, maxfin;\n    int64_t mininf, maxinf;\n    row_activity(P, i, L, U,",
      "  for (int32_t i = 0; i < P->m - 1; i++) {\n    double minfin, maxfin;\n    int64_t mininf, maxinf;\n    row_activity(P, i, L, U,"),
     ("negative_products_added", "  int side = ((a < 0.0) != (b < 0.0)) ? 1 : 0;", "  int side = 0;"),
+    ("store_rounds_nearest_not_down", "  if ((double)f > x) f = nextafterf(f, -INFINITY);",
+     "  if (0) f = nextafterf(f, -INFINITY);"),
+    ("store_rounds_inward", "static double store_up(double x) { return -store_down(-x) + 0.0; }",
+     "static double store_up(double x) { return store_down(x); }"),
+    ("store_keeps_subnormals", "  if (x > 0.0 && x < FLT_MIN) return 0.0;", "  if (0) return 0.0;"),
+    ("store_not_applied_at_commit", "    if (prm->store32) {\n      Ln[j] = store_down(Ln[j]);",
+     "    if (0) {\n      Ln[j] = store_down(Ln[j]);"),
+    ("store_change_test_before_rounding",
+     "    if (prm->store32) {\n      Ln[j] = store_down(Ln[j]);\n      Un[j] = store_up(Un[j]);\n    }\n    if (Ln[j] != L[j] || Un[j] != U[j]) ch = 1;",
+     "    if (Ln[j] != L[j] || Un[j] != U[j]) ch = 1;\n    if (prm->store32) {\n      Ln[j] = store_down(Ln[j]);\n      Un[j] = store_up(Un[j]);\n    }"),
+    ("store_input_not_rounded", "    if (prm->store32) {\n      lb[j] = store_down(lb[j]);",
+     "    if (0) {\n      lb[j] = store_down(lb[j]);"),
     ("integer_input_not_rounded", "      lb[j] = ceil(lb[j] - prm->eps_int);\n      ub[j] = floor(ub[j] + prm->eps_int);",
      "      lb[j] = lb[j];\n      ub[j] = ub[j];"),
 ]
