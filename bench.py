@@ -180,6 +180,8 @@ def main():
                     help="skip the 2,000 x 1,000 and 200,000 x 100,000 single-instance lines")
     ap.add_argument("--no-layouts", action="store_true",
                     help="skip the nnz-split layout comparison")
+    ap.add_argument("--no-store32", action="store_true",
+                    help="skip the single-precision bound store comparison")
     ap.add_argument("--no-children", action="store_true",
                     help="skip the branch-and-bound children leg (marked rounds from a parent)")
     ap.add_argument("--no-batch", action="store_true",
@@ -350,6 +352,9 @@ def main():
 
     small = None if args.no_small else small_configs(args.max_rounds)
     layouts = None if args.no_layouts else layout_compare(args.max_rounds, inst)
+    store32 = None if args.no_store32 else store_compare(prob, inst, args.max_rounds)
+    prob.set_loop(args.loop)
+    prob.set_kernel_timing(args.loop != "persistent")
 
     batch = None if args.no_batch else batched_nodes(args.batch_nodes, args.max_rounds)
     children = None if args.no_children else children_nodes(args.batch_nodes, args.max_rounds)
@@ -408,6 +413,7 @@ def main():
         "marked": marked,
         "small_configs": small,
         "layouts": layouts,
+        "store32": store32,
         "batched": batch,
         "children": children,
         "serving": serve,
@@ -502,6 +508,74 @@ def layout_compare(max_rounds: int, inst2, reps: int = 6):
         out[key] = {**res, "identical_results": same,
                     "nnz_split_over_chunks": res["nnz_split"]["loop_ms"] / res["chunks"]["loop_ms"]}
     log(f"layouts: {out}")
+    return out
+
+
+def store_compare(prob2, inst2, max_rounds: int, reps: int = 6):
+    """The single-precision bound store (FP64 arithmetic, bounds kept as
+    singles rounded outward) against the FP64 store, on the 5,000,000 x
+    2,000,000 and 200,000 x 100,000 instances: round-kernel time per launch,
+    run time, rounds, and how far the final bounds moved (outward rounding
+    only loosens, so the single-precision results are never tighter where
+    the runs otherwise agree)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2009_07785_amd import Problem
+
+    dev = torch.device("cuda:0")
+    out = {}
+    for key in ("config2", "config1"):
+        if key == "config2":
+            inst, p = inst2, prob2
+        else:
+            inst = synth.cached("config1_bench", synth.config1, 1)
+            p = Problem.from_instance(inst)
+        p.set_loop("stream")
+        p.set_kernel_timing(True)
+        rl = torch.tensor(inst.lb, dtype=torch.float64, device=dev)
+        ru = torch.tensor(inst.ub, dtype=torch.float64, device=dev)
+        dl, du = torch.empty_like(rl), torch.empty_like(ru)
+        res, final = {}, {}
+        for bits in (64, 32):
+            p.set_store(bits)
+            lm, km, kn, seen = [], [], [], set()
+            for i in range(reps + 1):
+                dl.copy_(rl)
+                du.copy_(ru)
+                r = p.run_device(dl, du, max_rounds)
+                seen.add((r.status, r.rounds, hash(dl.cpu().numpy().tobytes()),
+                          hash(du.cpu().numpy().tobytes())))
+                if i:
+                    lm.append(p.last_timing()[0])
+                    a, b = p.last_kernel_timing()
+                    km.append(a)
+                    kn.append(b)
+            res[f"f{bits}"] = {"loop_ms": float(np.median(lm)),
+                               "round_kernel_us": 1e3 * float(np.sum(km)) / max(1, int(np.sum(kn))),
+                               "status": ["CONVERGED", "INFEASIBLE", "MAX_ROUNDS"][r.status],
+                               "rounds": r.rounds, "repeatable": len(seen) == 1}
+            final[bits] = (dl.cpu().numpy(), du.cpu().numpy())
+        p.set_store(64)
+        if key != "config2":
+            p.close()
+        (l64, u64), (l32, u32) = final[64], final[32]
+        is_int = inst.vartype != 0
+        dlb, dub = l32 != l64, u32 != u64
+        fin = np.isfinite(l64) & np.isfinite(u64) & np.isfinite(l32) & np.isfinite(u32)
+        w64 = np.where(fin, u64 - l64, 0.0)
+        w32 = np.where(fin, u32 - l32, 0.0)
+        rel = np.where(fin & (w64 > 0), (w32 - w64) / np.maximum(w64, 1e-300), 0.0)
+        out[key] = {**res,
+                    "bounds_differing": int(dlb.sum() + dub.sum()),
+                    "integer_bounds_differing": int((dlb & is_int).sum() + (dub & is_int).sum()),
+                    "looser_or_equal": bool(np.all(l32 <= l64) and np.all(u32 >= u64)),
+                    "bounds_tighter_than_f64": int((l32 > l64).sum() + (u32 < u64).sum()),
+                    "max_rel_width_increase": float(rel.max()) if rel.size else 0.0,
+                    "f32_over_f64_round_kernel": res["f32"]["round_kernel_us"]
+                    / res["f64"]["round_kernel_us"]}
+    log(f"store32: {out}")
     return out
 
 

@@ -70,6 +70,10 @@ extern "C" {
 #define PROP_CONTINUOUS 0
 #define PROP_INTEGER 1
 
+/* Bound stores (prop_set_store). */
+#define PROP_STORE_F64 64 /* default: bounds kept as doubles */
+#define PROP_STORE_F32 32 /* bounds kept in single precision, rounded outward */
+
 /* Round-loop drivers (prop_set_loop).  All give identical results. */
 #define PROP_LOOP_PERSISTENT 0 /* one cooperative launch, grid barriers between phases */
 #define PROP_LOOP_STREAM 1     /* default: per-round kernels queued in batches; the host
@@ -250,8 +254,9 @@ int prop_set_marking(prop_problem* p, int32_t enable);
  * d_lb, d_ub: device arrays of n doubles holding bounds that are a fixed
  * point of this problem's propagation, such as the bounds a CONVERGED run
  * returned; the library keeps a copy (integer bounds rounded as at the
- * start of a run), so the caller's arrays may be reused at once.  While a
- * parent is set and marked rounds are enabled, round 1 of prop_run,
+ * start of a run, and rounded outward under the single-precision store of
+ * prop_set_store, which must be the store the parent was computed with),
+ * so the caller's arrays may be reused at once.  While a parent is set and marked rounds are enabled, round 1 of prop_run,
  * prop_run_device, prop_run_batch and prop_run_batch_device processes only
  * the rows holding a variable whose start bounds differ from the parent's
  * (in a batch: in any node of the row's group): every other row would
@@ -264,6 +269,32 @@ int prop_set_marking(prop_problem* p, int32_t enable);
  * and clears the parent.  The first call allocates 16 * n bytes (and the
  * marking data, as prop_set_marking does). */
 int prop_set_parent(prop_problem* p, const double* d_lb, const double* d_ub, void* stream);
+
+/* Bound store for later runs of prop_run and prop_run_device (every
+ * driver): PROP_STORE_F64 (default) or PROP_STORE_F32, the mixed-precision
+ * variant of the paper's single-precision runs (Sec. 4.5, where the method
+ * run wholly in single precision gives wrong results).  With PROP_STORE_F32
+ * the arithmetic is unchanged (the numerical contract above), but every
+ * bound is kept on the grid G of 0, -inf, +inf and the normal single-precision
+ * numbers, rounded outward: a lower bound becomes the largest member of G
+ * not above it, an upper bound the smallest member not below it.  This
+ * applies to the input bounds after their integer rounding and to every
+ * bound a round commits, before the round decides whether anything
+ * changed; a gain smaller than one step of G therefore changes nothing.
+ * Outward rounding only loosens bounds, so no point that the FP64 store
+ * keeps is cut off and no problem is reported infeasible that the FP64
+ * store finds feasible; bounds beyond the single-precision range become
+ * infinite, and integer bounds stay integers (every integer up to 2^24 is
+ * in G).  The activity pass then gathers 8 bytes per continuous variable
+ * instead of 16.  Returned bounds are doubles holding members of G.
+ * Results are bitwise those of the test oracle's single-precision store.
+ * The first PROP_STORE_F32 allocates 8 * n bytes, kept until prop_destroy.
+ * Changing the store clears the parent (prop_set_parent) and any captured
+ * rounds.  The nnz-split layout (prop_params.layout 1) returns
+ * PROP_EINVAL, and while PROP_STORE_F32 is set, prop_run_batch,
+ * prop_run_batch_device, prop_run_batch_device_static and
+ * prop_srv_add_instance return PROP_EINVAL. */
+int prop_set_store(prop_problem* p, int32_t bits);
 
 /* Fills *out with the problem's sizes. */
 int prop_get_info(const prop_problem* p, prop_info* out);

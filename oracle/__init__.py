@@ -163,7 +163,7 @@ class Oracle:
             store: int = 64) -> Result:
         """Full synchronous propagation: status, rounds and the bounds.
         ``store=32`` keeps the bounds in single precision, rounded outward
-        (reading R10 of ``prop_oracle.c``)."""
+        (reading R12 of ``prop_oracle.c``)."""
         p = params or Params()
         rp, ci, va, lh, rh, vt = _problem_arrays(inst)
         lb = np.array(lb, dtype=np.float64, copy=True)

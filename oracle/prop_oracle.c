@@ -51,7 +51,9 @@
  *   R9  before round 1 the integer bounds are rounded as in R4, and the run
  *       stops with status INFEASIBLE after 0 rounds when an input domain is
  *       empty (R7), some row has lhs > rhs, or an empty row excludes 0;
- *   R10 single-precision bound store (orc_run_store with 32; Sec. 4.5 runs
+ *   R12 (numbered as in the design notes, whose R10 and R11 state the
+ *       synchronous update and the IEEE infinities this file also follows)
+ *       single-precision bound store (orc_run_store with 32; Sec. 4.5 runs
  *       the whole method in single precision and reports results that are
  *       no longer correct): all arithmetic stays as in R1-R9, but every
  *       bound is kept as a member of F = {0, -inf, +inf} together with the
@@ -231,7 +233,7 @@ typedef struct {
 
 typedef struct {
   double eps_int, cont_rel_tol, feas_tol;
-  int store32; /* R10 */
+  int store32; /* R12 */
 } orc_params;
 
 static int valid_value(double x) { return isfinite(x) && fabs(x) <= orc_huge(); }
@@ -282,7 +284,7 @@ static int orc_validate_bounds(const orc_problem* P, const double* lb, const dou
   return 0;
 }
 
-/* Reading R10: the largest member of F not above x (x not NaN). */
+/* Reading R12: the largest member of F not above x (x not NaN). */
 static double store_down(double x) {
   if (isinf(x) || x == 0.0) return x + 0.0;
   if (x > FLT_MAX) return FLT_MAX;
@@ -294,7 +296,7 @@ static double store_down(double x) {
   return (double)f;
 }
 
-/* Reading R10: the smallest member of F not below x. */
+/* Reading R12: the smallest member of F not below x. */
 static double store_up(double x) { return -store_down(-x) + 0.0; }
 
 /* Exported for the oracle's own pins. */
@@ -612,7 +614,7 @@ int orc_run(int32_t m, int32_t n, const int64_t* row_ptr, const int32_t* col, co
                   lb, ub, max_rounds, status, rounds, flags);
 }
 
-/* The same run with the bound store of R10: store_bits 64 (doubles, as
+/* The same run with the bound store of R12: store_bits 64 (doubles, as
    orc_run) or 32 (single precision, rounded outward). */
 int orc_run_store(int32_t m, int32_t n, const int64_t* row_ptr, const int32_t* col,
                   const double* val, const double* lhs, const double* rhs,

@@ -22,11 +22,13 @@ OK, EINVAL, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4
 LOOP_PERSISTENT, LOOP_STREAM, LOOP_HOST, LOOP_GRAPH = 0, 1, 2, 3
 LOOP_NAMES = {"persistent": LOOP_PERSISTENT, "stream": LOOP_STREAM, "host": LOOP_HOST,
               "graph": LOOP_GRAPH}
+STORE_F64, STORE_F32 = 64, 32
 
 # every function the header declares
 EXPORTED = ("prop_create", "prop_autotune", "prop_run", "prop_run_device", "prop_run_batch",
             "prop_run_batch_device", "prop_run_batch_device_static",
-            "prop_set_loop", "prop_set_marking", "prop_set_parent", "prop_get_info",
+            "prop_set_loop", "prop_set_marking", "prop_set_parent", "prop_set_store",
+            "prop_get_info",
             "prop_last_timing", "prop_set_kernel_timing", "prop_last_kernel_timing",
             "prop_destroy", "prop_last_error",
             "prop_srv_create", "prop_srv_add_instance", "prop_srv_submit", "prop_srv_poll",
@@ -114,6 +116,8 @@ def _load():
     lib.prop_set_marking.argtypes = [P, i32]
     lib.prop_set_marking.restype = ctypes.c_int
     lib.prop_set_parent.argtypes = [P, P, P, P]
+    lib.prop_set_store.argtypes = [P, i32]
+    lib.prop_set_store.restype = ctypes.c_int
     lib.prop_set_parent.restype = ctypes.c_int
     lib.prop_get_info.argtypes = [P, ctypes.POINTER(_Info)]
     lib.prop_get_info.restype = ctypes.c_int
@@ -322,6 +326,11 @@ class Problem:
         _check(lib.prop_set_parent(self._h, ctypes.c_void_p(d_lb.data_ptr()),
                                    ctypes.c_void_p(d_ub.data_ptr()),
                                    ctypes.c_void_p(int(raw) if raw else 0)))
+
+    def set_store(self, bits: int):
+        """Bound store of later single runs: 64 (doubles) or 32 (single
+        precision, rounded outward; FP64 arithmetic)."""
+        _check(lib.prop_set_store(self._h, int(bits)))
 
     def info(self) -> dict:
         inf = _Info()

@@ -228,14 +228,14 @@ __device__ __forceinline__ void round_unit(const Problem& P, const Batch& Bt, in
   const bool marked = kMarks && group_marked(P, Bt, g, r, marks);
   if (unit < P.n_segs) {
     if (few)
-      seg_phase1<false>(P, unit, Bt.gA[g], kNodeGroup, mask, Bt.partials, Bt.nodes,
+      seg_phase1<kSrcPairs>(P, unit, Bt.gA[g], kNodeGroup, mask, Bt.partials, Bt.nodes,
                         g * kNodeGroup, marked, r, marks);
     else
       seg_phase1_nodes(P, unit, Bt.gA[g], mask, Bt.partials, Bt.nodes, g * kNodeGroup, marked, r,
                        marks);
   } else {
     if (few)
-      chunk_dispatch<false>(P, unit - P.n_segs, Bt.gA[g], Bt.gB[g], kNodeGroup, mask, exact,
+      chunk_dispatch<kSrcPairs>(P, unit - P.n_segs, Bt.gA[g], Bt.gB[g], kNodeGroup, mask, exact,
                             marked, r, marks);
     else
       chunk_round_nodes(P, P.chunks[unit - P.n_segs], Bt.gA[g], Bt.gB[g], mask, exact, marked, r,

@@ -169,6 +169,50 @@ __device__ __forceinline__ bool decode_code(uint16_t w, double& l, double& u) {
   return lb != -128;
 }
 
+// ---------------------------------------------------------------------------
+// Single-precision bound store (Problem::store32; Sec. 4.5 of the paper runs
+// the whole method in single precision and loses correctness).  Here the
+// arithmetic stays FP64; only the stored bounds move to the grid of zero,
+// the infinities and the normal singles, rounded outward: a lower bound to
+// the largest grid member not above it, an upper bound to the smallest not
+// below it.  Outward rounding only loosens a bound, so every point the FP64
+// store keeps is kept; integers below 2^24 are grid members.  The rounding
+// happens at the pack and at every commit, before the change test.
+// ---------------------------------------------------------------------------
+// Each result is taken from a branch of its own, never by negating the
+// other direction's result: a zero then comes from the literal +0, and no
+// sign change is left for the compiler to fold into a later conversion.
+// Near a representable single, the conversion to nearest is at most one
+// grid step off; a normal single's neighbour is one step of its bit pattern
+// (towards zero the magnitude shrinks, away from it it grows).
+__device__ __forceinline__ float store_down32(double x) {
+  float f;
+  if (is_inf(x)) f = x > 0.0 ? __builtin_inff() : -__builtin_inff();
+  else if (x > (double)__FLT_MAX__) f = __FLT_MAX__;
+  else if (x < -(double)__FLT_MAX__) f = -__builtin_inff();
+  else if (x >= 0.0 && x < (double)__FLT_MIN__) f = 0.0f;  // both zeros too
+  else if (x < 0.0 && x > -(double)__FLT_MIN__) f = -__FLT_MIN__;
+  else {
+    f = (float)x;
+    if ((double)f > x) f = __int_as_float(__float_as_int(f) + (f > 0.0f ? -1 : 1));
+  }
+  return f;
+}
+
+__device__ __forceinline__ float store_up32(double x) {
+  float f;
+  if (is_inf(x)) f = x > 0.0 ? __builtin_inff() : -__builtin_inff();
+  else if (x < -(double)__FLT_MAX__) f = -__FLT_MAX__;
+  else if (x > (double)__FLT_MAX__) f = __builtin_inff();
+  else if (x <= 0.0 && x > -(double)__FLT_MIN__) f = 0.0f;  // both zeros too
+  else if (x > 0.0 && x < (double)__FLT_MIN__) f = __FLT_MIN__;
+  else {
+    f = (float)x;
+    if ((double)f < x) f = __int_as_float(__float_as_int(f) + (f > 0.0f ? 1 : -1));
+  }
+  return f;
+}
+
 // Fire-and-forget FP64 atomics (the result is unused, so no wave waits).
 __device__ __forceinline__ void atomic_max_f64(double* p, double v) {
   (void)__hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -480,16 +524,38 @@ constexpr int kStepGroup = 2;
 static_assert(kStepGroup == 1 || kStepGroup == 2 || kStepGroup == 4,
               "lane_steps handles remainders of up to 3 steps");
 
-// Start-of-round bounds of N entries (column words cv): with kCodes, an
+// Where the activity pass finds start-of-round bounds: the pair arrays
+// (batches), integer variables' codes and the FP64 pairs of the rest (single
+// runs), or codes and the single-precision copies (single runs with the
+// single-precision store; the copies hold the pairs' exact values).
+constexpr int kSrcPairs = 0;
+constexpr int kSrcCodes = 1;
+constexpr int kSrcCodes32 = 2;
+
+// Bounds of variable word cw for node t, from the pairs or, with kSrcCodes32,
+// from the single-precision copies.
+template <int kSrc>
+__device__ __forceinline__ double2 pair_of(const double2* __restrict__ cur,
+                                           const float2* __restrict__ c32, int32_t cw,
+                                           uint32_t stride, uint32_t t) {
+  if (kSrc == kSrcCodes32) {
+    const float2 f = c32[cw & kColMask];
+    return make_double2((double)f.x, (double)f.y);
+  }
+  return cur[(size_t)(cw & kColMask) * stride + t];
+}
+
+// Start-of-round bounds of N entries (column words cv): with codes, an
 // integer variable's 2-byte code (its pair only on escape) and a continuous
 // variable's pair; otherwise the pairs.  All first gathers are issued before
 // any escape gather.
-template <int N, bool kCodes>
+template <int N, int kSrc>
 __device__ __forceinline__ void gather_bounds(const double2* __restrict__ cur,
+                                              const float2* __restrict__ c32,
                                               const uint16_t* __restrict__ codes,
                                               const int32_t* cv, uint32_t stride, uint32_t t,
                                               double2* bv) {
-  if (kCodes) {
+  if (kSrc != kSrcPairs) {
     bool pair[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -501,14 +567,14 @@ __device__ __forceinline__ void gather_bounds(const double2* __restrict__ cur,
     }
 #pragma unroll
     for (int k = 0; k < N; ++k)
-      if (pair[k]) bv[k] = cur[(size_t)(cv[k] & kColMask) * stride + t];
+      if (pair[k]) bv[k] = pair_of<kSrc>(cur, c32, cv[k], stride, t);
   } else {
 #pragma unroll
     for (int k = 0; k < N; ++k) bv[k] = cur[(size_t)(cv[k] & kColMask) * stride + t];
   }
 }
 
-template <int N, bool kCodes>
+template <int N, int kSrc>
 __device__ __forceinline__ void chunk_steps(const Problem& P, const double2* __restrict__ cur,
                                             const uint16_t* __restrict__ codes, uint32_t stride,
                                             uint32_t t, size_t e0, LaneAcc& L) {
@@ -522,7 +588,7 @@ __device__ __forceinline__ void chunk_steps(const Problem& P, const double2* __r
     cv[k] = stride == 1 ? __builtin_nontemporal_load(P.cols + e) : P.cols[e];
   }
   double2 bv[N];
-  gather_bounds<N, kCodes>(cur, codes, cv, stride, t, bv);
+  gather_bounds<N, kSrc>(cur, P.b32, codes, cv, stride, t, bv);
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     if (av[k] != 0.0) {
@@ -533,18 +599,18 @@ __device__ __forceinline__ void chunk_steps(const Problem& P, const double2* __r
 }
 
 // The activity pass over W steps of one lane, starting at entry e0.
-template <bool kCodes>
+template <int kSrc>
 __device__ __forceinline__ void lane_steps(const Problem& P, const double2* __restrict__ cur,
                                            const uint16_t* __restrict__ codes, uint32_t stride,
                                            uint32_t t, size_t e0, int W, LaneAcc& L) {
   int w0 = 0;
   for (; w0 + kStepGroup <= W; w0 += kStepGroup)
-    chunk_steps<kStepGroup, kCodes>(P, cur, codes, stride, t, e0 + (size_t)w0 * kWave, L);
+    chunk_steps<kStepGroup, kSrc>(P, cur, codes, stride, t, e0 + (size_t)w0 * kWave, L);
   // W is the same in every lane
   switch (W - w0) {
-    case 3: chunk_steps<3, kCodes>(P, cur, codes, stride, t, e0 + (size_t)w0 * kWave, L); break;
-    case 2: chunk_steps<2, kCodes>(P, cur, codes, stride, t, e0 + (size_t)w0 * kWave, L); break;
-    case 1: chunk_steps<1, kCodes>(P, cur, codes, stride, t, e0 + (size_t)w0 * kWave, L); break;
+    case 3: chunk_steps<3, kSrc>(P, cur, codes, stride, t, e0 + (size_t)w0 * kWave, L); break;
+    case 2: chunk_steps<2, kSrc>(P, cur, codes, stride, t, e0 + (size_t)w0 * kWave, L); break;
+    case 1: chunk_steps<1, kSrc>(P, cur, codes, stride, t, e0 + (size_t)w0 * kWave, L); break;
     default: break;
   }
 }
@@ -560,7 +626,7 @@ __device__ __forceinline__ void lane_steps(const Problem& P, const double2* __re
 // contribution (LaneAcc): "slack > largest threshold" skips every entry of
 // the lane exactly as the per-entry test would, so only lanes holding an
 // entry that may count revisit their entries, with the exact test.
-template <bool kCodes>
+template <int kSrc>
 __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd,
                                             const double2* __restrict__ cur,
                                             double2* __restrict__ nxt, uint32_t stride,
@@ -582,7 +648,7 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
     const uint32_t t = __builtin_ctz(mask);
     LaneAcc L;
     lane_acc_init(L);
-    if (want) lane_steps<kCodes>(P, cur, P.codes, stride, t, base, W, L);
+    if (want) lane_steps<kSrc>(P, cur, P.codes, stride, t, base, W, L);
     group_reduce(L.smin, L.smax, L.emin, L.emax, L.cmin, L.cmax, klog);
     RowState R = make_row_state(L.smin, L.smax, L.emin, L.emax, L.cmin, L.cmax, lhs, rhs,
                                 (exact_mask >> t) & 1u);
@@ -601,7 +667,7 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
         }
         double2 bv[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) bv[k] = cur[(size_t)(cv[k] & kColMask) * stride + t];
+        for (int k = 0; k < 4; ++k) bv[k] = pair_of<kSrc>(cur, P.b32, cv[k], stride, t);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
           if (k < cnt && av[k] != 0.0)
@@ -617,15 +683,15 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
   }
 }
 
-// kCodes: the single run's bounds, with the compact codes of integer
-// variables (P.codes); batches pass their own bound arrays without codes.
-template <bool kCodes>
+// kSrc: where the activity pass reads bounds (kSrcPairs for batches, which
+// pass their own bound arrays; kSrcCodes / kSrcCodes32 for single runs).
+template <int kSrc>
 __device__ __forceinline__ void chunk_dispatch(const Problem& P, int c, const double2* cur,
                                                double2* nxt, uint32_t stride,
                                                uint32_t node_mask, uint32_t exact_mask,
                                                bool marked = false, int r_round = 0,
                                                const int32_t* marks = nullptr) {
-  chunk_round<kCodes>(P, P.chunks[c], cur, nxt, stride, node_mask, exact_mask, marked, r_round,
+  chunk_round<kSrc>(P, P.chunks[c], cur, nxt, stride, node_mask, exact_mask, marked, r_round,
                       marks);
 }
 
@@ -813,7 +879,7 @@ __device__ __forceinline__ void nz_wave_round(const Problem& P, int w,
       cv[k] = __builtin_nontemporal_load(P.cols + e);
     }
     double2 bv[2];
-    gather_bounds<2, true>(cur, P.codes, cv, 1, 0, bv);
+    gather_bounds<2, kSrcCodes>(cur, nullptr, P.codes, cv, 1, 0, bv);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int kk = k0 + k;
@@ -1087,7 +1153,7 @@ __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkD
 // ---------------------------------------------------------------------------
 // long rows: partials live at partials[segment * pstride + node]
 // ---------------------------------------------------------------------------
-template <bool kCodes>
+template <int kSrc>
 __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
                                            const double2* __restrict__ cur, uint32_t stride,
                                            uint32_t node_mask, SegPartial* parts,
@@ -1104,7 +1170,7 @@ __device__ __forceinline__ void seg_phase1(const Problem& P, int s,
     const uint32_t t = __builtin_ctz(mask);
     LaneAcc L;
     lane_acc_init(L);
-    lane_steps<kCodes>(P, cur, P.codes, stride, t, base, W, L);
+    lane_steps<kSrc>(P, cur, P.codes, stride, t, base, W, L);
     group_reduce(L.smin, L.smax, L.emin, L.emax, L.cmin, L.cmax, 6);
     double tmin = L.tmin, tmax = L.tmax;
 #pragma unroll
@@ -1227,7 +1293,7 @@ __device__ __forceinline__ void exact_long_row(const Problem& P, const SegDesc s
   exact_finish(X, lane == 0, mn, mx);
 }
 
-template <bool kBatchLoads = false>
+template <bool kBatchLoads = false, int kSrc = kSrcPairs>
 __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
                                            const double2* __restrict__ cur,
                                            double2* __restrict__ nxt, uint32_t stride, uint32_t t,
@@ -1275,7 +1341,7 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
       }
       double2 bv[kSegBatch];
 #pragma unroll
-      for (int w = 0; w < kSegBatch; ++w) bv[w] = cur[(size_t)(cv[w] & kColMask) * stride + t];
+      for (int w = 0; w < kSegBatch; ++w) bv[w] = pair_of<kSrc>(cur, P.b32, cv[w], stride, t);
 #pragma unroll
       for (int w = 0; w < kSegBatch; ++w)
         if (av[w] != 0.0 && entry_wanted(R, av[w], bv[w].x, bv[w].y, cv[w], P.cont_rel_tol))
@@ -1287,7 +1353,7 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
     const double a = P.vals[sd.off + p];
     if (a == 0.0) continue;
     const int32_t cw = P.cols[sd.off + p];
-    const double2 b = cur[(size_t)(cw & kColMask) * stride + t];
+    const double2 b = pair_of<kSrc>(cur, P.b32, cw, stride, t);
     if (entry_wanted(R, a, b.x, b.y, cw, P.cont_rel_tol))
       entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride, stride == 1);
   }
@@ -1304,11 +1370,24 @@ __device__ __forceinline__ uint32_t u32_load(const uint32_t* p) {
 // the start-of-round pair folded in).
 __device__ __forceinline__ bool commit_one(const Problem& P, uint32_t v, double2 a, double2 b,
                                            uint32_t& changed, uint32_t& infeasible) {
+  float2 s32;
+  if (P.store32) {
+    s32 = make_float2(store_down32(b.x), store_up32(b.y));
+    const double2 raw = b;
+    b = make_double2((double)s32.x, (double)s32.y);
+    if (a.x == b.x && a.y == b.y) {
+      // a gain smaller than a grid step: nothing changes, and the candidate
+      // target goes back to the start-of-round pair
+      if (raw.x != a.x || raw.y != a.y) P.bnd[1][v] = a;
+      return false;
+    }
+  }
   if (a.x == b.x && a.y == b.y) return false;
   const bool is_int = P.vtype[v] != 0;
   P.bnd[0][v] = b;
   P.bnd[1][v] = b;
   P.codes[v] = bound_code(is_int, b.x, b.y);
+  if (P.store32) P.b32[v] = s32;
   ++changed;
   if (tiny_bound(b.x) || tiny_bound(b.y))
     __hip_atomic_store(&P.ctrl->tiny, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -249,6 +249,8 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   P.bnd[0] = b0;
   P.bnd[1] = b1;
   P.codes = codes;
+  P.b32 = nullptr;  // allocated by the first prop_set_store(p, 32)
+  P.store32 = 0;
   P.stripes = stripes;
   P.n_hot = n_hot;
   P.ctrl = d_ctrl;
@@ -807,6 +809,7 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
   if (max_rounds < 0) return fail(PROP_EINVAL, "max_rounds < 0");
   if (p->n > 0 && (!d_lb || !d_ub)) return fail(PROP_EINVAL, "bound arrays are NULL");
   if (p->P.nnz_split) return fail(PROP_EINVAL, "the nnz-split layout runs single bound vectors only");
+  if (p->P.store32) return fail(PROP_EINVAL, "the single-precision store runs single bound vectors only");
   HIP_TRY(hipSetDevice(p->device));
   int rc = ensure_batch(p, nodes);
   if (rc) return rc;
@@ -945,6 +948,7 @@ int prop_run_batch(prop_problem* p, int32_t nodes, double* lb, double* ub, int32
   if (!p || !out) return fail(PROP_EINVAL, "NULL argument");
   if (nodes < 1) return fail(PROP_EINVAL, "nodes < 1");
   if (p->n > 0 && (!lb || !ub)) return fail(PROP_EINVAL, "bound arrays are NULL");
+  if (p->P.store32) return fail(PROP_EINVAL, "the single-precision store runs single bound vectors only");
   HIP_TRY(hipSetDevice(p->device));
   const size_t bytes = sizeof(double) * (size_t)p->n * (size_t)nodes;
   if (nodes > p->bstage_capacity && bytes) {
@@ -1040,6 +1044,29 @@ int prop_set_marking(prop_problem* p, int32_t enable) {
     if (rc) return rc;
   }
   p->marking = enable != 0;
+  return PROP_OK;
+}
+
+int prop_set_store(prop_problem* p, int32_t bits) {
+  if (!p) return fail(PROP_EINVAL, "NULL problem");
+  if (bits != PROP_STORE_F64 && bits != PROP_STORE_F32)
+    return fail(PROP_EINVAL, "bound store of %d bits: 64 or 32", bits);
+  const int32_t want = bits == PROP_STORE_F32 ? 1 : 0;
+  if (want && p->P.nnz_split)
+    return fail(PROP_EINVAL, "the single-precision store runs on the layout of length classes");
+  if (want == p->P.store32) return PROP_OK;
+  HIP_TRY(hipSetDevice(p->device));
+  if (want && !p->P.b32) {
+    float2* b32 = nullptr;
+    const int rc = dev_alloc(p, &b32, (size_t)(p->n > 0 ? p->n : 1));
+    if (rc) return rc;
+    p->P.b32 = b32;
+  }
+  // captured rounds hold the old store's kernels; a parent was rounded for
+  // the old store
+  drop_graphs(p);
+  p->P.parent = nullptr;
+  p->P.store32 = want;
   return PROP_OK;
 }
 

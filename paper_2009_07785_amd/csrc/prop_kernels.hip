@@ -54,6 +54,12 @@ __global__ __launch_bounds__(kBlock) void k_pack(Problem P, const double* __rest
     }
     l = l + 0.0;
     u = u + 0.0;
+    if (P.store32) {
+      const float2 s32 = make_float2(store_down32(l), store_up32(u));
+      P.b32[j] = s32;
+      l = (double)s32.x;
+      u = (double)s32.y;
+    }
     const double2 b = make_double2(l, u);
     P.bnd[0][j] = b;
     P.bnd[1][j] = b;
@@ -84,8 +90,12 @@ __global__ __launch_bounds__(kBlock) void k_unpack(Problem P, double* __restrict
 }
 
 // ---- persistent driver: every round inside one cooperative launch -------
-template <bool kNz>
+// kMode: 0 chunks, 1 nnz-split waves, 2 chunks with the single-precision
+// store's copies as the gather source.
+template <int kMode>
 __global__ __launch_bounds__(kBlock) void k_persistent(Problem P, int max_rounds) {
+  constexpr bool kNz = kMode == 1;
+  constexpr int kSrc = kMode == 2 ? kSrcCodes32 : kSrcCodes;
   Ctrl* C = P.ctrl;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gwave = blockIdx.x * kWavesPerBlock + wave;
@@ -102,14 +112,14 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Problem P, int max_rounds
     const uint32_t exact = u32_load(&C->tiny) ? 1u : 0u;
     for (int c = gwave; c < P.n_chunks; c += nwaves) {
       if (kNz) nz_wave_round(P, c, A, B, exact != 0);
-      else chunk_dispatch<true>(P, c, A, B, 1, 1, exact);
+      else chunk_dispatch<kSrc>(P, c, A, B, 1, 1, exact);
     }
     if (P.n_segs) {
       for (int s = gwave; s < P.n_segs; s += nwaves)
-        seg_phase1<true>(P, s, A, 1, 1, P.partials, 1, 0);
+        seg_phase1<kSrc>(P, s, A, 1, 1, P.partials, 1, 0);
       if (!grid_barrier(P, kActNone, r, max_rounds)) return;
       for (int s = gwave; s < P.n_segs; s += nwaves)
-        seg_phase2(P, s, A, B, 1, 0, P.partials, 1, 0, exact != 0);
+        seg_phase2<false, kSrc>(P, s, A, B, 1, 0, P.partials, 1, 0, exact != 0);
     }
     if (!grid_barrier(P, kActNone, r, max_rounds)) return;
     uint32_t changed = 0, infeasible = 0;
@@ -144,7 +154,9 @@ __device__ __forceinline__ bool marked_round(const Problem& P) {
 // Six waves per SIMD (at most 84 VGPRs; the kernel fits in 78 without
 // spills): the round is bound by the gathers of the activity pass, and
 // resident waves hide their latency.  Eight waves (64 VGPRs) spill and run
-// twice as long.
+// twice as long.  kSrc: kSrcCodes, or kSrcCodes32 with the single-precision
+// store.
+template <int kSrc>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_round(
     Problem P) {
   if (u32_load(&P.ctrl->done)) return;
@@ -153,9 +165,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
   const int item = blockIdx.x * kWavesPerBlock + wave;
   const bool marked = marked_round(P);
   if (item < P.n_segs)
-    seg_phase1<true>(P, item, P.bnd[0], 1, 1, P.partials, 1, 0, marked, r, P.row_mark);
+    seg_phase1<kSrc>(P, item, P.bnd[0], 1, 1, P.partials, 1, 0, marked, r, P.row_mark);
   else if (item - P.n_segs < P.n_chunks)
-    chunk_dispatch<true>(P, item - P.n_segs, P.bnd[0], P.bnd[1], 1, 1,
+    chunk_dispatch<kSrc>(P, item - P.n_segs, P.bnd[0], P.bnd[1], 1, 1,
                          u32_load(&P.ctrl->tiny) ? 1u : 0u, marked, r, P.row_mark);
 }
 
@@ -168,18 +180,20 @@ __global__ __launch_bounds__(kBlock) void k_round_nz(Problem P) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = blockIdx.x * kWavesPerBlock + wave;
   if (item < P.n_segs)
-    seg_phase1<true>(P, item, P.bnd[0], 1, 1, P.partials, 1, 0, marked_round(P), r, P.row_mark);
+    seg_phase1<kSrcCodes>(P, item, P.bnd[0], 1, 1, P.partials, 1, 0, marked_round(P), r,
+                          P.row_mark);
   else if (item - P.n_segs < P.n_chunks)
     nz_wave_round(P, item - P.n_segs, P.bnd[0], P.bnd[1], u32_load(&P.ctrl->tiny) != 0);
 }
 
+template <int kSrc>
 __global__ __launch_bounds__(kBlock) void k_round_long(Problem P) {
   if (u32_load(&P.ctrl->done)) return;
   const int r = round_of(P);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int s = blockIdx.x * kWavesPerBlock + wave;
   if (s < P.n_segs)
-    seg_phase2<true>(P, s, P.bnd[0], P.bnd[1], 1, 0, P.partials, 1, 0,
+    seg_phase2<true, kSrc>(P, s, P.bnd[0], P.bnd[1], 1, 0, P.partials, 1, 0,
                      u32_load(&P.ctrl->tiny) != 0, marked_round(P), r, P.row_mark);
 }
 
@@ -245,7 +259,13 @@ __global__ __launch_bounds__(kBlock) void k_set_parent(Problem P, double2* __res
       l = __builtin_ceil(l - P.eps_int);
       u = __builtin_floor(u + P.eps_int);
     }
-    parent[j] = make_double2(l + 0.0, u + 0.0);
+    l = l + 0.0;
+    u = u + 0.0;
+    if (P.store32) {
+      l = (double)store_down32(l);
+      u = (double)store_up32(u);
+    }
+    parent[j] = make_double2(l, u);
   }
 }
 
@@ -306,17 +326,25 @@ hipError_t launch_unpack(const Problem& P, double* lb, double* ub, hipStream_t s
   return hipGetLastError();
 }
 
+// Blocks per CU of the persistent kernel; for the chunk layout the smaller
+// figure of its two store variants, so one grid fits either.
 hipError_t persistent_occupancy(int* blocks_per_cu, bool nnz_split) {
-  return nnz_split ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
-                                                                  k_persistent<true>, kBlock, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
-                                                                  k_persistent<false>, kBlock, 0);
+  if (nnz_split)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<1>, kBlock, 0);
+  int a = 0, b = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_persistent<0>, kBlock, 0);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_persistent<2>, kBlock, 0);
+  *blocks_per_cu = a < b ? a : b;
+  return e;
 }
 
 hipError_t launch_persistent(const Problem& P, int max_rounds, int grid, hipStream_t s) {
   Problem p = P;
   void* args[] = {(void*)&p, (void*)&max_rounds};
-  const void* fn = P.nnz_split ? (const void*)k_persistent<true> : (const void*)k_persistent<false>;
+  const void* fn = P.nnz_split ? (const void*)k_persistent<1>
+                   : P.store32 ? (const void*)k_persistent<2>
+                               : (const void*)k_persistent<0>;
   return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlock), args, 0, s);
 }
 
@@ -345,12 +373,18 @@ hipError_t launch_round(const Problem& P, hipStream_t s, hipEvent_t e0, hipEvent
   if (P.nnz_split)
     hipLaunchKernelGGL(k_round_nz, dim3(blocks_for(items, kWavesPerBlock, 1 << 30)), dim3(kBlock),
                        0, s, P);
+  else if (P.store32)
+    hipLaunchKernelGGL(k_round<kSrcCodes32>, dim3(blocks_for(items, kWavesPerBlock, 1 << 30)),
+                       dim3(kBlock), 0, s, P);
   else
-    hipLaunchKernelGGL(k_round, dim3(blocks_for(items, kWavesPerBlock, 1 << 30)), dim3(kBlock), 0,
-                       s, P);
+    hipLaunchKernelGGL(k_round<kSrcCodes>, dim3(blocks_for(items, kWavesPerBlock, 1 << 30)),
+                       dim3(kBlock), 0, s, P);
   if (e1) hipEventRecord(e1, s);
-  if (P.n_segs)
-    hipLaunchKernelGGL(k_round_long, dim3(blocks_for(P.n_segs, kWavesPerBlock, 1 << 30)),
+  if (P.n_segs && P.store32)
+    hipLaunchKernelGGL(k_round_long<kSrcCodes32>, dim3(blocks_for(P.n_segs, kWavesPerBlock, 1 << 30)),
+                       dim3(kBlock), 0, s, P);
+  else if (P.n_segs)
+    hipLaunchKernelGGL(k_round_long<kSrcCodes>, dim3(blocks_for(P.n_segs, kWavesPerBlock, 1 << 30)),
                        dim3(kBlock), 0, s, P);
   // at most 65535 blocks: the packed commit counter keeps 16 bits per field
   hipLaunchKernelGGL(k_commit, dim3(blocks_for((int64_t)P.n / 4 + 2 * (int64_t)P.n_hot, kBlock,

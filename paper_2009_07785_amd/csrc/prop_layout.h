@@ -60,6 +60,11 @@ struct Problem {
   // state: bnd[0] = start-of-round bounds, bnd[1] = candidate target
   double2* bnd[2];
   uint16_t* codes;          // [n] compact code of bnd[0] per variable (prop_device.h)
+  // single-precision store (store32 != 0): every bound is kept on the grid
+  // of zero, the infinities and the normal singles, rounded outward, and
+  // b32 holds bnd[0] as singles (the same values) for the gathers
+  float2* b32;              // [n]
+  int32_t store32;
   double2* stripes;         // [kStripes][n_hot] candidate targets of hot variables
   int32_t n_hot;
   int32_t pad_hot;

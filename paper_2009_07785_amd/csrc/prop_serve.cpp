@@ -543,6 +543,7 @@ static int srv_device_init(prop_server* s) {
 int prop_srv_add_instance(prop_server* s, prop_problem* p, int32_t* id) {
   if (!s || !p || !id) return fail(PROP_EINVAL, "NULL argument");
   if (p->P.nnz_split) return fail(PROP_EINVAL, "the nnz-split layout runs single bound vectors only");
+  if (p->P.store32) return fail(PROP_EINVAL, "the single-precision store runs single bound vectors only");
   HIP_TRY(hipSetDevice(p->device));
   {
     std::lock_guard<std::mutex> lk(s->mu);

@@ -109,6 +109,7 @@ extern "C" int prop_run_batch_device_static(prop_problem* p, int32_t nodes, doub
   if (max_rounds < 0) return fail(PROP_EINVAL, "max_rounds < 0");
   if (p->n > 0 && (!d_lb || !d_ub)) return fail(PROP_EINVAL, "bound arrays are NULL");
   if (p->P.nnz_split) return fail(PROP_EINVAL, "the nnz-split layout runs single bound vectors only");
+  if (p->P.store32) return fail(PROP_EINVAL, "the single-precision store runs single bound vectors only");
   const StaticLayout L = static_layout(p->n, p->P.n_segs, nodes);
   if (L.total > kScratchBytes)
     return fail(PROP_EINVAL,

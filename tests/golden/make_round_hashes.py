@@ -11,6 +11,12 @@ resume property its pins check).
 
     python tests/golden/make_round_hashes.py config2   # ~6 s per round
     python tests/golden/make_round_hashes.py config3
+
+With ``config2_store32`` it writes the same round-by-round trace of the
+5,000,000 x 2,000,000 instance under the oracle's single-precision bound
+store: each round is the oracle's run of one round from the bounds the
+previous one left (those are integer-rounded and on the store's grid
+already, so the run's entry normalisation leaves them unchanged).
 """
 from __future__ import annotations
 
@@ -63,12 +69,43 @@ def round_trace(inst, lb, ub, max_rounds=100, log=print):
     return {"status": status, "rounds": rounds, "sha": shas}
 
 
+def store32_trace(inst, lb, ub, max_rounds=100, log=print):
+    """round_trace under the single-precision bound store."""
+    start = oracle.run(inst, lb, ub, 0, store=32)
+    if start.status == oracle.INFEASIBLE:
+        return {"status": start.status, "rounds": 0, "sha": [bounds_sha(start.lb, start.ub)]}
+    L, U = start.lb, start.ub
+    shas = [bounds_sha(L, U)]
+    status, rounds = oracle.MAX_ROUNDS, max_rounds
+    for r in range(1, max_rounds + 1):
+        t0 = time.perf_counter()
+        one = oracle.run(inst, L, U, 1, store=32)
+        changed = not (np.array_equal(one.lb, L) and np.array_equal(one.ub, U))
+        L, U = one.lb, one.ub
+        shas.append(bounds_sha(L, U))
+        log(f"  round {r}: status={one.status} ({time.perf_counter() - t0:.1f} s)")
+        if one.status == oracle.INFEASIBLE:
+            status, rounds = oracle.INFEASIBLE, r
+            break
+        if one.status == oracle.CONVERGED:
+            assert not changed
+            status, rounds = oracle.CONVERGED, r
+            break
+    return {"status": status, "rounds": rounds, "sha": shas}
+
+
 def main(which: str):
     if which == "config2":
         inst = synth.config2()
         out = {"workload": f"{inst.name}: {inst.m} x {inst.n}, {inst.nnz} nnz, root bounds",
                "max_rounds": 100, **round_trace(inst, inst.lb, inst.ub)}
         path = os.path.join(HERE, "config2_rounds.json")
+    elif which == "config2_store32":
+        inst = synth.config2()
+        out = {"workload": f"{inst.name}: {inst.m} x {inst.n}, {inst.nnz} nnz, root bounds, "
+                           "single-precision bound store",
+               "max_rounds": 100, "store": 32, **store32_trace(inst, inst.lb, inst.ub)}
+        path = os.path.join(HERE, "config2_store32.json")
     elif which == "config3":
         inst = synth.config3_matrix()
         lbs, ubs = synth.config3_nodes(inst, 256)

@@ -394,7 +394,7 @@ def check_validation(orc):
 
 
 # ---------------------------------------------------------------------------
-# single-precision bound store, rounded outward (reading R10)
+# single-precision bound store, rounded outward (reading R12)
 # ---------------------------------------------------------------------------
 F32_MIN = float(np.finfo(np.float32).tiny)  # smallest normal single
 F32_MAX = float(np.finfo(np.float32).max)
@@ -460,6 +460,7 @@ def check_store_grid(orc):
         if _in_store_grid(x):
             assert d == x == u, (x, d, u)
         assert not (d == 0.0 and math.copysign(1.0, d) < 0), x
+        assert not (u == 0.0 and math.copysign(1.0, u) < 0), x
 
 
 def check_store_integer_identity(orc, count=40):

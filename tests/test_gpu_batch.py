@@ -7,6 +7,7 @@ import os
 
 import numpy as np
 import pytest
+from bitwise import same_bits
 
 import oracle
 import synth
@@ -53,7 +54,7 @@ def check_batch_vs_single(torch, lib, inst, lbs, ubs, max_rounds=100, with_oracl
         for _ in range(2):
             gres, glb, gub = run_batch(torch, p, lbs, ubs, max_rounds)
             assert [(r.status, r.rounds) for r in gres] == [(r.status, r.rounds) for r in res]
-            assert np.array_equal(glb, blb) and np.array_equal(gub, bub)
+            assert same_bits(glb, blb) and same_bits(gub, bub)
         p.set_loop("stream")
         statuses = set()
         for k in range(lbs.shape[0]):
@@ -61,12 +62,12 @@ def check_batch_vs_single(torch, lib, inst, lbs, ubs, max_rounds=100, with_oracl
             assert (res[k].status, res[k].rounds) == (r1.status, r1.rounds), (inst.name, k)
             statuses.add(r1.status)
             if r1.status != oracle.INFEASIBLE:
-                assert np.array_equal(blb[k], lb1) and np.array_equal(bub[k], ub1), (inst.name, k)
+                assert same_bits(blb[k], lb1) and same_bits(bub[k], ub1), (inst.name, k)
             if with_oracle:
                 ref = oracle.run(inst, lbs[k], ubs[k], max_rounds)
                 assert (ref.status, ref.rounds) == (r1.status, r1.rounds), (inst.name, k)
                 if ref.status != oracle.INFEASIBLE:
-                    assert np.array_equal(ref.lb, lb1) and np.array_equal(ref.ub, ub1)
+                    assert same_bits(ref.lb, lb1) and same_bits(ref.ub, ub1)
     return statuses
 
 
@@ -112,7 +113,7 @@ def test_batch_reuse_and_invalid(torch_cuda, lib):
         b, blb, bub = run_batch(torch, p, lbs[:5], ubs[:5])  # smaller batch, same workspace
         for k in range(5):
             assert (a[k].status, a[k].rounds) == (b[k].status, b[k].rounds)
-            assert np.array_equal(alb[k], blb[k]) and np.array_equal(aub[k], bub[k])
+            assert same_bits(alb[k], blb[k]) and same_bits(aub[k], bub[k])
         bad = lbs.copy()
         bad[3, 7] = np.nan
         with pytest.raises(lib.PropError) as e:
@@ -152,7 +153,7 @@ def test_batch_compaction(torch_cuda, lib):
             r1, lb1, ub1 = p.run(lbs[k], ubs[k], 100)
             assert (res[k].status, res[k].rounds) == (r1.status, r1.rounds)
             if r1.status != oracle.INFEASIBLE:
-                assert np.array_equal(blb[k], lb1) and np.array_equal(bub[k], ub1)
+                assert same_bits(blb[k], lb1) and same_bits(bub[k], ub1)
 
 
 def test_batch_host_arrays(torch_cuda, lib):
@@ -169,7 +170,7 @@ def test_batch_host_arrays(torch_cuda, lib):
                 [(r.status, r.rounds) for r in dev[:count]]
             for k in range(count):
                 if res[k].status != oracle.INFEASIBLE:
-                    assert np.array_equal(hlb[k], dlb[k]) and np.array_equal(hub[k], dub[k]), k
+                    assert same_bits(hlb[k], dlb[k]) and same_bits(hub[k], dub[k]), k
         with pytest.raises(ValueError):
             p.run_batch(lbs[:, :-1], ubs[:, :-1])
 
@@ -212,7 +213,7 @@ def test_batch_config3_256_nodes(torch_cuda, lib, config3):
             assert (res[k].status, res[k].rounds) == (r1.status, r1.rounds), k
             statuses.add(r1.status)
             if r1.status != oracle.INFEASIBLE:
-                assert np.array_equal(blb[k], lb1) and np.array_equal(bub[k], ub1), k
+                assert same_bits(blb[k], lb1) and same_bits(bub[k], ub1), k
         assert {oracle.CONVERGED, oracle.INFEASIBLE} <= statuses
         for key, g in gold.items():
             k = int(key)

@@ -5,6 +5,7 @@ bitwise the unmarked runs, which are bitwise the oracle's, whatever the
 round-loop driver; batches compact as children finish."""
 import numpy as np
 import pytest
+from bitwise import same_bits
 
 import oracle
 import synth
@@ -36,7 +37,7 @@ def same(tag, res, lb, ub, ref):
     assert (res.status, res.rounds) == (ref.status, ref.rounds), (
         f"{tag}: {res.status}/{res.rounds} vs oracle {ref.status}/{ref.rounds}")
     if ref.status != oracle.INFEASIBLE:
-        assert np.array_equal(lb, ref.lb) and np.array_equal(ub, ref.ub), tag
+        assert same_bits(lb, ref.lb) and same_bits(ub, ref.ub), tag
 
 
 CASES = [("config0", lambda: synth.config0(), 8, 1),
@@ -80,7 +81,7 @@ def test_children_single_runs(lib, torch_cuda, name, make, count, per_child):
         p.set_loop("stream")
         res, lb, ub = p.run(parent.lb, parent.ub, 100)
         assert (res.status, res.rounds) == (oracle.CONVERGED, 1)
-        assert np.array_equal(lb, parent.lb) and np.array_equal(ub, parent.ub)
+        assert same_bits(lb, parent.lb) and same_bits(ub, parent.ub)
         # persistent driver: parent and marking ignored, same results
         p.set_loop("persistent")
         res, lb, ub = p.run(lbs[0], ubs[0], 100)

@@ -15,6 +15,7 @@ import sys
 
 import numpy as np
 import pytest
+from bitwise import differing, same_bits
 
 import oracle
 import oracle_pins as pins
@@ -54,9 +55,8 @@ def assert_same(tag, got, ref):
     if ref.status == oracle.INFEASIBLE:
         return
     for name, g, r in (("lb", lb, ref.lb), ("ub", ub, ref.ub)):
-        same = (g == r) | (np.isnan(g) & np.isnan(r))
-        if not same.all():
-            bad = np.nonzero(~same)[0]
+        bad = differing(g, r)
+        if bad.size:
             fin = np.isfinite(g[bad]) & np.isfinite(r[bad])
             dev = np.max(np.abs(g[bad][fin] - r[bad][fin])) if fin.any() else math.inf
             raise AssertionError(f"{tag}: {name} differs at {bad.size} vars (first {bad[:5]}, "
@@ -187,10 +187,10 @@ def test_resume_and_idempotence(lib):
     r1, lb1, ub1 = gpu_run(lib, inst, inst.lb, inst.ub, k)
     r2, lb2, ub2 = gpu_run(lib, inst, lb1, ub1, 100)
     assert r1.status == oracle.MAX_ROUNDS and r1.rounds + r2.rounds == res.rounds
-    assert np.array_equal(lb2, lb) and np.array_equal(ub2, ub)
+    assert same_bits(lb2, lb) and same_bits(ub2, ub)
     r3, lb3, ub3 = gpu_run(lib, inst, lb, ub, 100)
     assert (r3.status, r3.rounds) == (oracle.CONVERGED, 1)
-    assert np.array_equal(lb3, lb) and np.array_equal(ub3, ub)
+    assert same_bits(lb3, lb) and same_bits(ub3, ub)
 
 
 def test_config1_suite(lib):
@@ -215,7 +215,7 @@ def test_determinism_device_path(lib, torch_cuda):
             outs.append((res.status, res.rounds, d_lb.cpu().numpy(), d_ub.cpu().numpy()))
     for o in outs[1:]:
         assert o[:2] == outs[0][:2]
-        assert np.array_equal(o[2], outs[0][2]) and np.array_equal(o[3], outs[0][3])
+        assert same_bits(o[2], outs[0][2]) and same_bits(o[3], outs[0][3])
 
 
 def test_edge_cases(lib):
@@ -376,6 +376,32 @@ def test_config2_marked_full_run(lib, big):
     assert bounds_sha(lb1, ub1) == g["sha"][g["rounds"]]
 
 
+def test_config2_store32(lib, big):
+    """The single-precision bound store on the full instance: every round's
+    bounds equal to the oracle's under the same store, and the full run on
+    every driver."""
+    inst, p = big
+    g = load_golden("config2_store32.json")
+    R = g["rounds"]
+    p.set_store(32)
+    try:
+        p.set_loop("stream")
+        for r in range(1, R + 1):
+            res, lb, ub = p.run(inst.lb, inst.ub, r)
+            want = (g["status"], R) if r == R else (oracle.MAX_ROUNDS, r)
+            assert (res.status, res.rounds) == want, f"store32 round {r}"
+            assert bounds_sha(lb, ub) == g["sha"][r], f"store32: bounds differ after round {r}"
+        for loop in LOOPS:
+            p.set_loop(loop)
+            res, lb, ub = p.run(inst.lb, inst.ub, 100)
+            assert (res.status, res.rounds) == (g["status"], R), loop
+            assert bounds_sha(lb, ub) == g["sha"][R], f"store32/{loop}: bounds differ"
+    finally:
+        p.set_store(64)
+        p.set_loop("stream")
+    say(f"config2 store32: {R} rounds, every one equal to the oracle's")
+
+
 def test_config2_nnz_split(lib, big):
     """The nnz-split layout on the full instance: every 4th round and the
     final state equal to the oracle's stored hashes."""
@@ -444,5 +470,5 @@ def test_empty_and_degenerate_shapes(lib, torch_cuda):
                 for k in range(3):
                     assert (res[k].status, res[k].rounds) == (ref.status, ref.rounds)
                     if ref.status != oracle.INFEASIBLE:
-                        assert np.array_equal(d_lb[k].cpu().numpy(), ref.lb)
-                        assert np.array_equal(d_ub[k].cpu().numpy(), ref.ub)
+                        assert same_bits(d_lb[k].cpu().numpy(), ref.lb)
+                        assert same_bits(d_ub[k].cpu().numpy(), ref.ub)

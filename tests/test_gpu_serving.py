@@ -7,6 +7,7 @@ import time
 
 import numpy as np
 import pytest
+from bitwise import same_bits
 
 import oracle
 import synth
@@ -67,7 +68,7 @@ def check_alone(probs, reqs, results):
         assert (res.status, res.rounds) == (r1.status, r1.rounds), (k, mr)
         statuses.add(r1.status)
         if r1.status != oracle.INFEASIBLE:
-            assert np.array_equal(glb, lb1) and np.array_equal(gub, ub1), (k, mr)
+            assert same_bits(glb, lb1) and same_bits(gub, ub1), (k, mr)
     return statuses
 
 
@@ -143,7 +144,7 @@ def test_serving_against_oracle(lib, pool):
             ref = oracle.run(insts[k], lb, ub, mr)
             assert (res.status, res.rounds) == (ref.status, ref.rounds)
             if ref.status != oracle.INFEASIBLE:
-                assert np.array_equal(glb, ref.lb) and np.array_equal(gub, ref.ub)
+                assert same_bits(glb, ref.lb) and same_bits(gub, ref.ub)
 
 
 def test_serving_errors_and_budget(lib, pool):
@@ -178,7 +179,7 @@ def test_serving_errors_and_budget(lib, pool):
         assert e.value.code == lib.EBUSY
         a = srv.wait(t1, inst.n, timeout_ms=60_000)
         b = srv.wait(t2, inst.n, timeout_ms=60_000)
-        assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+        assert a[0] == b[0] and same_bits(a[1], b[1]) and same_bits(a[2], b[2])
         with pytest.raises(lib.PropError):
             srv.poll(t1, inst.n)  # released
         t3 = srv.submit(i, inst.lb, inst.ub, 100)  # room again
@@ -205,4 +206,4 @@ def test_serving_completion_list_overflow(lib, pool):
     ref = probs[k].run(inst.lb, inst.ub, 1)
     for r in res[700:]:
         assert (r[0].status, r[0].rounds) == (ref[0].status, ref[0].rounds)
-        assert np.array_equal(r[1], ref[1]) and np.array_equal(r[2], ref[2])
+        assert same_bits(r[1], ref[1]) and same_bits(r[2], ref[2])

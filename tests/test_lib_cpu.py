@@ -97,6 +97,7 @@ def test_null_problem_calls():
     assert b.lib.prop_run(None, None, None, 10, ctypes.byref(res)) == b.EINVAL
     assert b.lib.prop_run_batch(None, 1, None, None, 10, ctypes.byref(res)) == b.EINVAL
     assert b.lib.prop_set_loop(None, 0) == b.EINVAL
+    assert b.lib.prop_set_store(None, 32) == b.EINVAL
     b.lib.prop_destroy(None)
 
 

@@ -4,6 +4,7 @@ bitwise equal on two calls in a row (the second with a smaller input, so
 the fixed workspace holds a larger call's leftovers), and the size limit."""
 import numpy as np
 import pytest
+from bitwise import same_bits
 
 import synth
 
@@ -48,7 +49,7 @@ def _compare(lib, torch, prob, lbs, ubs, tag):
     assert [(r.status, r.rounds) for r in r0] == [(r.status, r.rounds) for r in r1], tag
     for k, r in enumerate(r0):
         if r.status != lib.INFEASIBLE:
-            assert np.array_equal(l0[k], l1[k]) and np.array_equal(u0[k], u1[k]), (tag, k)
+            assert same_bits(l0[k], l1[k]) and same_bits(u0[k], u1[k]), (tag, k)
     print(f"{tag}: {len(r0)} nodes, statuses "
           f"{sorted({lib.STATUS_NAMES[r.status] for r in r0})}, rounds up to "
           f"{max(r.rounds for r in r0)}", flush=True)
