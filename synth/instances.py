@@ -13,7 +13,8 @@ Workloads (sizes and distributions):
            20% continuous [-1e3, 1e3] (5% of those with one infinite bound).
   config1  200,000 x 100,000; row lengths max(1, rint(LogNormal(ln 6, 1)))
            plus 0.1% dense rows of 5,000; coefficients 70% +-1, 30%
-           U[-100, 100]; a suite of seeds, every 50th made infeasible.
+           U[-100, 100]; a suite of seeds, every 50th made infeasible (one
+           row's rhs set 1-10 below its minimum over the root box).
   config2  5,000,000 x 2,000,000; row lengths floor(Pareto) with pdf exponent
            2.2, minimum 2, capped at 200,000; column weights from the same
            law and each row's distinct columns drawn in proportion to them;
@@ -198,19 +199,21 @@ def _sides(rng, s, frac_one_sided=0.1):
 
 
 def _make_infeasible(rng, inst: Instance):
-    """Set one row's rhs below anything its variables' bounds can reach: the
-    row is chosen among rows whose variables all have finite bounds, and rhs
-    goes below -sum |a_j| * max(|l_j|, |u_j|)."""
+    """Set one row's rhs below its minimum over the root box: the row is
+    chosen among rows whose minimising bounds (l_j for a_j > 0, u_j for
+    a_j < 0) are all finite, rhs becomes that minimum minus U[1, 10] and
+    lhs becomes -inf.  The margin of at least 1 is far above the rounding
+    of the float sum taken here, so the row excludes the whole box."""
     lengths = inst.row_lengths()
-    finite_var = np.isfinite(inst.lb) & np.isfinite(inst.ub)
-    ok_nnz = finite_var[inst.col_idx].astype(np.int64)
+    a = inst.vals
+    bmin = np.where(a > 0, inst.lb[inst.col_idx], inst.ub[inst.col_idx])
+    ok_nnz = np.isfinite(bmin).astype(np.int64)
     ok_rows = np.add.reduceat(ok_nnz, inst.row_ptr[:-1]) == lengths
     cand = np.nonzero(ok_rows & (lengths > 0))[0]
     i = int(rng.choice(cand))
     sl = slice(inst.row_ptr[i], inst.row_ptr[i + 1])
-    j = inst.col_idx[sl]
-    reach = np.sum(np.abs(inst.vals[sl]) * np.maximum(np.abs(inst.lb[j]), np.abs(inst.ub[j])))
-    inst.rhs[i] = -reach - rng.uniform(1.0, 10.0)
+    low = float(np.sum(a[sl] * bmin[sl]))
+    inst.rhs[i] = low - rng.uniform(1.0, 10.0)
     inst.lhs[i] = -INF
     inst.meta["infeasible_row"] = i
     return inst
