@@ -180,6 +180,9 @@ def main():
                     help="skip the 2,000 x 1,000 and 200,000 x 100,000 single-instance lines")
     ap.add_argument("--no-layouts", action="store_true",
                     help="skip the nnz-split layout comparison")
+    ap.add_argument("--store", type=int, default=64, choices=[64, 32],
+                    help="bound store of the timed runs: 64 (doubles) or 32 (single "
+                         "precision, rounded outward; FP64 arithmetic either way)")
     ap.add_argument("--no-store32", action="store_true",
                     help="skip the single-precision bound store comparison")
     ap.add_argument("--no-children", action="store_true",
@@ -252,6 +255,7 @@ def main():
     log(f"device problem ready in {time.perf_counter() - t0:.1f} s: {info}")
     prob.set_loop(args.loop)
     prob.set_kernel_timing(args.loop != "persistent")
+    prob.set_store(args.store)
 
     root_lb = torch.tensor(inst.lb, dtype=torch.float64, device=dev)
     root_ub = torch.tensor(inst.ub, dtype=torch.float64, device=dev)
@@ -311,7 +315,8 @@ def main():
     if os.path.exists(args.traffic):
         with open(args.traffic) as f:
             tr = json.load(f)
-        if tr.get("kernel_source_sha") == kernel_source_sha():
+        if (tr.get("kernel_source_sha") == kernel_source_sha()
+                and tr.get("bound_store", 64) == args.store):
             traffic = tr.get("bytes_per_launch")
 
     loops = {}
@@ -353,6 +358,7 @@ def main():
     small = None if args.no_small else small_configs(args.max_rounds)
     layouts = None if args.no_layouts else layout_compare(args.max_rounds, inst)
     store32 = None if args.no_store32 else store_compare(prob, inst, args.max_rounds)
+    prob.set_store(args.store)
     prob.set_loop(args.loop)
     prob.set_kernel_timing(args.loop != "persistent")
 
@@ -390,6 +396,7 @@ def main():
                         "(pdf exponent 2.2, cap 200,000) and column degrees",
             "m": inst.m, "n": inst.n, "nnz": nnz, "max_rounds": args.max_rounds,
             "loop": args.loop, "parallelism": "single GPU", "layout_steps": info["steps"],
+            "bound_store": args.store,
         },
         "status": ["CONVERGED", "INFEASIBLE", "MAX_ROUNDS"][status],
         "rounds": nrounds,
