@@ -1581,44 +1581,58 @@ enum BarrierAction { kActNone = 0, kActStart = 1, kActEndRound = 2 };
 // sees more than ceil(blocks / G) returning atomics per barrier.  `add` is
 // the block's packed commit total (changed pairs, infeasible flag), summed
 // along: the end-of-round action reads the round's totals from the count.
+//
+// Ordering uses fences around relaxed atomics, one release and one acquire
+// per block: on this chip an agent-scope release writes back the XCD's L2
+// and an acquire invalidates it, so acquire loads in the polling loop would
+// empty the L2 of every XCD over and over while other blocks still work.
+// A block's writes before its release fence reach the last block of its
+// group (acquire fence after the group's count is complete), whose release
+// fence passes them on through the control word to the last block overall,
+// whose release fence before the generation store passes everything to the
+// waiters' acquire fence after they see the new generation.
 __device__ __forceinline__ bool grid_barrier(const Problem& P, int action, int r, int max_rounds,
                                              uint64_t add = 0) {
   Ctrl* C = P.ctrl;
   __syncthreads();
   __shared__ uint32_t ok_shared;
   if (threadIdx.x == 0) {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     uint32_t ok = 1;
-    const uint32_t g = __hip_atomic_load(&C->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    // the generation cannot advance before this block has arrived
+    const uint32_t g = __hip_atomic_load(&C->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t ngroups = gridDim.x < (uint32_t)kCommitGroups ? gridDim.x : kCommitGroups;
     const uint32_t grp = blockIdx.x % ngroups;
     const uint32_t in_grp = (gridDim.x - 1u - grp) / ngroups + 1u;
     uint64_t* gw = P.commit_grp + (size_t)grp * kGroupWordStride;
     const uint64_t mine = kCommitBlock | add;
-    const uint64_t gold = __hip_atomic_fetch_add(gw, mine, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t gold = __hip_atomic_fetch_add(gw, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     bool last = false;
     uint64_t tot = 0;
     if ((gold >> 48) == in_grp - 1u) {
       // the group is complete: reset its word (its blocks touch it again
       // only after this barrier's release) and report the group's total
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
       const uint64_t gtot = gold + mine;
       __hip_atomic_store(gw, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const uint64_t old =
-          __hip_atomic_fetch_add(&C->commit_word, gtot, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(&C->commit_word, gtot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       tot = old + gtot;
       last = (tot >> 48) == gridDim.x;
     }
     if (last) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       if (action == kActStart) {
         start_status(P, max_rounds);
       } else if (action == kActEndRound) {
         end_of_round(P, r, max_rounds, (uint32_t)tot, (uint32_t)((tot >> 32) & 0xffff));
       }
       __hip_atomic_store(&C->commit_word, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&C->bar_gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&C->bar_gen, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       uint32_t spins = 0;
-      while (__hip_atomic_load(&C->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+      while (__hip_atomic_load(&C->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
         __builtin_amdgcn_s_sleep(2);
         if (++spins > PROP_SPIN_LIMIT ||
             __hip_atomic_load(&C->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
@@ -1627,8 +1641,8 @@ __device__ __forceinline__ bool grid_barrier(const Problem& P, int action, int r
           break;
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __threadfence();
     ok_shared = ok;
   }
   __syncthreads();
