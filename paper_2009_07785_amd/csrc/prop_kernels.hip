@@ -108,18 +108,21 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Problem P, int max_rounds
   if (!grid_barrier(P, kActStart, 0, max_rounds)) return;
   if (u32_load(&C->done)) return;
 
+  const int items = P.n_segs + P.n_chunks;
   for (int r = 1; r <= max_rounds; ++r) {
     const uint32_t exact = u32_load(&C->tiny) ? 1u : 0u;
-    for (int c = gwave; c < P.n_chunks; c += nwaves) {
-      if (kNz) nz_wave_round(P, c, A, B, exact != 0);
-      else chunk_dispatch<kSrc>(P, c, A, B, 1, 1, exact);
+    // long rows' first phase and the chunks in one pass, segments first (as
+    // the per-round kernel numbers its waves), so that no wave is left with
+    // segments after the others have run out of chunks
+    for (int it = gwave; it < items; it += nwaves) {
+      if (it < P.n_segs) seg_phase1<kSrc>(P, it, A, 1, 1, P.partials, 1, 0);
+      else if (kNz) nz_wave_round(P, it - P.n_segs, A, B, exact != 0);
+      else chunk_dispatch<kSrc>(P, it - P.n_segs, A, B, 1, 1, exact);
     }
     if (P.n_segs) {
-      for (int s = gwave; s < P.n_segs; s += nwaves)
-        seg_phase1<kSrc>(P, s, A, 1, 1, P.partials, 1, 0);
       if (!grid_barrier(P, kActNone, r, max_rounds)) return;
       for (int s = gwave; s < P.n_segs; s += nwaves)
-        seg_phase2<false, kSrc>(P, s, A, B, 1, 0, P.partials, 1, 0, exact != 0);
+        seg_phase2<true, kSrc>(P, s, A, B, 1, 0, P.partials, 1, 0, exact != 0);
     }
     if (!grid_barrier(P, kActNone, r, max_rounds)) return;
     uint32_t changed = 0, infeasible = 0;
