@@ -640,6 +640,27 @@ def batched_nodes(count: int, max_rounds: int):
     feas = torch.tensor([r.status != 1 for r in seq], device=dev)
     same_bounds = bool(torch.all(torch.where(feas[:, None], (b_lb == out_lb) & (b_ub == out_ub),
                                              True)).item())
+    # the same with marked rounds (rows whose variables did not change in
+    # the previous round are skipped; per group of 8 nodes in the batch)
+    prob.set_marking(True)
+    one_at_a_time()
+    batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_m = one_at_a_time()
+    torch.cuda.synchronize()
+    t_seq_m = time.perf_counter() - t0
+    same_m = all((a.status, a.rounds) == (b.status, b.rounds) for a, b in zip(seq, seq_m))
+    same_m &= bool(torch.all(torch.where(feas[:, None], (b_lb == out_lb) & (b_ub == out_ub),
+                                         True)).item())
+    t0 = time.perf_counter()
+    bat_m, m_lb, m_ub = batched()
+    torch.cuda.synchronize()
+    t_bat_m = time.perf_counter() - t0
+    prob.set_marking(False)
+    same_m &= all((a.status, a.rounds) == (b.status, b.rounds) for a, b in zip(seq, bat_m))
+    same_m &= bool(torch.all(torch.where(feas[:, None], (m_lb == b_lb) & (m_ub == b_ub),
+                                         True)).item())
     statuses = {}
     for r in seq:
         statuses[r.status_name] = statuses.get(r.status_name, 0) + 1
@@ -657,6 +678,9 @@ def batched_nodes(count: int, max_rounds: int):
         "rounds_mean": float(np.mean(rounds)),
         "statuses": statuses,
         "identical_results": bool(same_status and same_bounds),
+        "marked": {"batched_ms": t_bat_m * 1e3, "one_at_a_time_ms": t_seq_m * 1e3,
+                   "speedup": t_seq_m / t_bat_m, "batched_vs_plain_one_at_a_time": t_seq / t_bat_m,
+                   "identical_results": bool(same_m)},
     }
     log(f"batched nodes: {out}")
     prob.close()
