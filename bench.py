@@ -171,7 +171,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--max-rounds", type=int, default=100)
-    ap.add_argument("--loop", default="stream", choices=["persistent", "stream", "host", "graph"])
+    ap.add_argument("--loop", default="stream",
+                    choices=["persistent", "stream", "host", "graph", "graph_all"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cpu-seq", action="store_true",
                     help="skip the sequential-propagation comparison on the medium instance")
@@ -321,7 +322,7 @@ def main():
 
     loops = {}
     if not args.no_loop_compare:
-        for mode in ("persistent", "stream", "host", "graph"):
+        for mode in ("persistent", "stream", "host", "graph", "graph_all"):
             prob.set_loop(mode)
             ts = []
             for _ in range(3):

@@ -81,6 +81,9 @@ extern "C" {
 #define PROP_LOOP_HOST 2       /* per-round kernels, host reads the flag every round */
 #define PROP_LOOP_GRAPH 3      /* as STREAM, each batch of rounds one replay of a HIP graph
                                   captured on the first run (kernels exit early once done) */
+#define PROP_LOOP_GRAPH_ALL 4  /* the replays of GRAPH for all max_rounds rounds queued at
+                                  once: the host reads nothing until the end, and rounds
+                                  after the last one exit at once */
 
 typedef struct prop_problem prop_problem; /* opaque */
 
@@ -170,8 +173,10 @@ int prop_run(prop_problem* p, double* lb, double* ub, int32_t max_rounds, prop_r
  * of 4 and, after queueing a batch, wait on the event of the batch before
  * it to read the device's done flag; the host driver synchronises the
  * stream after every round; the persistent driver runs every round in one
- * launch.  All of them synchronise the stream at the end to fill *out (host
- * memory).  Bound validation happens on the device; an invalid bound makes
+ * launch, and the graph-all driver queues ceil(max_rounds / 4) graph
+ * replays before waiting on anything (each round after the run has ended
+ * costs three kernel launches that exit at once).  All of them synchronise
+ * the stream at the end to fill *out (host memory).  Bound validation happens on the device; an invalid bound makes
  * the call return PROP_EINVAL. */
 int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rounds,
                     void* stream, prop_result* out);
@@ -226,7 +231,9 @@ int prop_run_batch(prop_problem* p, int32_t nodes, double* lb, double* ub, int32
 int prop_run_batch_device_static(prop_problem* p, int32_t nodes, double* d_lb, double* d_ub,
                                  int32_t max_rounds, void* stream, prop_result* out);
 
-/* Selects the round-loop driver (PROP_LOOP_*) for later runs. */
+/* Selects the round-loop driver (PROP_LOOP_*) for later runs.  Batches run
+ * PROP_LOOP_GRAPH_ALL as PROP_LOOP_GRAPH (their compaction reads the device's
+ * node counts). */
 int prop_set_loop(prop_problem* p, int32_t mode);
 
 /* Marked rounds (enable != 0; off by default), for prop_run and

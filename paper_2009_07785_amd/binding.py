@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libprop.so")
 CONVERGED, INFEASIBLE, MAX_ROUNDS = 0, 1, 2
 STATUS_NAMES = {CONVERGED: "CONVERGED", INFEASIBLE: "INFEASIBLE", MAX_ROUNDS: "MAX_ROUNDS"}
 OK, EINVAL, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4
-LOOP_PERSISTENT, LOOP_STREAM, LOOP_HOST, LOOP_GRAPH = 0, 1, 2, 3
+LOOP_PERSISTENT, LOOP_STREAM, LOOP_HOST, LOOP_GRAPH, LOOP_GRAPH_ALL = 0, 1, 2, 3, 4
 LOOP_NAMES = {"persistent": LOOP_PERSISTENT, "stream": LOOP_STREAM, "host": LOOP_HOST,
-              "graph": LOOP_GRAPH}
+              "graph": LOOP_GRAPH, "graph_all": LOOP_GRAPH_ALL}
 STORE_F64, STORE_F32 = 64, 32
 
 # every function the header declares

@@ -377,6 +377,17 @@ int run_loop(prop_problem* p, int32_t max_rounds, hipStream_t s) {
       }
       return PROP_OK;
     }
+    case PROP_LOOP_GRAPH_ALL: {
+      // every replay the round limit may need, queued before any wait: the
+      // round loop runs without the host (rounds after the end exit at once)
+      HIP_TRY(launch_start(P, max_rounds, s));
+      if (P.marking && P.parent) HIP_TRY(launch_seed(P, s));
+      const int rc = ensure_graphs(p);
+      if (rc) return rc;
+      for (int r = 1, slot = 0; r <= max_rounds; r += p->batch_rounds, slot ^= 1)
+        HIP_TRY(hipGraphLaunch(p->gexec[slot], s));
+      return PROP_OK;
+    }
     case PROP_LOOP_GRAPH: {
       // as the stream driver, with each batch one replay of a captured graph
       // (rounds past the limit find the done flag set and exit at once)
@@ -843,7 +854,7 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
   // rounds in batches; the done flag and the active-node count are read one
   // batch behind (see the stream driver of single runs).  When the active
   // nodes would fit in fewer groups, the batch is compacted.
-  bool graph = p->loop_mode == PROP_LOOP_GRAPH;
+  bool graph = p->loop_mode == PROP_LOOP_GRAPH || p->loop_mode == PROP_LOOP_GRAPH_ALL;
   if (graph) {
     rc = ensure_batch_graphs(p, bt);
     if (rc) return rc;
@@ -1031,7 +1042,7 @@ int prop_autotune(const prop_csr* A, const double* lhs, const double* rhs, const
 int prop_set_loop(prop_problem* p, int32_t mode) {
   if (!p) return fail(PROP_EINVAL, "NULL problem");
   if (mode != PROP_LOOP_PERSISTENT && mode != PROP_LOOP_STREAM && mode != PROP_LOOP_HOST &&
-      mode != PROP_LOOP_GRAPH)
+      mode != PROP_LOOP_GRAPH && mode != PROP_LOOP_GRAPH_ALL)
     return fail(PROP_EINVAL, "unknown loop mode %d", mode);
   p->loop_mode = mode;
   return PROP_OK;

@@ -72,7 +72,7 @@ def test_children_single_runs(lib, torch_cuda, name, make, count, per_child):
             same(f"{inst.name}/child{k}/unmarked", res, lb, ub, refs[k])
         p.set_marking(True)
         p.set_parent(d_plb, d_pub)
-        for loop in ("stream", "graph", "host"):
+        for loop in ("stream", "graph", "graph_all", "host"):
             p.set_loop(loop)
             for k in range(count):
                 res, lb, ub = p.run(lbs[k], ubs[k], 100)

@@ -13,7 +13,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-LOOPS = ("stream", "persistent", "host", "graph")
+LOOPS = ("stream", "persistent", "host", "graph", "graph_all")
 # every chunk layout, and the nnz-split waves
 LAYOUTS = (dict(steps=4), dict(steps=8), dict(steps=16), dict(layout=1))
 

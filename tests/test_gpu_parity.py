@@ -23,7 +23,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-LOOPS = ("persistent", "stream", "host", "graph")
+LOOPS = ("persistent", "stream", "host", "graph", "graph_all")
 
 
 @pytest.fixture(scope="module")
@@ -272,7 +272,7 @@ def test_marked_rounds(lib):
         ref = oracle.run(inst, inst.lb, inst.ub, 100)
         with lib.Problem.from_instance(inst) as p:
             p.set_marking(True)
-            for loop in ("stream", "host", "graph", "persistent"):
+            for loop in ("stream", "host", "graph", "graph_all", "persistent"):
                 p.set_loop(loop)
                 say(f"  marked {inst.name} loop={loop}")
                 assert_same(f"marked {inst.name}/{loop}", p.run(inst.lb, inst.ub, 100), ref)
@@ -457,7 +457,7 @@ def test_empty_and_degenerate_shapes(lib, torch_cuda):
         with lib.Problem.from_instance(inst) as p:
             for marking in (False, True):
                 p.set_marking(marking)
-                for loop in ("stream", "graph", "host"):
+                for loop in ("stream", "graph", "graph_all", "host"):
                     p.set_loop(loop)
                     assert_same(f"{inst.name} {loop} marking={marking}",
                                 p.run(inst.lb, inst.ub, 100), ref)

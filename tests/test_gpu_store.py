@@ -16,7 +16,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-LOOPS = ("persistent", "stream", "host", "graph")
+LOOPS = ("persistent", "stream", "host", "graph", "graph_all")
 
 
 @pytest.fixture(scope="module")
@@ -162,7 +162,7 @@ def test_marking_parent_and_switching(lib):
         dev = torch.device("cuda:0")
         p.set_parent(torch.tensor(ref32.lb, dtype=torch.float64, device=dev),
                      torch.tensor(ref32.ub, dtype=torch.float64, device=dev))
-        for loop in ("stream", "graph", "host"):
+        for loop in ("stream", "graph", "graph_all", "host"):
             p.set_loop(loop)
             for k in range(6):
                 same(f"child{k}/marked+parent/{loop}", p.run(lbs[k], ubs[k], 100), kids[k])
