@@ -201,6 +201,8 @@ def main():
     ap.add_argument("--serving-rate-below", type=float, default=400.0,
                     help="a second, shorter phase at a rate the server sustains (0: none)")
     ap.add_argument("--serving-seconds-below", type=float, default=20.0)
+    ap.add_argument("--serving-marking", type=int, default=1, choices=[0, 1],
+                    help="marked rounds per group of serving slots (results unchanged)")
     ap.add_argument("--serving-max-slots", type=int, default=256,
                     help="slots per instance (requests of one instance running at once)")
     ap.add_argument("--serving-max-pending", type=int, default=1024,
@@ -371,7 +373,7 @@ def main():
         serve = serving(args.serving_scale, args.serving_seconds, args.serving_rate,
                         int(args.serving_budget_gib * (1 << 30)), args.serving_max_pending,
                         args.serving_rate_below, args.serving_seconds_below,
-                        args.serving_max_slots)
+                        args.serving_max_slots, marking=bool(args.serving_marking))
 
     # the CPU baseline leg: the oracle's synchronous rounds on config2 and,
     # as the paper's own comparison, its sequential Algorithm 1 on config1
@@ -769,7 +771,7 @@ def children_nodes(count: int, max_rounds: int):
 
 def serving(scale: float, seconds: float, rate: float, budget: int, max_pending: int,
             rate_below: float = 0.0, seconds_below: float = 0.0, max_slots: int = 256,
-            variants: int = 8, max_rounds: int = 50, verify: int = 1000):
+            variants: int = 8, max_rounds: int = 50, verify: int = 1000, marking: bool = False):
     """Open-loop serving: Poisson arrivals at `rate` per second for `seconds`,
     each request a bound vector (0-5% of all variables fixed to a feasible
     point's values) on one of 64 resident instances drawn uniformly.  A
@@ -804,7 +806,7 @@ def serving(scale: float, seconds: float, rate: float, budget: int, max_pending:
               for k, inst in enumerate(pool)]
     alone = [[probs[k].run(lb, ub, max_rounds) for lb, ub in bounds[k]]
              for k in range(len(pool))]
-    srv = binding.Server(budget, max_slots=max_slots, max_pending=max_pending)
+    srv = binding.Server(budget, max_slots=max_slots, max_pending=max_pending, marking=marking)
     for p in probs:
         srv.add_instance(p)
     # warm the server: one request per instance
@@ -911,6 +913,7 @@ def serving(scale: float, seconds: float, rate: float, budget: int, max_pending:
         **main,
         "max_pending": max_pending,
         "max_slots": max_slots,
+        "marking": marking,
         "budget_bytes": budget,
         "verified_against": "the same request run alone (prop_run), bitwise, on a sample spread "
                             "over the run",

@@ -362,6 +362,16 @@ typedef struct {
   int32_t rounds_per_step; /* rounds queued between status reads (0: 2) */
   int32_t max_pending;     /* requests held (queued, running or unread) before
                               prop_srv_submit returns PROP_EBUSY (0: 1 << 20) */
+  int32_t marking;         /* != 0: marked rounds per group of 8 slots, as by
+                              prop_set_marking for batches (a row is processed only
+                              when one of its variables changed in the previous round
+                              in a slot of the group; a request joining a group makes
+                              the group's next round process every row); results are
+                              bitwise those without.  prop_srv_add_instance then
+                              uploads the problem's variable rows (as the first
+                              prop_set_marking does, charged to the problem) and adds
+                              4 bytes per row and n / 8 + 8 bytes per group of slots
+                              to the instance's state (charged to the budget). */
 } prop_srv_config;
 
 typedef struct {

@@ -68,7 +68,8 @@ class _Info(ctypes.Structure):
 
 class _SrvConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
-                ("rounds_per_step", ctypes.c_int32), ("max_pending", ctypes.c_int32)]
+                ("rounds_per_step", ctypes.c_int32), ("max_pending", ctypes.c_int32),
+                ("marking", ctypes.c_int32)]
 
 
 class _SrvStats(ctypes.Structure):
@@ -396,10 +397,10 @@ class Server:
     (prop_srv_* in the C ABI).  Problems added must outlive the server."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 0, rounds_per_step: int = 0,
-                 max_pending: int = 0):
+                 max_pending: int = 0, marking: bool = False):
         self._h = None
         cfg = _SrvConfig(int(budget_bytes), int(max_slots), int(rounds_per_step),
-                         int(max_pending))
+                         int(max_pending), 1 if marking else 0)
         h = ctypes.c_void_p()
         _check(lib.prop_srv_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

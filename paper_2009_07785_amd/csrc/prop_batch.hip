@@ -184,6 +184,9 @@ __global__ __launch_bounds__(kBlock) void k_start_batch(Problem P, Batch Bt, int
     Bt.infeasible[k] = 0;
     Bt.invalid[k] = 0;
     if (Bt.live) Bt.live[k] = 1;
+    // serving: a slot that joins a running group forces the group's next
+    // round over every row (its own first round must see them all)
+    if (!whole && a && Bt.row_mark) Bt.gall[k / kNodeGroup] = 1;
     act += a;
   }
   if (whole && Bt.row_mark) {
@@ -212,8 +215,9 @@ __device__ __forceinline__ bool group_marked(const Problem& P, const Batch& Bt, 
   return true;
 }
 
-// kMarks: the batch driver's kernels, whose groups may run marked rounds;
-// the serving kernels never do.
+// kMarks: kernels whose groups may run marked rounds (the batch driver's,
+// and the serving engine's when the server marks); without it the
+// registers of the marking paths are not allocated.
 template <bool kMarks>
 __device__ __forceinline__ void round_unit(const Problem& P, const Batch& Bt, int unit, int g) {
   if (unit >= P.n_segs + P.n_chunks) return;
@@ -415,9 +419,8 @@ __global__ __launch_bounds__(kBlock) void k_end_batch(Problem P, Batch Bt) {
 // one thread per piece of <= kMarkPiece rows of a variable (blockIdx.y is
 // the group).  A group that changed more than n / kMarkAllDiv variables
 // processes every row instead (stamping them would cost more).
-__global__ __launch_bounds__(kBlock) void k_mark_batch(Problem P, Batch Bt, int offset) {
-  if (u32_load(&P.ctrl->done)) return;
-  const int g = blockIdx.y;
+__device__ __forceinline__ void mark_group(const Problem& P, const Batch& Bt, int g, uint32_t bx,
+                                           uint32_t nbx, int offset) {
   if (!group_mask(Bt, g)) return;
   uint32_t count = 0;
   if (offset == 0) {
@@ -430,20 +433,25 @@ __global__ __launch_bounds__(kBlock) void k_mark_batch(Problem P, Batch Bt, int 
     }
   }
   const bool all = count > (uint32_t)(P.n / kMarkAllDiv);
-  if (blockIdx.x == 0 && threadIdx.x == 0) Bt.gall[g] = all ? 1u : 0u;
+  if (bx == 0 && threadIdx.x == 0) Bt.gall[g] = all ? 1u : 0u;
   if (all) return;
   const int next = __hip_atomic_load(&P.ctrl->round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
                    offset;
   const uint64_t* bits = Bt.chg + (size_t)g * ((P.n + kWave - 1) / kWave);
   int32_t* marks = Bt.row_mark + (size_t)g * P.n_rows;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P.n_pieces; q += stride) {
+  const int64_t stride = (int64_t)nbx * blockDim.x;
+  for (int64_t q = (int64_t)bx * blockDim.x + threadIdx.x; q < P.n_pieces; q += stride) {
     const int32_t v = P.piece_var[q];
     if (!((bits[v / kWave] >> (v % kWave)) & 1ull)) continue;
     const int64_t start = P.piece_off[q];
     const int64_t stop = P.var_ptr[v + 1] < start + kMarkPiece ? P.var_ptr[v + 1] : start + kMarkPiece;
     for (int64_t i = start; i < stop; ++i) marks[P.var_rows[i]] = next;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mark_batch(Problem P, Batch Bt, int offset) {
+  if (u32_load(&P.ctrl->done)) return;
+  mark_group(P, Bt, blockIdx.y, blockIdx.x, gridDim.x, offset);
 }
 
 // Marked batches from a parent fixed point: bit v of group g's bitmap is set
@@ -487,7 +495,10 @@ __device__ __forceinline__ int step_entry(const SrvStep* S, int64_t x, int which
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     const SrvEntry& E = S->e[mid];
-    const int64_t base = which == 0 ? E.round_base : which == 1 ? E.long_base : E.commit_base;
+    const int64_t base = which == 0   ? E.round_base
+                         : which == 1 ? E.long_base
+                         : which == 2 ? E.commit_base
+                                      : E.mark_base;
     if (base <= x) lo = mid;
     else hi = mid - 1;
   }
@@ -501,8 +512,9 @@ __device__ __forceinline__ Batch step_batch(const SrvInst* I, const SrvEntry& E)
   return Bt;
 }
 
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_srv_round(const SrvInst* __restrict__ I,
-                                                      const SrvStep* __restrict__ S) {
+template <bool kMarks>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_srv_round(
+    const SrvInst* __restrict__ I, const SrvStep* __restrict__ S) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
   if (wid >= S->round_total) return;
@@ -515,9 +527,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   const int64_t units = (int64_t)P.n_segs + P.n_chunks;
   if (units == 0) return;
   const int g = (int)(local / units);
-  round_unit<false>(P, Bt, (int)(local - (int64_t)g * units), g);
+  round_unit<kMarks>(P, Bt, (int)(local - (int64_t)g * units), g);
 }
 
+template <bool kMarks>
 __global__ __launch_bounds__(kBlock) void k_srv_long(const SrvInst* __restrict__ I,
                                                      const SrvStep* __restrict__ S) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -530,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_srv_long(const SrvInst* __restrict__
   const int64_t local = wid - E.long_base;
   if (P.n_segs == 0) return;
   const int k = (int)(local / P.n_segs);
-  long_unit<false>(P, Bt, (int)(local - (int64_t)k * P.n_segs), k);
+  long_unit<kMarks>(P, Bt, (int)(local - (int64_t)k * P.n_segs), k);
 }
 
 __global__ __launch_bounds__(kBlock) void k_srv_commit(const SrvInst* __restrict__ I,
@@ -546,14 +559,34 @@ __global__ __launch_bounds__(kBlock) void k_srv_commit(const SrvInst* __restrict
   commit_part(P, Bt, g, local - g * E.commit_blocks, E.commit_blocks, ch, inf);
 }
 
+// Marked rounds of the instances that mark, after the commit: stamps the
+// rows of each group's changed variables with the next round (mark_group).
+__global__ __launch_bounds__(kBlock) void k_srv_mark(const SrvInst* __restrict__ I,
+                                                     const SrvStep* __restrict__ S) {
+  if ((int64_t)blockIdx.x >= S->mark_total) return;
+  const SrvEntry E = S->e[step_entry(S, blockIdx.x, 3)];
+  if (E.mark_blocks == 0) return;
+  const Problem P = I[E.inst].P;
+  if (u32_load(&P.ctrl->done)) return;
+  const Batch Bt = step_batch(I, E);
+  const int local = (int)((int64_t)blockIdx.x - E.mark_base);
+  const int g = local / E.mark_blocks;
+  if (g >= E.groups) return;
+  mark_group(P, Bt, g, local - g * E.mark_blocks, E.mark_blocks, 1);
+}
+
 // One block per entry.  No early exit on the done flag: slots finished at
-// their start, or left unreported by a full list, are reported here.
+// their start, or left unreported by a full list, are reported here.  A
+// marking instance counts its rounds in its control block (the stamps of
+// the mark kernel name the next one).
 __global__ __launch_bounds__(kBlock) void k_srv_end(const SrvInst* __restrict__ I,
                                                     SrvStep* __restrict__ S) {
   if ((int)blockIdx.x >= S->n) return;
   const SrvEntry E = S->e[blockIdx.x];
   const Problem P = I[E.inst].P;
-  end_slots(P, step_batch(I, E), S, E.inst);
+  const Batch Bt = step_batch(I, E);
+  if (Bt.row_mark && threadIdx.x == 0) P.ctrl->round = P.ctrl->round + 1;
+  end_slots(P, Bt, S, E.inst);
 }
 
 // ---------------------------------------------------------------------------
@@ -626,13 +659,19 @@ hipError_t launch_unpack_slots(const Problem& P, const Batch& Bt, double* lb, do
 
 hipError_t launch_srv_round(const SrvInst* I, SrvStep* S, const SrvStep& H, hipStream_t s) {
   if (H.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_srv_round, dim3(blocks_for(H.round_total, kWavesPerBlock, 1 << 30)),
-                     dim3(kBlock), 0, s, I, S);
-  if (H.long_total)
-    hipLaunchKernelGGL(k_srv_long, dim3(blocks_for(H.long_total, kWavesPerBlock, 1 << 30)),
-                       dim3(kBlock), 0, s, I, S);
+  const dim3 rgrid(blocks_for(H.round_total, kWavesPerBlock, 1 << 30));
+  if (H.mark_total) hipLaunchKernelGGL(k_srv_round<true>, rgrid, dim3(kBlock), 0, s, I, S);
+  else hipLaunchKernelGGL(k_srv_round<false>, rgrid, dim3(kBlock), 0, s, I, S);
+  if (H.long_total) {
+    const dim3 lgrid(blocks_for(H.long_total, kWavesPerBlock, 1 << 30));
+    if (H.mark_total) hipLaunchKernelGGL(k_srv_long<true>, lgrid, dim3(kBlock), 0, s, I, S);
+    else hipLaunchKernelGGL(k_srv_long<false>, lgrid, dim3(kBlock), 0, s, I, S);
+  }
   hipLaunchKernelGGL(k_srv_commit, dim3(blocks_for(H.commit_total, 1, 1 << 30)), dim3(kBlock), 0,
                      s, I, S);
+  if (H.mark_total)
+    hipLaunchKernelGGL(k_srv_mark, dim3(blocks_for(H.mark_total, 1, 1 << 30)), dim3(kBlock), 0,
+                       s, I, S);
   hipLaunchKernelGGL(k_srv_end, dim3(H.n), dim3(kBlock), 0, s, I, S);
   return hipGetLastError();
 }

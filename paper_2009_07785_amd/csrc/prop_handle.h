@@ -26,6 +26,9 @@ extern thread_local std::string g_error;
                         #expr, hipGetErrorString(e_));                                   \
   } while (0)
 
+// Uploads the rows of every variable for marked rounds (once per problem).
+int ensure_mark_data(prop_problem* p);
+
 struct prop_problem {
   int device = 0;
   int32_t m = 0, n = 0;

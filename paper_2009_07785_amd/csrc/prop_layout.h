@@ -143,8 +143,9 @@ struct SrvEntry {          // an instance in a step, with the first work item of
   int64_t round_base;      // waves of the round kernel
   int64_t long_base;       // waves of the long-row kernel
   int64_t commit_base;     // blocks of the commit kernel
+  int64_t mark_base;       // blocks of the mark kernel (marked rounds)
   int32_t commit_blocks;   // commit blocks per group
-  int32_t pad;
+  int32_t mark_blocks;     // mark blocks per group, 0 when the instance is unmarked
 };
 
 constexpr int kSrvStepDone = 512;     // completions a step can report (more wait a round)
@@ -153,7 +154,7 @@ constexpr int kSrvMaxInstances = 256;
 struct SrvStep {
   int32_t n;               // entries
   uint32_t n_done;         // completions reported (may exceed kSrvStepDone)
-  int64_t round_total, long_total, commit_total;
+  int64_t round_total, long_total, commit_total, mark_total;
   SrvDone done[kSrvStepDone];
   SrvEntry e[kSrvMaxInstances];
 };

@@ -323,7 +323,7 @@ int prop_server::queue_step() {
   SrvStep& H = *h_step[ring];
   H.n = 0;
   H.n_done = 0;
-  int64_t rw = 0, lw = 0, cb = 0;
+  int64_t rw = 0, lw = 0, cb = 0, mb = 0;
   for (Instance* ip : live) {
     Instance& I = *ip;
     if (I.running == 0 || I.hi_groups == 0) continue;
@@ -335,14 +335,19 @@ int prop_server::queue_step() {
     E.commit_base = cb;
     E.commit_blocks = (int32_t)std::min<int64_t>(256, ((int64_t)I.n * kNodeGroup + kBlock - 1) / kBlock);
     if (E.commit_blocks < 1) E.commit_blocks = 1;
-    E.pad = 0;
+    E.mark_base = mb;
+    E.mark_blocks = I.bt.row_mark ? (int32_t)std::min<int64_t>(
+                                        256, std::max<int64_t>(1, (I.P.n_pieces + kBlock - 1) / kBlock))
+                                  : 0;
     rw += (int64_t)(I.P.n_chunks + I.P.n_segs) * E.groups;
     lw += (int64_t)I.P.n_segs * E.groups * kNodeGroup;
     cb += (int64_t)E.commit_blocks * E.groups;
+    mb += (int64_t)E.mark_blocks * E.groups;
   }
   H.round_total = rw;
   H.long_total = lw;
   H.commit_total = cb;
+  H.mark_total = mb;
   if (H.n == 0) return PROP_OK;
   SRV_TRY(hipMemcpyAsync(d_step[ring], &H, offsetof(SrvStep, e) + (size_t)H.n * sizeof(SrvEntry),
                          hipMemcpyHostToDevice, stream));
@@ -561,13 +566,28 @@ int prop_srv_add_instance(prop_server* s, prop_problem* p, int32_t* id) {
   I->cap = s->cfg.max_slots;
   const int32_t cap = I->cap, G8 = cap / kNodeGroup;
   const int32_t segs = p->P.n_segs;
-  // one allocation: 9 per-slot arrays, partials, the two group tables, control
+  const bool marks = s->cfg.marking != 0;
+  if (marks) {
+    // the rows of every variable, uploaded once per problem (its own memory)
+    const int rc2 = ensure_mark_data(p);
+    if (rc2) return rc2;
+  }
+  // one allocation: 9 per-slot arrays, partials, the two group tables,
+  // control, and with marked rounds the row stamps, changed-variable bitmaps
+  // and two flags per group
   const size_t slot_arrays = 9 * (size_t)cap * sizeof(int32_t);
   const size_t part_off = (slot_arrays + 255) & ~(size_t)255;
   const size_t part_bytes = (size_t)(segs > 0 ? segs : 1) * cap * sizeof(SegPartial);
   const size_t table_off = (part_off + part_bytes + 255) & ~(size_t)255;
   const size_t ctrl_off = (table_off + 2 * (size_t)G8 * sizeof(double2*) + 255) & ~(size_t)255;
-  const size_t total = ctrl_off + sizeof(Ctrl);
+  const size_t words = ((size_t)(p->n > 0 ? p->n : 1) + kWave - 1) / kWave;
+  const size_t rows = (size_t)(p->P.n_rows > 0 ? p->P.n_rows : 1);
+  const size_t mark_off = (ctrl_off + sizeof(Ctrl) + 255) & ~(size_t)255;
+  const size_t chg_off = (mark_off + (marks ? (size_t)G8 * rows * sizeof(int32_t) : 0) + 255) &
+                         ~(size_t)255;
+  const size_t flag_off = (chg_off + (marks ? (size_t)G8 * words * sizeof(uint64_t) : 0) + 255) &
+                          ~(size_t)255;
+  const size_t total = flag_off + (marks ? 2 * (size_t)G8 * sizeof(uint32_t) : 0);
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->device_bytes + (int64_t)total > s->cfg.budget_bytes)
@@ -603,6 +623,12 @@ int prop_srv_add_instance(prop_server* s, prop_problem* p, int32_t* id) {
   bt.gB = I->d_table + G8;
   bt.nodes = cap;
   bt.groups = G8;
+  if (marks) {
+    bt.row_mark = reinterpret_cast<int32_t*>(base + mark_off);
+    bt.chg = reinterpret_cast<uint64_t*>(base + chg_off);
+    bt.gall = reinterpret_cast<uint32_t*>(base + flag_off);
+    bt.gcnt = bt.gall + G8;
+  }
   I->P = p->P;
   I->P.ctrl = reinterpret_cast<Ctrl*>(base + ctrl_off);
   I->groups.resize(G8);

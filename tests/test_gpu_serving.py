@@ -127,6 +127,37 @@ def test_serving_staggered_arrivals(lib, pool):
     check_alone(probs, reqs, results)
 
 
+@pytest.mark.parametrize("rounds_per_step", [1, 3])
+def test_serving_marked_matches_alone(lib, pool, rounds_per_step):
+    """Marked rounds per group of slots: requests join running groups (each
+    join forces its group's next round over every row), finish at different
+    rounds and leave; every result stays bitwise that of the request run
+    alone without marking, and the oracle's on a sample."""
+    insts, probs = pool
+    ns = [i.n for i in insts]
+    reqs = make_requests(insts, 160, 3 + rounds_per_step)
+    with lib.Server(1 << 30, max_slots=32, rounds_per_step=rounds_per_step,
+                    marking=True) as srv:
+        for p in probs:
+            srv.add_instance(p)
+        tickets = []
+        for q, (k, lb, ub, mr) in enumerate(reqs):
+            tickets.append(srv.submit(k, lb, ub, mr))
+            if q % 7 == 6:
+                time.sleep(0.002)
+        results = [srv.wait(t, ns[k], timeout_ms=60_000) for t, (k, *_) in zip(tickets, reqs)]
+        st = srv.stats()
+    assert all(r is not None for r in results)
+    assert st["completed"] == len(reqs)
+    statuses = check_alone(probs, reqs, results)
+    assert oracle.CONVERGED in statuses
+    for (k, lb, ub, mr), (res, glb, gub) in list(zip(reqs, results))[:12]:
+        ref = oracle.run(insts[k], lb, ub, mr)
+        assert (res.status, res.rounds) == (ref.status, ref.rounds)
+        if ref.status != oracle.INFEASIBLE:
+            assert same_bits(glb, ref.lb) and same_bits(gub, ref.ub)
+
+
 def test_serving_against_oracle(lib, pool):
     insts, probs = pool
     order = np.argsort([i.nnz for i in insts])[:2]
