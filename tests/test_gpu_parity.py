@@ -203,6 +203,29 @@ def test_config1_suite(lib):
             assert ref.status == oracle.CONVERGED
 
 
+def test_limit_point_matches_sequential(lib):
+    """Bounded pure-integer systems have one limit point (Sec. 1.1): the
+    GPU's synchronous rounds end at the bounds of the sequential Algorithm 1
+    with marking (plain double sums in CSR order), in no fewer rounds than
+    its sweeps; the large-instance version of this check is the rounds
+    study of bench.py."""
+    same = 0
+    with_seq = 0
+    for s in range(40):
+        inst = synth.random_small(2_900 + s, m=int(4 + s % 6), n=int(4 + s % 5), box=6, slack=4.0)
+        seq, _ = oracle.CpuSeq(inst).run(inst.lb, inst.ub, 200)
+        with lib.Problem.from_instance(inst) as p:
+            p.set_loop("graph_all" if s % 2 else "stream")
+            res, lb, ub = p.run(inst.lb, inst.ub, 200)
+        assert res.status == seq.status, s
+        if seq.status == oracle.CONVERGED:
+            assert same_bits(lb, seq.lb) and same_bits(ub, seq.ub), s
+            assert seq.rounds <= res.rounds, s
+            same += 1
+        with_seq += 1
+    assert same > 20, (same, with_seq)
+
+
 def test_determinism_device_path(lib, torch_cuda):
     torch = torch_cuda
     inst = synth.config1(1)
