@@ -343,11 +343,20 @@ int run_loop(prop_problem* p, int32_t max_rounds, hipStream_t s) {
   p->kev_used = 0;
   hipError_t e;
   switch (p->loop_mode) {
-    case PROP_LOOP_PERSISTENT:
-      e = launch_persistent(P, max_rounds, p->grid, s);
+    case PROP_LOOP_PERSISTENT: {
+      // no more blocks than the work needs: one wave per chunk or segment
+      // and about four variables per commit thread; every block takes part
+      // in every grid barrier, so idle blocks only add to their cost
+      const int64_t items = (int64_t)P.n_chunks + P.n_segs;
+      const int64_t want =
+          std::max<int64_t>({(items + kWavesPerBlock - 1) / kWavesPerBlock,
+                             ((int64_t)P.n + 4 * kBlock - 1) / (4 * kBlock), (int64_t)1});
+      const int grid = (int)std::min<int64_t>(p->grid, want);
+      e = launch_persistent(P, max_rounds, grid, s);
       if (e != hipSuccess)
         return fail(PROP_EDEVICE, "cooperative launch failed: %s", hipGetErrorString(e));
       return PROP_OK;
+    }
     case PROP_LOOP_STREAM: {
       // Rounds are queued in batches; after each batch the device's done
       // flag is copied to pinned memory behind an event.  The host waits for
