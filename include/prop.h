@@ -190,8 +190,9 @@ int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rou
  * and bounds are bitwise those a separate prop_run_device call on that node
  * returns; nodes that finish early stop consuming work.  Rounds are queued
  * on `stream` in batches as by PROP_LOOP_STREAM (or replayed as by
- * PROP_LOOP_GRAPH).  When the nodes still running would fit in fewer groups
- * of 8, the call synchronises `stream`, writes the finished nodes' rows of
+ * PROP_LOOP_GRAPH, also for PROP_LOOP_GRAPH_ALL).  When the nodes still
+ * running would fit in fewer groups of 8, the call synchronises `stream`,
+ * writes the finished nodes' rows of
  * d_lb / d_ub, and packs the running nodes into fewer groups; the rest of
  * the rows are written at the end.  The first call with more nodes than any
  * earlier call allocates the batch workspace (32 * n * ceil(nodes / 8) * 8
@@ -237,7 +238,7 @@ int prop_run_batch_device_static(prop_problem* p, int32_t nodes, double* d_lb, d
 int prop_set_loop(prop_problem* p, int32_t mode);
 
 /* Marked rounds (enable != 0; off by default), for prop_run and
- * prop_run_device with the stream, graph or host driver, and for
+ * prop_run_device with the stream, graph, graph-all or host driver, and for
  * prop_run_batch / prop_run_batch_device (the persistent driver and
  * prop_run_batch_device_static ignore it).  A row is then processed in
  * round r >= 2 only when one of its variables changed in round r - 1 (in a
