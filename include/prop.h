@@ -192,9 +192,8 @@ int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rou
  * on `stream` in batches as by PROP_LOOP_STREAM (or replayed as by
  * PROP_LOOP_GRAPH, also for PROP_LOOP_GRAPH_ALL).  When the nodes still
  * running would fit in fewer groups of 8, the call synchronises `stream`,
- * writes the finished nodes' rows of
- * d_lb / d_ub, and packs the running nodes into fewer groups; the rest of
- * the rows are written at the end.  The first call with more nodes than any
+ * writes the finished nodes' rows of d_lb / d_ub, and packs the running
+ * nodes into fewer groups; the rest of the rows are written at the end.  The first call with more nodes than any
  * earlier call allocates the batch workspace (32 * n * ceil(nodes / 8) * 8
  * bytes of bounds, plus per-node counters and lists and long-row partials),
  * kept until prop_destroy; later calls allocate nothing.  An invalid bound
