@@ -190,8 +190,8 @@ int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rou
  * and bounds are bitwise those a separate prop_run_device call on that node
  * returns; nodes that finish early stop consuming work.  Rounds are queued
  * on `stream` in batches as by PROP_LOOP_STREAM (or replayed as by
- * PROP_LOOP_GRAPH, also for PROP_LOOP_GRAPH_ALL).  When the nodes still
- * running would fit in fewer groups of 8, the call synchronises `stream`,
+ * PROP_LOOP_GRAPH; PROP_LOOP_GRAPH_ALL: see prop_set_loop).  When the nodes
+ * still running would fit in fewer groups of 8, the call synchronises `stream`,
  * writes the finished nodes' rows of d_lb / d_ub, and packs the running
  * nodes into fewer groups; the rest of the rows are written at the end.  The first call with more nodes than any
  * earlier call allocates the batch workspace (32 * n * ceil(nodes / 8) * 8
@@ -231,9 +231,10 @@ int prop_run_batch(prop_problem* p, int32_t nodes, double* lb, double* ub, int32
 int prop_run_batch_device_static(prop_problem* p, int32_t nodes, double* d_lb, double* d_ub,
                                  int32_t max_rounds, void* stream, prop_result* out);
 
-/* Selects the round-loop driver (PROP_LOOP_*) for later runs.  Batches run
- * PROP_LOOP_GRAPH_ALL as PROP_LOOP_GRAPH (their compaction reads the device's
- * node counts). */
+/* Selects the round-loop driver (PROP_LOOP_*) for later runs.  Batches with
+ * PROP_LOOP_GRAPH_ALL queue every replay up front as well and read nothing
+ * until the end, so they are never compacted: finished nodes leave their
+ * groups, which keep running with the nodes left. */
 int prop_set_loop(prop_problem* p, int32_t mode);
 
 /* Marked rounds (enable != 0; off by default), for prop_run and

@@ -820,6 +820,47 @@ int compact_batch(prop_problem* p, Batch& bt, std::vector<int32_t>& slot_node,
   return PROP_OK;
 }
 
+// The end of a batch run: the rows of the nodes still in slots are
+// unpacked, every node's status and rounds are read, the stream is
+// synchronised and *out filled.
+int finish_batch(prop_problem* p, const Batch& bt, int32_t nodes, double* d_lb, double* d_ub,
+                 const std::vector<int32_t>& slot_node, std::vector<prop_result>& res,
+                 bool compacted, hipStream_t s, prop_result* out) {
+  const Problem& P = p->P;
+  HIP_TRY(hipEventRecord(p->ev[2], s));
+  if (!compacted) {
+    HIP_TRY(launch_unpack_batch(P, bt, d_lb, d_ub, 0, nodes, s));
+  } else if (bt.nodes > 0) {
+    std::vector<int2> fin;
+    for (int k = 0; k < bt.nodes; ++k)
+      if (slot_node[k] >= 0) fin.push_back(make_int2(k, slot_node[k]));
+    // the stream may still run a compaction's unpack of d_bret
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(p->d_bret, fin.data(), fin.size() * sizeof(int2), hipMemcpyHostToDevice));
+    HIP_TRY(launch_unpack_slots(P, bt, d_lb, d_ub, p->d_bret, (int)fin.size(), s));
+  }
+  if (bt.nodes > 0) {
+    HIP_TRY(hipMemcpyAsync(p->h_bstatus, bt.status, bt.nodes * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(p->h_brounds, bt.rounds, bt.nodes * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipEventRecord(p->ev[3], s));
+  HIP_TRY(hipStreamSynchronize(s));
+  hipEventElapsedTime(&p->last_loop_ms, p->ev[1], p->ev[2]);
+  hipEventElapsedTime(&p->last_total_ms, p->ev[0], p->ev[3]);
+  p->kev_used = 0;
+  p->last_kernel_ms = 0.0;
+  for (int k = 0; k < bt.nodes; ++k)
+    if (slot_node[k] >= 0) res[slot_node[k]] = prop_result{p->h_bstatus[k], p->h_brounds[k]};
+  for (int32_t k = 0; k < nodes; ++k)
+    if (res[k].status == kInvalidInput)
+      return fail(PROP_EINVAL, "node %d: a bound is NaN, +inf as lower, -inf as upper, or beyond 2^200", k);
+  for (int32_t k = 0; k < nodes; ++k) out[k] = res[k];
+  g_error.clear();
+  return PROP_OK;
+}
+
 }  // namespace
 
 int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* d_ub,
@@ -860,18 +901,28 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
   HIP_TRY(launch_start_batch(P, bt, max_rounds, 0, nodes, true, s));
   if (bt.row_mark && P.parent) HIP_TRY(launch_seed_batch(P, bt, s));
   HIP_TRY(hipEventRecord(p->ev[1], s));
-  // rounds in batches; the done flag and the active-node count are read one
-  // batch behind (see the stream driver of single runs).  When the active
-  // nodes would fit in fewer groups, the batch is compacted.
-  bool graph = p->loop_mode == PROP_LOOP_GRAPH || p->loop_mode == PROP_LOOP_GRAPH_ALL;
-  if (graph) {
-    rc = ensure_batch_graphs(p, bt);
-    if (rc) return rc;
-  }
   std::vector<int32_t> slot_node(nodes);
   std::iota(slot_node.begin(), slot_node.end(), 0);
   std::vector<prop_result> res(nodes, prop_result{kInvalidInput, 0});
   bool compacted = false;
+  if (p->loop_mode == PROP_LOOP_GRAPH_ALL) {
+    // every replay the round limit may need, queued before any wait: no
+    // host read and no compaction (finished nodes leave their groups, which
+    // keep running with the rest)
+    rc = ensure_batch_graphs(p, bt);
+    if (rc) return rc;
+    for (int r = 1, slot = 0; r <= max_rounds; r += p->batch_rounds, slot ^= 1)
+      HIP_TRY(hipGraphLaunch(p->bgexec[slot], s));
+    return finish_batch(p, bt, nodes, d_lb, d_ub, slot_node, res, compacted, s, out);
+  }
+  // rounds in batches; the done flag and the active-node count are read one
+  // batch behind (see the stream driver of single runs).  When the active
+  // nodes would fit in fewer groups, the batch is compacted.
+  bool graph = p->loop_mode == PROP_LOOP_GRAPH;
+  if (graph) {
+    rc = ensure_batch_graphs(p, bt);
+    if (rc) return rc;
+  }
   int r = 1;
   if (bt.groups > 1 && max_rounds >= 1) {
     // round 1 on its own: nodes whose input domains or first round make
@@ -929,39 +980,9 @@ int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* 
       }
     }
   }
-  HIP_TRY(hipEventRecord(p->ev[2], s));
-  if (!compacted) {
-    HIP_TRY(launch_unpack_batch(P, bt, d_lb, d_ub, 0, nodes, s));
-  } else if (bt.nodes > 0) {
-    std::vector<int2> fin;
-    for (int k = 0; k < bt.nodes; ++k)
-      if (slot_node[k] >= 0) fin.push_back(make_int2(k, slot_node[k]));
-    // the stream may still run a compaction's unpack of d_bret
-    HIP_TRY(hipStreamSynchronize(s));
-    HIP_TRY(hipMemcpy(p->d_bret, fin.data(), fin.size() * sizeof(int2), hipMemcpyHostToDevice));
-    HIP_TRY(launch_unpack_slots(P, bt, d_lb, d_ub, p->d_bret, (int)fin.size(), s));
-  }
-  if (bt.nodes > 0) {
-    HIP_TRY(hipMemcpyAsync(p->h_bstatus, bt.status, bt.nodes * sizeof(int32_t),
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(p->h_brounds, bt.rounds, bt.nodes * sizeof(int32_t),
-                           hipMemcpyDeviceToHost, s));
-  }
-  HIP_TRY(hipEventRecord(p->ev[3], s));
-  HIP_TRY(hipStreamSynchronize(s));
-  hipEventElapsedTime(&p->last_loop_ms, p->ev[1], p->ev[2]);
-  hipEventElapsedTime(&p->last_total_ms, p->ev[0], p->ev[3]);
-  p->kev_used = 0;
-  p->last_kernel_ms = 0.0;
-  for (int k = 0; k < bt.nodes; ++k)
-    if (slot_node[k] >= 0) res[slot_node[k]] = prop_result{p->h_bstatus[k], p->h_brounds[k]};
-  for (int32_t k = 0; k < nodes; ++k)
-    if (res[k].status == kInvalidInput)
-      return fail(PROP_EINVAL, "node %d: a bound is NaN, +inf as lower, -inf as upper, or beyond 2^200", k);
-  for (int32_t k = 0; k < nodes; ++k) out[k] = res[k];
-  g_error.clear();
-  return PROP_OK;
+  return finish_batch(p, bt, nodes, d_lb, d_ub, slot_node, res, compacted, s, out);
 }
+
 
 int prop_run_batch(prop_problem* p, int32_t nodes, double* lb, double* ub, int32_t max_rounds,
                    prop_result* out) {

@@ -49,12 +49,14 @@ def run_batch(torch, p, lbs, ubs, max_rounds=100):
 def check_batch_vs_single(torch, lib, inst, lbs, ubs, max_rounds=100, with_oracle=False):
     with lib.Problem.from_instance(inst) as p:
         res, blb, bub = run_batch(torch, p, lbs, ubs, max_rounds)
-        # the graph driver replays captured rounds: the same results, twice
-        p.set_loop("graph")
-        for _ in range(2):
-            gres, glb, gub = run_batch(torch, p, lbs, ubs, max_rounds)
-            assert [(r.status, r.rounds) for r in gres] == [(r.status, r.rounds) for r in res]
-            assert same_bits(glb, blb) and same_bits(gub, bub)
+        # the graph drivers replay captured rounds (graph-all: every replay
+        # queued up front, no compaction): the same results, twice each
+        for loop in ("graph", "graph_all"):
+            p.set_loop(loop)
+            for _ in range(2):
+                gres, glb, gub = run_batch(torch, p, lbs, ubs, max_rounds)
+                assert [(r.status, r.rounds) for r in gres] == [(r.status, r.rounds) for r in res]
+                assert same_bits(glb, blb) and same_bits(gub, bub)
         p.set_loop("stream")
         statuses = set()
         for k in range(lbs.shape[0]):
