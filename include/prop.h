@@ -346,10 +346,12 @@ void prop_destroy(prop_problem* p);
  * state is never released.  A request waits in its problem's queue (first
  * in, first out) while neither a slot nor room is available.
  *
- * One host thread per server schedules.  All device work goes to one HIP
- * stream of the server (default priority): each round of every problem with
- * running requests is one launch per phase, so the host's launch count does
- * not grow with the number of problems.  At most 256 problems per server,
+ * One host thread per server schedules.  The kernels go to one HIP stream
+ * of the server, the copies of request bounds and results to a second one
+ * (both default priority, ordered with events) so that the copies overlap
+ * the rounds: each round of every problem with running requests is one
+ * launch per phase, so the host's launch count does not grow with the
+ * number of problems.  At most 256 problems per server,
  * all on one device.  The server reads only a problem's matrix and keeps its own
  * control state: prop_run calls on an added problem stay allowed, from one
  * thread at a time as always.  Destroy the server before its problems.

@@ -14,9 +14,13 @@
 // back with the step.  A finished slot is unpacked into its staging area,
 // copied to the host, and freed once that copy has landed.
 //
-// All device work is queued on the server's one stream, so the host staging
-// of a slot, and a step's host copy, are only rewritten after the device
-// work that used them has completed (observed through an event).
+// Kernels and the step tables go on the server's stream; the copies of
+// request bounds in and results out go on a second stream, ordered against
+// the kernels with events (a slot's input copy before its pack kernel, its
+// unpack kernel before the result copy), so that they overlap the rounds
+// of other slots.  The host staging of a slot, and a step's host copy, are
+// only rewritten after the device work that used them has completed
+// (observed through an event).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -125,6 +129,9 @@ struct prop_server {
   std::thread worker;
   // device side, created with the first instance
   hipStream_t stream = nullptr;
+  hipStream_t copy = nullptr;         // request bounds in, results out
+  hipEvent_t ev_in = nullptr;         // an input copy, for the pack kernel to wait on
+  hipEvent_t ev_out = nullptr;        // an unpack kernel, for the result copy to wait on
   SrvInst* d_insts = nullptr;         // kSrvMaxInstances descriptors
   SrvStep* d_step[kStepRing] = {};
   SrvStep* h_step[kStepRing] = {};    // pinned: the step table up, completions down
@@ -231,6 +238,7 @@ void release_group(SlotGroup& G) {
 
 void prop_server::free_group(Instance& I, int g) {
   hipStreamSynchronize(stream);
+  hipStreamSynchronize(copy);
   release_group(I.groups[g]);
   const int32_t G8 = I.cap / kNodeGroup;
   I.h_table[g] = nullptr;
@@ -294,7 +302,9 @@ int prop_server::admit(Instance& I) {
     if (n) {
       std::memcpy(h, r->lb.data(), n * sizeof(double));
       std::memcpy(h + n, r->ub.data(), n * sizeof(double));
-      SRV_TRY(hipMemcpyAsync(d, h, 2 * n * sizeof(double), hipMemcpyHostToDevice, stream));
+      SRV_TRY(hipMemcpyAsync(d, h, 2 * n * sizeof(double), hipMemcpyHostToDevice, copy));
+      SRV_TRY(hipEventRecord(ev_in, copy));
+      SRV_TRY(hipStreamWaitEvent(stream, ev_in, 0));
     }
     Batch bt = I.bt;
     bt.groups = I.hi_groups;
@@ -391,10 +401,12 @@ bool prop_server::poll_steps() {
       bt.groups = I.hi_groups;
       bt.nodes = I.hi_groups * kNodeGroup;
       hipError_t e = launch_unpack_batch(I.P, bt, d, d + n, D.slot, 1, stream);
+      if (e == hipSuccess) e = hipEventRecord(ev_out, stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(copy, ev_out, 0);
       if (e == hipSuccess && n)
         e = hipMemcpyAsync(G.h_io + (size_t)t * 2 * n, d, 2 * n * sizeof(double),
-                           hipMemcpyDeviceToHost, stream);
-      if (e == hipSuccess) e = hipEventRecord(G.drain[t], stream);
+                           hipMemcpyDeviceToHost, copy);
+      if (e == hipSuccess) e = hipEventRecord(G.drain[t], copy);
       if (e != hipSuccess) {
         fail_all(PROP_EDEVICE, hipGetErrorString(e));
         return false;
@@ -531,6 +543,9 @@ static int srv_device_init(prop_server* s) {
       return fail(PROP_ENOMEM, "server state (%lld bytes) exceeds the budget", (long long)bytes);
   }
   HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
   HIP_TRY(hipMalloc((void**)&s->d_insts, kSrvMaxInstances * sizeof(SrvInst)));
   for (int i = 0; i < kStepRing; ++i) {
     HIP_TRY(hipMalloc((void**)&s->d_step[i], sizeof(SrvStep)));
@@ -808,6 +823,7 @@ void prop_srv_destroy(prop_server* s) {
   if (s->worker.joinable()) s->worker.join();
   if (!s->insts.empty()) hipSetDevice(s->insts[0]->h->device);
   if (s->stream) hipStreamSynchronize(s->stream);
+  if (s->copy) hipStreamSynchronize(s->copy);
   for (auto& up : s->insts) {
     Instance& I = *up;
     for (auto& G : I.groups) release_group(G);
@@ -820,6 +836,9 @@ void prop_srv_destroy(prop_server* s) {
     if (s->h_step[i]) hipHostFree(s->h_step[i]);
     if (s->step_ev[i]) hipEventDestroy(s->step_ev[i]);
   }
+  if (s->ev_in) hipEventDestroy(s->ev_in);
+  if (s->ev_out) hipEventDestroy(s->ev_out);
+  if (s->copy) hipStreamDestroy(s->copy);
   if (s->stream) hipStreamDestroy(s->stream);
   delete s;
 }
