@@ -201,6 +201,8 @@ def main():
     ap.add_argument("--serving-rate-below", type=float, default=400.0,
                     help="a second, shorter phase at a rate the server sustains (0: none)")
     ap.add_argument("--serving-seconds-below", type=float, default=20.0)
+    ap.add_argument("--serving-rounds-per-step", type=int, default=0,
+                    help="rounds the server queues between status reads (0: its default, 1)")
     ap.add_argument("--serving-marking", type=int, default=1, choices=[0, 1],
                     help="marked rounds per group of serving slots (results unchanged)")
     ap.add_argument("--serving-max-slots", type=int, default=256,
@@ -373,7 +375,8 @@ def main():
         serve = serving(args.serving_scale, args.serving_seconds, args.serving_rate,
                         int(args.serving_budget_gib * (1 << 30)), args.serving_max_pending,
                         args.serving_rate_below, args.serving_seconds_below,
-                        args.serving_max_slots, marking=bool(args.serving_marking))
+                        args.serving_max_slots, marking=bool(args.serving_marking),
+                        rounds_per_step=args.serving_rounds_per_step)
 
     # the CPU baseline leg: the oracle's synchronous rounds on config2 and,
     # as the paper's own comparison, its sequential Algorithm 1 on config1
@@ -777,7 +780,8 @@ def children_nodes(count: int, max_rounds: int):
 
 def serving(scale: float, seconds: float, rate: float, budget: int, max_pending: int,
             rate_below: float = 0.0, seconds_below: float = 0.0, max_slots: int = 256,
-            variants: int = 8, max_rounds: int = 50, verify: int = 1000, marking: bool = False):
+            variants: int = 8, max_rounds: int = 50, verify: int = 1000, marking: bool = False,
+            rounds_per_step: int = 0):
     """Open-loop serving: Poisson arrivals at `rate` per second for `seconds`,
     each request a bound vector (0-5% of all variables fixed to a feasible
     point's values) on one of 64 resident instances drawn uniformly.  A
@@ -812,7 +816,8 @@ def serving(scale: float, seconds: float, rate: float, budget: int, max_pending:
               for k, inst in enumerate(pool)]
     alone = [[probs[k].run(lb, ub, max_rounds) for lb, ub in bounds[k]]
              for k in range(len(pool))]
-    srv = binding.Server(budget, max_slots=max_slots, max_pending=max_pending, marking=marking)
+    srv = binding.Server(budget, max_slots=max_slots, max_pending=max_pending, marking=marking,
+                         rounds_per_step=rounds_per_step)
     for p in probs:
         srv.add_instance(p)
     # warm the server: one request per instance
@@ -920,6 +925,7 @@ def serving(scale: float, seconds: float, rate: float, budget: int, max_pending:
         "max_pending": max_pending,
         "max_slots": max_slots,
         "marking": marking,
+        "rounds_per_step": rounds_per_step or 1,
         "budget_bytes": budget,
         "verified_against": "the same request run alone (prop_run), bitwise, on a sample spread "
                             "over the run",

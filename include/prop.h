@@ -362,7 +362,7 @@ typedef struct prop_server prop_server; /* opaque */
 typedef struct {
   int64_t budget_bytes;    /* device bytes for slot groups and per-problem state, > 0 */
   int32_t max_slots;       /* slots per problem, a multiple of 8 (0: 256) */
-  int32_t rounds_per_step; /* rounds queued between status reads (0: 2) */
+  int32_t rounds_per_step; /* rounds queued between status reads (0: 1) */
   int32_t max_pending;     /* requests held (queued, running or unread) before
                               prop_srv_submit returns PROP_EBUSY (0: 1 << 20) */
   int32_t marking;         /* != 0: marked rounds per group of 8 slots, as by

@@ -519,7 +519,7 @@ int prop_srv_create(const prop_srv_config* cfg, prop_server** out) {
   if (!s) return fail(PROP_ENOMEM, "host allocation failed");
   s->cfg = *cfg;
   if (!s->cfg.max_slots) s->cfg.max_slots = 256;
-  if (!s->cfg.rounds_per_step) s->cfg.rounds_per_step = 2;
+  if (!s->cfg.rounds_per_step) s->cfg.rounds_per_step = 1;
   if (!s->cfg.max_pending) s->cfg.max_pending = 1 << 20;
   if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
   try {
