@@ -40,38 +40,49 @@ __device__ __forceinline__ uint32_t group_exact(const Batch& Bt, int g) {
 }
 
 // Packs nodes [k0, k0 + cnt) from node-major arrays (row q = node k0 + q).
+// One thread takes one variable of one group of 8 nodes and writes its
+// nodes' pairs of that variable's 128-byte line itself, so a full group
+// writes whole lines; reads stay coalesced (consecutive threads, consecutive
+// variables of one node row).
 __global__ __launch_bounds__(kBlock) void k_pack_batch(Problem P, Batch Bt,
                                                        const double* __restrict__ ulb,
                                                        const double* __restrict__ uub, int k0,
                                                        int cnt) {
-  const size_t total = (size_t)cnt * P.n;
+  const int g0 = k0 / kNodeGroup;
+  const int groups = (k0 + cnt - 1) / kNodeGroup - g0 + 1;
+  const size_t total = (size_t)groups * P.n;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    const int q = (int)(i / (size_t)P.n);
-    const int k = k0 + q;
-    const int v = (int)(i - (size_t)q * P.n);
-    double l = ulb[i], u = uub[i];
-    const bool bad = __builtin_isnan(l) || __builtin_isnan(u) || l == __builtin_inf() ||
-                     u == -__builtin_inf() ||
-                     (!is_inf(l) && __builtin_fabs(l) > PROP_HUGE) ||
-                     (!is_inf(u) && __builtin_fabs(u) > PROP_HUGE);
-    if (bad) __hip_atomic_store(&Bt.invalid[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int g = g0 + (int)(i / (size_t)P.n);
+    const int v = (int)(i - (size_t)(g - g0) * P.n);
+    const int kb = max(k0, g * kNodeGroup);
+    const int ke = min(k0 + cnt, (g + 1) * kNodeGroup);
     const int32_t j = P.perm[v];
     const bool is_int = P.vtype[j] != 0;
-    if (is_int) {
-      l = __builtin_ceil(l - P.eps_int);
-      u = __builtin_floor(u + P.eps_int);
+    double2* const la = Bt.gA[g] + (size_t)j * kNodeGroup;
+    double2* const lb2 = Bt.gB[g] + (size_t)j * kNodeGroup;
+    for (int k = kb; k < ke; ++k) {
+      const size_t src = (size_t)(k - k0) * P.n + v;
+      double l = ulb[src], u = uub[src];
+      const bool bad = __builtin_isnan(l) || __builtin_isnan(u) || l == __builtin_inf() ||
+                       u == -__builtin_inf() ||
+                       (!is_inf(l) && __builtin_fabs(l) > PROP_HUGE) ||
+                       (!is_inf(u) && __builtin_fabs(u) > PROP_HUGE);
+      if (bad) __hip_atomic_store(&Bt.invalid[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (is_int) {
+        l = __builtin_ceil(l - P.eps_int);
+        u = __builtin_floor(u + P.eps_int);
+      }
+      l = l + 0.0;
+      u = u + 0.0;
+      const double2 b = make_double2(l, u);
+      la[k % kNodeGroup] = b;
+      lb2[k % kNodeGroup] = b;
+      if (tiny_bound(l) || tiny_bound(u))
+        __hip_atomic_store(&Bt.tiny[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (domain_empty(is_int, l, u, P.feas_tol))
+        __hip_atomic_store(&Bt.infeasible[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    l = l + 0.0;
-    u = u + 0.0;
-    const size_t dst = (size_t)j * kNodeGroup + (k % kNodeGroup);
-    const double2 b = make_double2(l, u);
-    Bt.gA[k / kNodeGroup][dst] = b;
-    Bt.gB[k / kNodeGroup][dst] = b;
-    if (tiny_bound(l) || tiny_bound(u))
-      __hip_atomic_store(&Bt.tiny[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (domain_empty(is_int, l, u, P.feas_tol))
-      __hip_atomic_store(&Bt.infeasible[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -594,7 +605,8 @@ __global__ __launch_bounds__(kBlock) void k_srv_end(const SrvInst* __restrict__ 
 // ---------------------------------------------------------------------------
 hipError_t launch_pack_batch(const Problem& P, const Batch& Bt, const double* lb, const double* ub,
                              int k0, int cnt, hipStream_t s) {
-  hipLaunchKernelGGL(k_pack_batch, dim3(blocks_for((int64_t)cnt * P.n, kBlock, 16384)),
+  const int64_t groups = (k0 + cnt - 1) / kNodeGroup - k0 / kNodeGroup + 1;
+  hipLaunchKernelGGL(k_pack_batch, dim3(blocks_for(groups * P.n, kBlock, 16384)),
                      dim3(kBlock), 0, s, P, Bt, lb, ub, k0, cnt);
   return hipGetLastError();
 }
