@@ -195,7 +195,8 @@ int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rou
  * writes the finished nodes' rows of d_lb / d_ub, and packs the running
  * nodes into fewer groups; the rest of the rows are written at the end.  The first call with more nodes than any
  * earlier call allocates the batch workspace (32 * n * ceil(nodes / 8) * 8
- * bytes of bounds, plus per-node counters and lists and long-row partials),
+ * bytes of bounds, about n / 8 bytes of touch flags per group of 8 nodes,
+ * plus per-node counters and lists and long-row partials),
  * kept until prop_destroy; later calls allocate nothing.  An invalid bound
  * in any node returns PROP_EINVAL. */
 int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* d_ub,
@@ -216,7 +217,8 @@ int prop_run_batch(prop_problem* p, int32_t nodes, double* lb, double* ub, int32
  * forbid hipMalloc.  Same arguments, results and errors, but the batch
  * workspace lives in a fixed 64 MiB device array of the library instead of
  * memory the call allocates, and the call allocates nothing.  The
- * workspace takes 32 * n * 8 * ceil(nodes / 8) bytes of bound pairs, 80
+ * workspace takes 32 * n * 8 * ceil(nodes / 8) bytes of bound pairs plus
+ * n / 8 bytes of touch flags per group (rounded up to 256 bytes), 80
  * bytes per long-row segment and node, and 40 bytes per node, each region
  * rounded up to 256 bytes; a call that needs more than 64 MiB returns
  * PROP_EINVAL before touching the device.  Every group of 8 nodes runs
@@ -338,7 +340,8 @@ void prop_destroy(prop_problem* p);
  *
  * Admission by device-memory footprint: slots come in groups of 8, each
  * group holding 384 * n bytes (start-of-round and candidate bound pairs,
- * and the request's input/output staging); groups are allocated when a
+ * and the request's input/output staging) plus about n / 8 bytes of touch
+ * flags; groups are allocated when a
  * request finds no free slot and the budget has room, and idle groups are
  * released when another problem needs the room.  Each added problem also
  * holds 32 * max_slots bytes of per-slot state plus 64 * max_slots bytes

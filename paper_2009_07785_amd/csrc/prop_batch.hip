@@ -291,13 +291,17 @@ __device__ __forceinline__ void commit_part(const Problem& P, const Batch& Bt, i
   const uint32_t mask = group_mask(Bt, g);
   if (mask) {
     double2* A = Bt.gA[g];
-    const double2* B = Bt.gB[g];
+    double2* B = Bt.gB[g];
+    // a wave's 64 pairs are 8 variables x 8 nodes: one touch byte
+    uint8_t* const touch = touch_of(P, B, kNodeGroup);
     const size_t total = (size_t)P.n * kNodeGroup;
     const size_t stride = (size_t)nbx * blockDim.x;
     for (size_t e = (size_t)bx * blockDim.x + threadIdx.x; e < total; e += stride) {
       const uint32_t t = (uint32_t)(e % kNodeGroup);
       bool chg = false;
-      if ((mask >> t) & 1u) {
+      const bool hit = touch[e / kWave] != 0;
+      if (hit && (threadIdx.x & (kWave - 1)) == 0) touch[e / kWave] = 0;
+      if (hit && ((mask >> t) & 1u)) {
         const double2 a = A[e];
         const double2 b = B[e];
         if (a.x != b.x || a.y != b.y) {

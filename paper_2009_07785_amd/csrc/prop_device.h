@@ -221,6 +221,12 @@ __device__ __forceinline__ void atomic_min_f64(double* p, double v) {
   (void)__hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Touch bytes of the candidate block whose first pair is nxt (n x stride
+// pairs; prop_layout.h).
+__device__ __forceinline__ uint8_t* touch_of(const Problem& P, double2* nxt, uint32_t stride) {
+  return reinterpret_cast<uint8_t*>(nxt + (size_t)(P.n > 0 ? P.n : 1) * stride);
+}
+
 // Row-level quantities every entry of a row needs.
 struct RowState {
   double minfin, maxfin;
@@ -359,11 +365,14 @@ __device__ __forceinline__ bool entry_wanted(const RowState& R, double a, double
 // (l, u); the column word holds the variable in bits 0-30 and its
 // integrality in bit 31.
 // `nxt` points at this node's first pair; variable j's pair is nxt[j * stride].
-// With `striped`, variables below P.n_hot write to this block's stripe copy.
+// With `striped`, variables below P.n_hot write to this block's stripe copy
+// (the commit merges every hot variable each round); for any other
+// variable with a side that may count, the variable's touch byte is set
+// (`touch`: the block's, from touch_of).
 __device__ __forceinline__ void entry_candidates(const Problem& P, const RowState& R, double a,
                                                  double l, double u, int32_t cw,
                                                  double2* __restrict__ nxt, uint32_t stride,
-                                                 bool striped) {
+                                                 bool striped, uint8_t* __restrict__ touch) {
   bool dmin, dmax;
   entry_sides(R, a, l, u, cw, P.cont_rel_tol, dmin, dmax);
   if (!(dmin || dmax)) return;
@@ -372,6 +381,10 @@ __device__ __forceinline__ void entry_candidates(const Problem& P, const RowStat
   if (striped && var < P.n_hot) {
     nxt = P.stripes + (size_t)(blockIdx.x % kStripes) * P.n_hot;
     j = (size_t)var;
+  } else {
+    // set before the candidates are known: a byte set with nothing
+    // written only costs the commit a compare
+    touch[var >> 3] = 1;
   }
   const bool is_int = cw < 0;
   const double bmin = a > 0.0 ? l : u;
@@ -508,7 +521,8 @@ __device__ __forceinline__ void exact_chunk_row(const Problem& P, const ChunkDes
     if (a == 0.0) continue;
     const int32_t cw = P.cols[e];
     const double2 b = cur[(size_t)(cw & kColMask) * stride + t];
-    entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride, stride == 1);
+    entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride, stride == 1,
+                     touch_of(P, nxt, stride));
   }
 }
 
@@ -671,7 +685,8 @@ __device__ __forceinline__ void chunk_round(const Problem& P, const ChunkDesc cd
 #pragma unroll
         for (int k = 0; k < 4; ++k)
           if (k < cnt && av[k] != 0.0)
-            entry_candidates(P, R, av[k], bv[k].x, bv[k].y, cv[k], nxt + t, stride, stride == 1);
+            entry_candidates(P, R, av[k], bv[k].x, bv[k].y, cv[k], nxt + t, stride, stride == 1,
+                             touch_of(P, nxt, stride));
       }
     }
     // rows the fast sums cannot certify, one at a time with the whole wave
@@ -776,7 +791,7 @@ __device__ __forceinline__ void nz_piece_candidates(const Problem& P, const RowS
     if (a == 0.0) continue;
     const int32_t cw = P.cols[e];
     const double2 b = cur[cw & kColMask];
-    entry_candidates(P, R, a, b.x, b.y, cw, nxt, 1, true);
+    entry_candidates(P, R, a, b.x, b.y, cw, nxt, 1, true, touch_of(P, nxt, 1));
   }
 }
 
@@ -838,7 +853,7 @@ __device__ void nz_wave_exact(const Problem& P, const ChunkDesc cd, size_t base,
       if (a == 0.0) continue;
       const int32_t cw = P.cols[e];
       const double2 b = cur[cw & kColMask];
-      entry_candidates(P, R, a, b.x, b.y, cw, nxt, 1, true);
+      entry_candidates(P, R, a, b.x, b.y, cw, nxt, 1, true, touch_of(P, nxt, 1));
     }
   }
 }
@@ -1060,7 +1075,8 @@ __device__ __forceinline__ void exact_nodes_row(const Problem& P, const ChunkDes
       if (a == 0.0) continue;
       const int32_t cw = P.cols[idx];
       const double2 b = cur[(size_t)(cw & kColMask) * kNodeGroup + t];
-      entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, kNodeGroup, false);
+      entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, kNodeGroup, false,
+                       touch_of(P, nxt, kNodeGroup));
     }
   }
 }
@@ -1134,7 +1150,8 @@ __device__ __forceinline__ void chunk_round_nodes(const Problem& P, const ChunkD
 #pragma unroll
           for (int k = 0; k < 4; ++k)
             if (k < cnt && av[k] != 0.0)
-              entry_candidates(P, R, av[k], bv[k].x, bv[k].y, cv[k], nxt + t, kNodeGroup, false);
+              entry_candidates(P, R, av[k], bv[k].x, bv[k].y, cv[k], nxt + t, kNodeGroup, false,
+                               touch_of(P, nxt, kNodeGroup));
         }
       }
     }
@@ -1345,7 +1362,8 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
 #pragma unroll
       for (int w = 0; w < kSegBatch; ++w)
         if (av[w] != 0.0 && entry_wanted(R, av[w], bv[w].x, bv[w].y, cv[w], P.cont_rel_tol))
-          entry_candidates(P, R, av[w], bv[w].x, bv[w].y, cv[w], nxt + t, stride, stride == 1);
+          entry_candidates(P, R, av[w], bv[w].x, bv[w].y, cv[w], nxt + t, stride, stride == 1,
+                           touch_of(P, nxt, stride));
     }
     return;
   }
@@ -1355,7 +1373,8 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
     const int32_t cw = P.cols[sd.off + p];
     const double2 b = pair_of<kSrc>(cur, P.b32, cw, stride, t);
     if (entry_wanted(R, a, b.x, b.y, cw, P.cont_rel_tol))
-      entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride, stride == 1);
+      entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride, stride == 1,
+                     touch_of(P, nxt, stride));
   }
 }
 
@@ -1462,24 +1481,38 @@ __device__ __forceinline__ void commit_hot(const Problem& P, uint32_t tid, uint3
 }
 
 // Second part: variables [H, n), a wave taking kCommitUnroll consecutive
-// 64-variable words per step of a grid-stride loop, every pair of the step
-// loaded before any is compared.  In marked rounds the wave also stores
-// each word's changed flags as one word of the round's bitmap; the loop
-// keeps the lanes of a wave together for that.
+// 64-variable words per step of a grid-stride loop.  With kTouch, a word's
+// eight touch bytes (one 64-bit load) say whether any of its variables got
+// a candidate this round; only touched words load their pairs, all of the
+// step's before any is compared, and their touch bytes are cleared.
+// Without it (the persistent kernel, whose registers have no room for the
+// touch pointer) every word is compared and the bytes stay set, which
+// costs the next per-round commit one compare per word.  In marked rounds
+// the wave also stores each word's changed flags as one word of the
+// round's bitmap; the loop keeps the lanes of a wave together for that.
 constexpr int kCommitUnroll = 2;
 
+template <bool kTouch>
 __device__ __forceinline__ void commit_range(const Problem& P, uint32_t tid, uint32_t nthreads,
                                              uint32_t& changed, uint32_t& infeasible) {
   commit_hot(P, tid, nthreads, changed, infeasible);
   const uint32_t lane = tid & (kWave - 1);
   const uint32_t n = (uint32_t)P.n;
+  uint64_t* const touch =
+      kTouch ? reinterpret_cast<uint64_t*>(touch_of(P, P.bnd[1], 1)) : nullptr;
   const uint64_t step = (uint64_t)nthreads * kCommitUnroll;
   for (uint64_t v0 = hot_end(P) + (uint64_t)(tid - lane) * kCommitUnroll; v0 < n; v0 += step) {
+    bool hit[kCommitUnroll];
+#pragma unroll
+    for (int k = 0; k < kCommitUnroll; ++k) {
+      const uint64_t w0 = v0 + (uint64_t)k * kWave;
+      hit[k] = w0 < n && (!kTouch || touch[w0 / kWave] != 0);
+    }
     double2 a[kCommitUnroll], b[kCommitUnroll];
 #pragma unroll
     for (int k = 0; k < kCommitUnroll; ++k) {
       const uint64_t v = v0 + (uint64_t)k * kWave + lane;
-      if (v < n) {
+      if (hit[k] && v < n) {
         a[k] = P.bnd[0][v];
         b[k] = P.bnd[1][v];
       }
@@ -1489,7 +1522,10 @@ __device__ __forceinline__ void commit_range(const Problem& P, uint32_t tid, uin
       const uint64_t w0 = v0 + (uint64_t)k * kWave;
       const uint64_t v = w0 + lane;
       bool chg = false;
-      if (v < n) chg = commit_one(P, (uint32_t)v, a[k], b[k], changed, infeasible);
+      if (hit[k]) {
+        if (v < n) chg = commit_one(P, (uint32_t)v, a[k], b[k], changed, infeasible);
+        if (kTouch && lane == 0) touch[w0 / kWave] = 0;
+      }
       if (P.marking && w0 < n) {
         const uint64_t bits = __ballot(chg);
         if (lane == 0) P.chg_bits[w0 / kWave] = bits;

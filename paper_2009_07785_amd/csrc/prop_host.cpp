@@ -214,7 +214,10 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   if ((rc = dev_alloc(p, &d_part, h_segs.size()))) return rc;
   double2 *b0, *b1;
   if ((rc = dev_alloc(p, &b0, (size_t)n))) return rc;
-  if ((rc = dev_alloc(p, &b1, (size_t)n))) return rc;
+  // the candidate target is followed by its touch bytes, zero to start
+  const size_t b1_pairs = (size_t)(n > 0 ? n : 1);
+  if ((rc = dev_alloc(p, &b1, b1_pairs + touch_bytes(n) / sizeof(double2)))) return rc;
+  HIP_TRY(hipMemset(b1 + b1_pairs, 0, touch_bytes(n)));
   uint16_t* codes;
   if ((rc = dev_alloc(p, &codes, (size_t)(n > 0 ? n : 1)))) return rc;
   const int32_t n_hot = L.n_hot;
@@ -458,16 +461,18 @@ int ensure_batch(prop_problem* p, int32_t nodes) {
   int rc;
   double2 *A = nullptr, *B = nullptr;
   double2** tables = nullptr;
+  // group g's [n][8] block of B is followed by its touch bytes
+  const size_t per_group = (size_t)kNodeGroup * (size_t)(p->n > 0 ? p->n : 1);
+  const size_t per_group_b = per_group + touch_bytes(p->n) / sizeof(double2);
   if ((rc = alloc((void**)&A, pairs * sizeof(double2)))) return rc;
-  if ((rc = alloc((void**)&B, pairs * sizeof(double2)))) return rc;
+  if ((rc = alloc((void**)&B, (size_t)groups * per_group_b * sizeof(double2)))) return rc;
+  HIP_TRY(hipMemset(B, 0, (size_t)groups * per_group_b * sizeof(double2)));
   if ((rc = alloc((void**)&tables, 2 * (size_t)groups * sizeof(double2*)))) return rc;
   {
-    // group g's [n][8] block starts at g * n * 8 in the two pair arrays
     std::vector<double2*> h((size_t)2 * groups);
-    const size_t per_group = (size_t)kNodeGroup * (size_t)(p->n > 0 ? p->n : 1);
     for (int32_t g = 0; g < groups; ++g) {
       h[g] = A + g * per_group;
-      h[groups + g] = B + g * per_group;
+      h[groups + g] = B + g * per_group_b;
     }
     HIP_TRY(hipMemcpy(tables, h.data(), h.size() * sizeof(double2*), hipMemcpyHostToDevice));
     b.gA = tables;

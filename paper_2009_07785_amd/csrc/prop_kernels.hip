@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Problem P, int max_rounds
     }
     if (!grid_barrier(P, kActNone, r, max_rounds)) return;
     uint32_t changed = 0, infeasible = 0;
-    commit_range(P, tid, nthreads, changed, infeasible);
+    commit_range<false>(P, tid, nthreads, changed, infeasible);
     block_sum2(changed, infeasible);
     const uint64_t add = (uint64_t)changed | (infeasible ? kCommitInf : 0ull);
     if (!grid_barrier(P, kActEndRound, r, max_rounds, add)) return;
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_commit(Problem P) {
   const int r = round_of(P);
   const int max_rounds = C->max_rounds;
   uint32_t changed = 0, infeasible = 0;
-  commit_range(P, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, changed,
+  commit_range<true>(P, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, changed,
                infeasible);
   block_sum2(changed, infeasible);
   if (threadIdx.x == 0) {

@@ -58,6 +58,7 @@ struct Problem {
   int32_t pad_nz;
   const uint8_t* wave_flags; // nnz-split: [n_chunks][64] row starts per lane
   // state: bnd[0] = start-of-round bounds, bnd[1] = candidate target
+  // (followed by its touch bytes, see touch_bytes)
   double2* bnd[2];
   uint16_t* codes;          // [n] compact code of bnd[0] per variable (prop_device.h)
   // single-precision store (store32 != 0): every bound is kept on the grid
@@ -93,6 +94,20 @@ struct Problem {
 // every row instead.
 constexpr int kMarkPiece = 64;
 constexpr int kMarkAllDiv = 32;
+
+// Touch bytes.  Every block of candidate targets (a single run's bnd[1],
+// n pairs; a batch group's B, n x 8 pairs) is followed by touch_bytes(n)
+// bytes: byte i is set when a candidate was written for one of variables
+// 8i .. 8i + 7 (in any node of the block) in the current round, and the
+// commit reads only the pairs of touched variables and clears the bytes.
+// A byte set with nothing written costs a compare; every write sets its
+// byte before the commit runs, so none is missed.  A block holds
+// max(n, 1) x nodes pairs; the size keeps 64-variable words whole and
+// the next block 256-byte aligned.
+inline __host__ __device__ size_t touch_bytes(int32_t n) {
+  const size_t words = ((size_t)(n > 0 ? n : 1) + 63) / 64;
+  return (words * 8 + 255) / 256 * 256;
+}
 
 // Batch of branch-and-bound nodes sharing one problem.  Bounds of node
 // k = 8 g + t for variable j sit at A[(g * n + j) * 8 + t]: the 8 nodes of a

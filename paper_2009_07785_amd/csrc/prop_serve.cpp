@@ -91,7 +91,9 @@ struct Instance {
   int32_t hi_groups = 0;              // 1 + highest allocated group
 };
 
-int64_t group_bytes(int32_t n) { return (int64_t)kNodeGroup * 48 * (int64_t)(n > 0 ? n : 1); }
+int64_t group_bytes(int32_t n) {
+  return (int64_t)kNodeGroup * 48 * (int64_t)(n > 0 ? n : 1) + (int64_t)touch_bytes(n);
+}
 
 bool bound_ok(double l, double u) {
   const double huge = std::ldexp(1.0, 200);
@@ -203,7 +205,10 @@ int prop_server::alloc_group(Instance& I, int g) {
   SlotGroup& G = I.groups[g];
   const size_t pairs = (size_t)kNodeGroup * (size_t)(I.n > 0 ? I.n : 1);
   SRV_TRY(hipMalloc((void**)&G.A, pairs * sizeof(double2)));
-  SRV_TRY(hipMalloc((void**)&G.B, pairs * sizeof(double2)));
+  // B is followed by its touch bytes, zero to start (stream order puts the
+  // clear before any kernel that reads the group)
+  SRV_TRY(hipMalloc((void**)&G.B, pairs * sizeof(double2) + touch_bytes(I.n)));
+  SRV_TRY(hipMemsetAsync(G.B + pairs, 0, touch_bytes(I.n), stream));
   SRV_TRY(hipMalloc((void**)&G.d_io, 2 * pairs * sizeof(double)));
   SRV_TRY(hipHostMalloc((void**)&G.h_io, 2 * pairs * sizeof(double), hipHostMallocDefault));
   for (auto& e : G.drain) SRV_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));

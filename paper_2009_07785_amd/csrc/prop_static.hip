@@ -57,8 +57,8 @@ StaticLayout static_layout(int32_t n, int32_t n_segs, int32_t nodes) {
   size_t off = 0;
   L.pairs_a = off;
   off = align256(off + pair_bytes);
-  L.pairs_b = off;
-  off = align256(off + pair_bytes);
+  L.pairs_b = off;  // each group's block followed by its touch bytes
+  off = align256(off + pair_bytes + groups * touch_bytes(n));
   L.tables = off;
   off = align256(off + 2 * groups * sizeof(double2*));
   L.partials = off;
@@ -77,13 +77,16 @@ StaticLayout static_layout(int32_t n, int32_t n_segs, int32_t nodes) {
 // flags that the pack kernel only ever sets: invalid, infeasible, tiny.
 // The array keeps whatever the last call left, so they are cleared here
 // (a kernel, not a memset, so the clear also works inside captured work).
+// The touch bytes after each group's B block are left as they are: a stale
+// set byte only makes the first commit compare pairs that are equal.
 __global__ __launch_bounds__(kBlock) void k_static_setup(double2** tables, double2* A, double2* B,
                                                          int groups, size_t per_group,
-                                                         uint32_t* flags, int flag_words) {
+                                                         size_t per_group_b, uint32_t* flags,
+                                                         int flag_words) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < groups) {
     tables[i] = A + (size_t)i * per_group;
-    tables[groups + i] = B + (size_t)i * per_group;
+    tables[groups + i] = B + (size_t)i * per_group_b;
   }
   for (int q = i; q < flag_words; q += gridDim.x * blockDim.x) flags[q] = 0;
 }
@@ -150,7 +153,8 @@ extern "C" int prop_run_batch_device_static(prop_problem* p, int32_t nodes, doub
                                ? (3 * nodes + kBlock - 1) / kBlock
                                : (groups + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_static_setup, dim3(setup_blocks < 1024 ? setup_blocks : 1024), dim3(kBlock),
-                     0, s, tables, A, B, groups, per_group, n32, 3 * nodes);
+                     0, s, tables, A, B, groups, per_group,
+                     per_group + touch_bytes(p->n) / sizeof(double2), n32, 3 * nodes);
   HIP_TRY(hipGetLastError());
   HIP_TRY(launch_init(P, s));
   HIP_TRY(launch_pack_batch(P, bt, d_lb, d_ub, 0, nodes, s));
