@@ -366,9 +366,9 @@ __device__ __forceinline__ bool entry_wanted(const RowState& R, double a, double
 // integrality in bit 31.
 // `nxt` points at this node's first pair; variable j's pair is nxt[j * stride].
 // With `striped`, variables below P.n_hot write to this block's stripe copy
-// (the commit merges every hot variable each round); for any other
-// variable with a side that may count, the variable's touch byte is set
-// (`touch`: the block's, from touch_of).
+// (the commit merges them); for every variable with a side that may
+// count, the variable's touch byte is set (`touch`: the block's, from
+// touch_of).
 __device__ __forceinline__ void entry_candidates(const Problem& P, const RowState& R, double a,
                                                  double l, double u, int32_t cw,
                                                  double2* __restrict__ nxt, uint32_t stride,
@@ -381,11 +381,10 @@ __device__ __forceinline__ void entry_candidates(const Problem& P, const RowStat
   if (striped && var < P.n_hot) {
     nxt = P.stripes + (size_t)(blockIdx.x % kStripes) * P.n_hot;
     j = (size_t)var;
-  } else {
-    // set before the candidates are known: a byte set with nothing
-    // written only costs the commit a compare
-    touch[var >> 3] = 1;
   }
+  // set before the candidates are known: a byte set with nothing written
+  // only costs the commit a compare
+  touch[var >> 3] = 1;
   const bool is_int = cw < 0;
   const double bmin = a > 0.0 ? l : u;
   const double bmax = a > 0.0 ? u : l;
@@ -1419,22 +1418,35 @@ __device__ __forceinline__ bool commit_one(const Problem& P, uint32_t v, double2
 // the max / min over eight of a hot variable's stripe copies (and resets
 // them); lane 0 of the eight also takes the variable's pair in B.  Three
 // butterfly steps combine the eight lanes (max and min are exact, so the
-// grouping does not matter) and lane 0 commits.  In marked rounds a wave
-// covers eight variables and stores their changed flags as one byte of the
-// bitmap; the general part starts at H, so no bitmap word has two writers.
+// grouping does not matter) and lane 0 commits.  A wave covers eight
+// variables, one touch byte: with kTouch, a wave whose byte is clear skips
+// its variables (their stripes still hold the reset values and B equals
+// A) and a wave whose byte is set clears it.  In marked rounds the wave
+// stores the eight changed flags as one byte of the bitmap; the general
+// part starts at H, so no bitmap word has two writers.
 __device__ __forceinline__ uint32_t hot_end(const Problem& P) {
   if (P.n_hot <= 0) return 0;
   const uint32_t h = ((uint32_t)P.n_hot + kWave - 1) / kWave * kWave;
   return h < (uint32_t)P.n ? h : (uint32_t)P.n;
 }
 
+template <bool kTouch>
 __device__ __forceinline__ void commit_hot(const Problem& P, uint32_t tid, uint32_t nthreads,
                                            uint32_t& changed, uint32_t& infeasible) {
   const uint32_t H = hot_end(P);
   const uint32_t items = H * 8u;
   const uint32_t lane = tid & (kWave - 1);
+  uint8_t* const touch = kTouch ? touch_of(P, P.bnd[1], 1) : nullptr;
   for (uint32_t q0 = tid - lane; q0 < items; q0 += nthreads) {
     const uint32_t q = q0 + lane;
+    if (kTouch) {
+      // variables q0 / 8 .. q0 / 8 + 7: touch byte q0 / 64
+      if (touch[q0 / kWave] == 0) {
+        if (P.marking && lane == 0) reinterpret_cast<uint8_t*>(P.chg_bits)[q0 / kWave] = 0;
+        continue;
+      }
+      if (lane == 0) touch[q0 / kWave] = 0;
+    }
     const bool ok = q < items;
     const uint32_t v = ok ? q >> 3 : 0;
     const uint32_t g = q & 7;
@@ -1495,7 +1507,7 @@ constexpr int kCommitUnroll = 2;
 template <bool kTouch>
 __device__ __forceinline__ void commit_range(const Problem& P, uint32_t tid, uint32_t nthreads,
                                              uint32_t& changed, uint32_t& infeasible) {
-  commit_hot(P, tid, nthreads, changed, infeasible);
+  commit_hot<kTouch>(P, tid, nthreads, changed, infeasible);
   const uint32_t lane = tid & (kWave - 1);
   const uint32_t n = (uint32_t)P.n;
   uint64_t* const touch =
