@@ -258,16 +258,48 @@ __device__ __forceinline__ void round_unit(const Problem& P, const Batch& Bt, in
   }
 }
 
-// One wave: phase 2 of segment s for node k.
-template <bool kMarks>
+// One wave: phase 2 of segment s for node k.  With row states (kRowStates
+// and a buffer: the batch driver's), the state of the segment's row comes
+// from the row-state kernel; otherwise the wave combines the row's
+// partials itself (the serving engine, the allocation-free entry point).
+template <bool kMarks, bool kRowStates = false>
 __device__ __forceinline__ void long_unit(const Problem& P, const Batch& Bt, int s, int k) {
   if (s >= P.n_segs || !Bt.active[k]) return;
   const int g = k / kNodeGroup;
   int r = 0;
   const int32_t* marks = nullptr;
   const bool marked = kMarks && group_marked(P, Bt, g, r, marks);
+  if (kRowStates && Bt.row_state) {
+    const SegDesc sd = P.segs[s];
+    if (marked && marks[sd.row] != r) return;
+    const RowState R = Bt.row_state[(size_t)sd.first * Bt.nodes + k];
+    seg_revisit<true, kSrcPairs>(P, s, sd, R, Bt.gA[g], Bt.gB[g], kNodeGroup, k % kNodeGroup,
+                                 Bt.partials, Bt.nodes, k);
+    return;
+  }
   seg_phase2<true>(P, s, Bt.gA[g], Bt.gB[g], kNodeGroup, k % kNodeGroup, Bt.partials, Bt.nodes, k,
                    Bt.tiny[k] != 0, marked, r, marks);
+}
+
+// One wave: the state of long row i (first segment long_first[i]) for
+// node k, stored at that segment.  A long row of nseg segments has nseg
+// phase-2 waves per node; combining its partials once here instead of in
+// each of them reads nseg partials per node instead of nseg^2 (and sums an
+// uncertain row's exact sums once).  The grid has a wave per (long row,
+// node): one per (segment, node) would mostly exit at once, and for 256
+// nodes of the 1,000,000 x 500,000 instance (3,038 segments, 595 long
+// rows) its dispatch alone took 176 us a launch.
+__device__ __forceinline__ void row_state_unit(const Problem& P, const Batch& Bt, int i, int k) {
+  if (!Bt.active[k]) return;
+  const int s = Bt.long_first[i];
+  const SegDesc sd = P.segs[s];
+  const int g = k / kNodeGroup;
+  int r = 0;
+  const int32_t* marks = nullptr;
+  if (group_marked(P, Bt, g, r, marks) && marks[sd.row] != r) return;
+  const RowState R = seg_row_state(P, sd, Bt.gA[g], kNodeGroup, k % kNodeGroup, Bt.partials,
+                                   Bt.nodes, k, Bt.tiny[k] != 0);
+  if ((threadIdx.x & (kWave - 1)) == 0) Bt.row_state[(size_t)s * Bt.nodes + k] = R;
 }
 
 // The 8 variable bits of a wave's ballot over 8 variables x 8 nodes (lane
@@ -405,6 +437,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   round_unit<true>(P, Bt, (int)(wid - (int64_t)g * units), g);
 }
 
+// Row states: one wave per (long row, node).
+__global__ __launch_bounds__(kBlock) void k_row_state_batch(Problem P, Batch Bt) {
+  if (u32_load(&P.ctrl->done)) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  if (Bt.n_long == 0) return;
+  const int k = (int)(wid / Bt.n_long);
+  if (k >= Bt.nodes) return;
+  row_state_unit(P, Bt, (int)(wid - (int64_t)k * Bt.n_long), k);
+}
+
 __global__ __launch_bounds__(kBlock) void k_round_long_batch(Problem P, Batch Bt) {
   if (u32_load(&P.ctrl->done)) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -412,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_round_long_batch(Problem P, Batch Bt
   if (P.n_segs == 0) return;
   const int k = (int)(wid / P.n_segs);
   if (k >= Bt.nodes) return;
-  long_unit<true>(P, Bt, (int)(wid - (int64_t)k * P.n_segs), k);
+  long_unit<true, true>(P, Bt, (int)(wid - (int64_t)k * P.n_segs), k);
 }
 
 // Commit per (variable, node) of group blockIdx.y, with per-node counts.
@@ -633,6 +676,10 @@ hipError_t launch_round_batch(const Problem& P, const Batch& Bt, hipStream_t s) 
   const int64_t waves = (int64_t)(P.n_chunks + P.n_segs) * Bt.groups;
   hipLaunchKernelGGL(k_round_batch, dim3(blocks_for(waves, kWavesPerBlock, 1 << 30)),
                      dim3(kBlock), 0, s, P, Bt);
+  if (P.n_segs && Bt.row_state)
+    hipLaunchKernelGGL(k_row_state_batch,
+                       dim3(blocks_for((int64_t)Bt.n_long * Bt.nodes, kWavesPerBlock, 1 << 30)),
+                       dim3(kBlock), 0, s, P, Bt);
   if (P.n_segs)
     hipLaunchKernelGGL(k_round_long_batch,
                        dim3(blocks_for((int64_t)P.n_segs * Bt.nodes, kWavesPerBlock, 1 << 30)),

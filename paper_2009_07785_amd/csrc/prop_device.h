@@ -236,6 +236,7 @@ struct RowState {
   double smn;               // rhs - min activity
   double smx;               // lhs - max activity
 };
+static_assert(sizeof(RowState) == kRowStateBytes, "RowState size (batch row-state buffers)");
 
 // Row state from the reduced double-doubles; `force` sends the row to the
 // exact path whatever the certification says (a tiny bound is in play).
@@ -1309,16 +1310,16 @@ __device__ __forceinline__ void exact_long_row(const Problem& P, const SegDesc s
   exact_finish(X, lane == 0, mn, mx);
 }
 
-template <bool kBatchLoads = false, int kSrc = kSrcPairs>
-__device__ __forceinline__ void seg_phase2(const Problem& P, int s,
-                                           const double2* __restrict__ cur,
-                                           double2* __restrict__ nxt, uint32_t stride, uint32_t t,
-                                           const SegPartial* parts, uint32_t pstride,
-                                           uint32_t node, bool force_exact, bool marked = false,
-                                           int r_round = 0, const int32_t* marks = nullptr) {
+// Phase 2, first half: the state of the long row of segment descriptor sd
+// for node t from all of the row's segment partials, combined in segment
+// order (and the exact sums when the fast sums cannot certify it, or with
+// force_exact).  The same in every lane after the full-wave reduction.
+__device__ __forceinline__ RowState seg_row_state(const Problem& P, const SegDesc& sd,
+                                                  const double2* __restrict__ cur,
+                                                  uint32_t stride, uint32_t t,
+                                                  const SegPartial* parts, uint32_t pstride,
+                                                  uint32_t node, bool force_exact) {
   const int lane = threadIdx.x & (kWave - 1);
-  const SegDesc sd = P.segs[s];
-  if (marked && marks[sd.row] != r_round) return;
   DD smin = {0.0, 0.0}, smax = {0.0, 0.0};
   double emin = 0.0, emax = 0.0;
   int cmin = 0, cmax = 0;
@@ -1332,18 +1333,35 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
   group_reduce(smin, smax, emin, emax, cmin, cmax, 6);
   const double lhs = P.lhs[sd.row], rhs = P.rhs[sd.row];
   RowState R = make_row_state(smin, smax, emin, emax, cmin, cmax, lhs, rhs, force_exact);
-  if (R.uncertain) {  // the same in every lane after the full-wave reduction
-    // every segment of the row recomputes the exact sums: rare, and no wave
-    // waits on another
+  if (R.uncertain) {
     double mn, mx;
     exact_long_row(P, sd, cur, stride, t, mn, mx);
     set_exact(R, mn, mx, lhs, rhs);
   }
-  const SegPartial own = parts[(size_t)s * pstride + node];
+  return R;
+}
+
+// Whether a segment whose partial is `own` may hold a counting entry of
+// its row (state R): its largest skip thresholds do not rule one out, or
+// it owns a side's only infinite contribution.
+__device__ __forceinline__ bool seg_needs(const RowState& R, const SegPartial& own) {
   bool need = false;
   if (R.min_side) need |= (R.cmin == 0) ? !(R.smn > own.tmin) : (own.min_inf > 0);
   if (R.max_side) need |= (R.cmax == 0) ? !((-R.smx) > own.tmax) : (own.max_inf > 0);
-  if (!need) return;
+  return need;
+}
+
+// Phase 2, second half: the candidates of segment s (descriptor sd) for
+// node t given its row's state, when the segment's own largest skip
+// thresholds do not rule out a counting entry.
+template <bool kBatchLoads, int kSrc>
+__device__ __forceinline__ void seg_revisit(const Problem& P, int s, const SegDesc& sd,
+                                            const RowState& R, const double2* __restrict__ cur,
+                                            double2* __restrict__ nxt, uint32_t stride,
+                                            uint32_t t, const SegPartial* parts,
+                                            uint32_t pstride, uint32_t node) {
+  const int lane = threadIdx.x & (kWave - 1);
+  if (!seg_needs(R, parts[(size_t)s * pstride + node])) return;
   if (kBatchLoads) {
     for (int w0 = 0; w0 < kSegLen / kWave; w0 += kSegBatch) {
       if (w0 * kWave >= sd.len) break;
@@ -1373,8 +1391,24 @@ __device__ __forceinline__ void seg_phase2(const Problem& P, int s,
     const double2 b = pair_of<kSrc>(cur, P.b32, cw, stride, t);
     if (entry_wanted(R, a, b.x, b.y, cw, P.cont_rel_tol))
       entry_candidates(P, R, a, b.x, b.y, cw, nxt + t, stride, stride == 1,
-                     touch_of(P, nxt, stride));
+                       touch_of(P, nxt, stride));
   }
+}
+
+// Phase 2 of segment s for node t: its row's state, then its candidates.
+// Every segment of a row computes the row state itself (no wave waits on
+// another; an uncertain row's exact sums are then summed once per segment).
+template <bool kBatchLoads = false, int kSrc = kSrcPairs>
+__device__ __forceinline__ void seg_phase2(const Problem& P, int s,
+                                           const double2* __restrict__ cur,
+                                           double2* __restrict__ nxt, uint32_t stride, uint32_t t,
+                                           const SegPartial* parts, uint32_t pstride,
+                                           uint32_t node, bool force_exact, bool marked = false,
+                                           int r_round = 0, const int32_t* marks = nullptr) {
+  const SegDesc sd = P.segs[s];
+  if (marked && marks[sd.row] != r_round) return;
+  const RowState R = seg_row_state(P, sd, cur, stride, t, parts, pstride, node, force_exact);
+  seg_revisit<kBatchLoads, kSrc>(P, s, sd, R, cur, nxt, stride, t, parts, pstride, node);
 }
 
 // ---------------------------------------------------------------------------

@@ -63,6 +63,8 @@ struct prop_problem {
   int32_t* h_brounds = nullptr;
   int2* d_bret = nullptr;        // batch compaction: (slot, node) lists to unpack
   int2* d_bmove = nullptr;       // and (from slot, to slot) moves, batch capacity each
+  int32_t* d_long_first = nullptr;  // first segment of each long row (batch row states)
+  int32_t n_long = 0;
   // staging for prop_run_batch (host arrays), grown on demand
   double* d_bstage_lb = nullptr;
   double* d_bstage_ub = nullptr;

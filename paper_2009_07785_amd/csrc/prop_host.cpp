@@ -204,6 +204,13 @@ int build_layout(prop_problem* p, const prop_csr* A, const double* lhs, const do
   if ((rc = dev_upload(p, &d_cols, h_cols))) return rc;
   if ((rc = dev_upload(p, &d_chunks, h_chunks))) return rc;
   if ((rc = dev_upload(p, &d_segs, h_segs))) return rc;
+  {
+    std::vector<int32_t> firsts;
+    for (size_t q = 0; q < h_segs.size(); ++q)
+      if (h_segs[q].first == (int32_t)q) firsts.push_back((int32_t)q);
+    if (!firsts.empty() && (rc = dev_upload(p, &p->d_long_first, firsts))) return rc;
+    p->n_long = (int32_t)firsts.size();
+  }
   if ((rc = dev_upload(p, &d_lhs, h_lhs))) return rc;
   if ((rc = dev_upload(p, &d_rhs, h_rhs))) return rc;
   if ((rc = dev_upload(p, &d_vtype, vtype))) return rc;
@@ -481,6 +488,11 @@ int ensure_batch(prop_problem* p, int32_t nodes) {
   if ((rc = alloc((void**)&b.partials,
                   (size_t)(p->P.n_segs > 0 ? p->P.n_segs : 1) * nodes * sizeof(SegPartial))))
     return rc;
+  if (p->P.n_segs > 0 &&
+      (rc = alloc((void**)&b.row_state, (size_t)p->P.n_segs * nodes * kRowStateBytes)))
+    return rc;
+  b.long_first = p->d_long_first;
+  b.n_long = p->n_long;
   if ((rc = alloc((void**)&b.active, nodes * sizeof(uint32_t)))) return rc;
   if ((rc = alloc((void**)&b.status, nodes * sizeof(int32_t)))) return rc;
   if ((rc = alloc((void**)&b.rounds, nodes * sizeof(int32_t)))) return rc;

@@ -116,12 +116,23 @@ constexpr int kNodeGroup = 8;
 // a group with at most this many active nodes runs them one after another
 constexpr int kLoopNodes = 2;
 
+// State of a long row for one node after its segments' partials are
+// combined (prop_device.h); batches keep one per (first segment, node).
+struct RowState;
+constexpr int kRowStateBytes = 48;
+
 // Node slots in groups of kNodeGroup; each group's bound pairs live in their
 // own [n][8] block so that groups can be allocated and released one by one.
 struct Batch {
   double2* const* gA;      // [groups] -> start-of-round bounds of the group, [n][8]
   double2* const* gB;      // [groups] -> candidate targets, same layout
   SegPartial* partials;    // [segments][nodes]
+  // [segments][nodes] long-row states, filled at a row's first segment by
+  // a kernel of its own so that a row's partials are combined once per node
+  // (null: every segment combines them itself, as single runs do)
+  RowState* row_state;
+  const int32_t* long_first;  // [n_long] first segment of each long row (with row_state)
+  int32_t n_long;
   uint32_t* active;        // [nodes] still propagating
   int32_t* status;         // [nodes]
   int32_t* rounds;         // [nodes]
