@@ -196,7 +196,8 @@ int prop_run_device(prop_problem* p, double* d_lb, double* d_ub, int32_t max_rou
  * nodes into fewer groups; the rest of the rows are written at the end.  The first call with more nodes than any
  * earlier call allocates the batch workspace (32 * n * ceil(nodes / 8) * 8
  * bytes of bounds, about n / 8 bytes of touch flags per group of 8 nodes,
- * plus per-node counters and lists and long-row partials),
+ * plus per-node counters and lists, and 80 + 48 bytes of long-row partial
+ * and row state per long-row segment and node),
  * kept until prop_destroy; later calls allocate nothing.  An invalid bound
  * in any node returns PROP_EINVAL. */
 int prop_run_batch_device(prop_problem* p, int32_t nodes, double* d_lb, double* d_ub,
