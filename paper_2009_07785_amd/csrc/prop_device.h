@@ -84,6 +84,14 @@ __device__ __forceinline__ void group_reduce(DD& smin, DD& smax, double& emin, d
 
 __device__ __forceinline__ bool is_inf(double x) { return __builtin_isinf(x); }
 
+// Lane 0's value of x in every lane.
+__device__ __forceinline__ double lane0_f64(double x) {
+  const uint64_t v = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 0);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 0);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Contribution of one entry to both activities; mmin / mmax are the lane's
 // error bounds of the two sums (dd_add_prod).
 __device__ __forceinline__ void accumulate(double a, double l, double u, DD& smin, DD& smax,
@@ -1330,7 +1338,21 @@ __device__ __forceinline__ RowState seg_row_state(const Problem& P, const SegDes
     cmin += pp.min_inf;
     cmax += pp.max_inf;
   }
-  group_reduce(smin, smax, emin, emax, cmin, cmax, 6);
+  if (sd.nseg <= 8) {
+    // the partials sit in lanes 0-7 (zeros beyond): three levels, then
+    // lane 0's sums for the whole wave
+    group_reduce(smin, smax, emin, emax, cmin, cmax, 3);
+    smin.hi = lane0_f64(smin.hi);
+    smin.lo = lane0_f64(smin.lo);
+    smax.hi = lane0_f64(smax.hi);
+    smax.lo = lane0_f64(smax.lo);
+    emin = lane0_f64(emin);
+    emax = lane0_f64(emax);
+    cmin = __builtin_amdgcn_readlane(cmin, 0);
+    cmax = __builtin_amdgcn_readlane(cmax, 0);
+  } else {
+    group_reduce(smin, smax, emin, emax, cmin, cmax, 6);
+  }
   const double lhs = P.lhs[sd.row], rhs = P.rhs[sd.row];
   RowState R = make_row_state(smin, smax, emin, emax, cmin, cmax, lhs, rhs, force_exact);
   if (R.uncertain) {
